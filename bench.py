@@ -1,0 +1,234 @@
+#!/usr/bin/env python3
+"""Hartree solves/sec on one MI355X: the 360^3 diamond workload, FP32 fwd+bwd.
+
+One step (one "solve") is the whole hot path on one batch of synthetic input:
+  splat      rho = sum of 4096 Gaussians (Z = 4, sigma = 0.8 Bohr) - Q/Omega
+  solve      V = P rho, E_H                         (P1 .. P5 + E_H finalize)
+  backward   grad_rho = P (c dV + 1 * dV * rho)     (loss L = E_H + <c, V> dV)
+  adjoint    dL/dR for every atom
+All inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line.  Extra fields: the same step with an FP64 plan (the
+"plain FP64" comparison), per-kernel HIP-event timings over the timed region,
+the roofline of the dominant kernel, and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "Hartree solves/sec & HBM GB/s, 360^3 FP32 fwd+bwd vs FP64 plain"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-atoms", type=int, default=512, help="atoms in the CPU-oracle sample")
+    ap.add_argument("--out", default=None, help="also write the JSON line to this file")
+    return ap.parse_args()
+
+
+def source_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1209_4506_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+class Step:
+    """Preallocated buffers and the four C-ABI calls of one fwd+bwd solve."""
+
+    def __init__(self, prob, precision, torch, H, inputs):
+        self.torch = torch
+        dev = torch.device("cuda:0")
+        self.plan = H.Plan(prob.cell, prob.dims, precision=precision, device=dev, max_atoms=prob.natoms)
+        p = self.plan
+        self.pos = torch.tensor(prob.pos, device=dev)
+        self.Z = torch.tensor(prob.Z, device=dev)
+        self.sig = torch.tensor(prob.sigma, device=dev)
+        dv = p.dv()[0]
+        c = torch.tensor(inputs.random_grid(prob.dims, 1209), device=dev, dtype=torch.float64)
+        self.gv = (c * dv).to(p.dtype).contiguous()
+        self.ge = torch.ones(1, dtype=torch.float64, device=dev)
+        self.rho = p.empty_grid()
+        self.V = p.empty_grid()
+        self.E = torch.empty(1, dtype=torch.float64, device=dev)
+        self.grho = p.empty_grid()
+        self.gpos = torch.empty((prob.natoms, 3), dtype=torch.float64, device=dev)
+
+    def __call__(self):
+        p = self.plan
+        p.splat(self.pos, self.Z, self.sig, out=self.rho)
+        p.solve(self.rho, v=self.V, e_h=self.E)
+        p.backward(grad_v=self.gv, grad_e=self.ge, rho=self.rho, out=self.grho)
+        p.splat_adjoint(self.pos, self.Z, self.sig, self.grho, out=self.gpos)
+
+    def timed(self, steps, warmup, profile=False):
+        torch = self.torch
+        for _ in range(warmup):
+            self()
+        torch.cuda.synchronize()
+        if profile:
+            self.plan.profile_begin()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = self.plan.profile_end() if profile else None
+        return (t1 - t0), prof
+
+
+def kernel_bytes(name, prob, s):
+    """Algorithmic HBM bytes of one launch of a kernel group (s = bytes per real)."""
+    na, nb, nc = prob.dims
+    n = na * nb * nc
+    spec = na * nb * (nc // 2 + 1) * 2 * s  # half spectrum, complex
+    return {
+        "r2c": n * s + spec,
+        "r2c_bwd": 2 * n * s + spec,
+        "fft_b": 2 * spec,
+        "fft_b_inv": 2 * spec,
+        "fft_a": 2 * spec,
+        "fft_a_bwd": 2 * spec,
+        "c2r": spec + n * s,
+        "splat": n * s,
+        "adjoint": n * s,
+    }.get(name)
+
+
+def traffic_for(kernel, precision):
+    """Counter-measured HBM bytes per launch, if taken on the current sources."""
+    f = os.path.join(ROOT, "profiles", "traffic_diamond360.json")
+    if not os.path.exists(f):
+        return None
+    with open(f) as fh:
+        t = json.load(fh)
+    if t.get("source_hash") != source_hash():
+        return None
+    return t.get("kernels", {}).get(precision, {}).get(kernel)
+
+
+def cpu_baseline(prob, natoms_sample, inputs):
+    """The oracle on a bounded sample: the full-grid transforms of one step
+    (forward solve and backward) plus splat and adjoint for a subset of the
+    atoms, scaled to the whole atom count."""
+    import numpy as np
+
+    import oracle
+
+    cell9 = prob.cell.reshape(9)
+    k = min(natoms_sample, prob.natoms)
+    sel = np.arange(k)
+    t0 = time.perf_counter()
+    rho = oracle.splat(cell9, prob.dims, prob.pos[sel], prob.Z[sel], prob.sigma[sel])
+    t1 = time.perf_counter()
+    V, _, E, _ = oracle.poisson(cell9, rho)
+    dv = abs(np.linalg.det(prob.cell)) / prob.npoints
+    c = inputs.random_grid(prob.dims, 1209)
+    g = oracle.backward(cell9, rho, grad_v=c * dv, grad_e=1.0)
+    t2 = time.perf_counter()
+    oracle.splat_adjoint(cell9, prob.pos[sel], prob.Z[sel], prob.sigma[sel], g)
+    t3 = time.perf_counter()
+    scale = prob.natoms / k
+    t_step = (t2 - t1) + scale * ((t1 - t0) + (t3 - t2))
+    return {
+        "value": 1.0 / t_step,
+        "unit": "solves/s",
+        "cores": oracle.max_threads(),
+        "kind": "oracle",
+        "sample": "one step on the full %dx%dx%d grid (forward solve + backward transforms, %.1f s) with the "
+                  "splat and adjoint of %d of %d atoms (%.1f s) scaled x%.0f; measured %.1f s" % (
+                      *prob.dims, t2 - t1, k, prob.natoms, (t1 - t0) + (t3 - t2), scale, t3 - t0),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (the sharded "
+              "design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1209_4506_amd.hartree as H
+    from paper_1209_4506_amd import inputs
+
+    prob = inputs.diamond360()
+    step = Step(prob, "fp32", torch, H, inputs)
+    assert step.plan.device_status() == 0
+    dt, prof = step.timed(args.steps, args.warmup, profile=True)
+    assert step.plan.device_status() == 0, "device status bits set"
+    ms = 1000.0 * dt / args.steps
+    s = 4
+    n = prob.npoints
+    model_bytes = 23 * s * n
+    # dominant kernel group by time
+    groups = {k: v for k, v in prof.items()}
+    dom = max((k for k in groups if kernel_bytes(k, prob, s)), key=lambda k: groups[k][0])
+    dom_ms = groups[dom][0] / groups[dom][1]
+    dom_bytes = kernel_bytes(dom, prob, s)
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    per_kernel = {k: {"avg_us": round(1000.0 * v[0] / v[1], 2), "launches": v[1],
+                      "share": round(v[0] / sum(x[0] for x in groups.values()), 4)} for k, v in groups.items()}
+    out = {
+        "metric": METRIC,
+        "value": args.steps / dt,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "diamond360: 8x8x8 diamond supercell, a = 53.93 Bohr, 4096 Gaussian atoms "
+                               "(Z = 4, sigma = 0.8 Bohr, N(0, 0.05) displacements, seed 1211), 360^3 grid, "
+                               "FP32 transforms with FP64 E_H and force reductions, splat + solve + backward "
+                               "+ adjoint per step",
+                   "grid": list(prob.dims), "atoms": prob.natoms, "precision": "fp32"},
+        "hbm_gbs_model": model_bytes / (ms * 1e-3) / 1e9,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_for(dom, "fp32"),
+                     "bytes_per_launch": dom_bytes, "avg_launch_us": 1000.0 * dom_ms},
+        "kernels": per_kernel,
+        "source_hash": source_hash(),
+    }
+    if not args.no_fp64:
+        del step
+        torch.cuda.empty_cache()
+        step64 = Step(prob, "fp64", torch, H, inputs)
+        k64 = max(3, args.steps // 4)
+        dt64, prof64 = step64.timed(k64, 2, profile=True)
+        out["fp64_plain"] = {"value": k64 / dt64, "unit": "solves/s", "ms_per_step": 1000.0 * dt64 / k64,
+                             "steps": k64, "hbm_gbs_model": 23 * 8 * n / (dt64 / k64) / 1e9,
+                             "kernels": {k: round(1000.0 * v[0] / v[1], 2) for k, v in prof64.items()}}
+        out["speedup_vs_fp64_plain"] = out["value"] / out["fp64_plain"]["value"]
+        del step64
+        torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_atoms, inputs)
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "w") as fh:
+            fh.write(line + "\n")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+/*
+ * hartree.h -- C ABI of the MI355X periodic Hartree (FFT-Poisson) library.
+ *
+ * The library computes, on one GPU, the Hartree potential of a density given
+ * on a periodic real-space grid, its energy, the gradient of a loss through
+ * both, the Gaussian atomic density that feeds the solve, and that density's
+ * adjoint (Hartree forces on atoms).  Paper: Duy & Ozaki, "A three-dimensional
+ * domain decomposition method for large-scale DFT electronic structure
+ * calculations" (arXiv:1209.4506).
+ *
+ * Units are Hartree atomic units throughout: Bohr, Hartree, electron charge.
+ *
+ * Grid convention (Sec. 3.2.2, structure B in "abc" order): the cell rows are
+ * the axes a, b, c; the grid has Na x Nb x Nc points at
+ * r_ijk = (i/Na) a + (j/Nb) b + (k/Nc) c, stored row-major as
+ * [Na][Nb][Nc] with the c index fastest.  Every grid array passed to the
+ * library uses this layout.
+ *
+ * Precision: a plan is FP64 or FP32.  Every grid array passed to a plan holds
+ * elements of the plan's precision (double or float).  Energies, atom
+ * positions, charges, widths and gradients with respect to positions are
+ * always double.
+ *
+ * Memory ownership: the caller owns all device memory.  The plan owns only
+ * host metadata; its device workspace (twiddle tables, the half spectrum,
+ * reduction partials, atom bins) is a caller allocation of
+ * hartree_workspace_size() bytes handed over by hartree_bind_workspace().
+ * Unless stated otherwise, pointers below are DEVICE pointers, arrays are
+ * C-contiguous, and nothing is retained after a call returns.
+ *
+ * Execution: every compute call enqueues asynchronously on `stream` (a
+ * hipStream_t; NULL means the default stream), performs no allocation and no
+ * host synchronization, and returns once the work is enqueued.  A plan and its
+ * workspace serve one stream at a time: two calls on one plan that overlap in
+ * time race on the workspace.
+ *
+ * Errors: each call validates its arguments before enqueuing anything and
+ * returns a status code; hartree_last_error() then describes the problem
+ * (thread-local).  No C++ exception crosses this boundary.  A HIP launch
+ * failure returns HARTREE_ERR_HIP.  Conditions that only the device can see
+ * (a non-finite atom position, an atom wider than the plan's max_sigma, atom
+ * bins overflowing) set bits in a device status word read by
+ * hartree_device_status(); the affected outputs are then unspecified.
+ */
+#ifndef HARTREE_H
+#define HARTREE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hartree_plan_s *hartree_plan;
+
+typedef enum { HARTREE_FP64 = 0, HARTREE_FP32 = 1 } hartree_precision;
+
+typedef enum {
+    HARTREE_OK = 0,
+    HARTREE_ERR_ARG = 1,         /* null pointer, negative count, bad enum, ... */
+    HARTREE_ERR_DIMS = 2,        /* a grid dimension < 1, too large, or with a prime factor > 7 */
+    HARTREE_ERR_CELL = 3,        /* non-finite cell or |det| too small */
+    HARTREE_ERR_UNSUPPORTED = 4, /* valid input the library does not handle (e.g. a non-orthorhombic splat) */
+    HARTREE_ERR_WORKSPACE = 5,   /* no workspace bound, or the bound one is too small / misaligned */
+    HARTREE_ERR_HIP = 6          /* a HIP runtime call failed */
+} hartree_status;
+
+/* Device status bits (hartree_device_status). */
+#define HARTREE_DEV_BAD_ATOM 0x1u      /* non-finite position, sigma <= 0 or non-finite charge */
+#define HARTREE_DEV_SIGMA_RANGE 0x2u   /* an atom's sigma exceeds the plan's max_sigma */
+#define HARTREE_DEV_BIN_OVERFLOW 0x4u  /* atom bins exceeded their capacity */
+
+/* Optional plan settings; zero fields take the defaults in brackets. */
+typedef struct {
+    double cutoff_sigmas; /* Gaussian truncation radius in units of sigma [8 for FP64, 6 for FP32] */
+    double max_sigma;     /* largest sigma the splat workspace is sized for, Bohr [1.0] */
+    int32_t max_atoms;    /* largest atom count per splat call [65536] */
+    int32_t reserved[7];  /* must be zero */
+} hartree_plan_opts;
+
+/* Create a plan for one periodic cell.
+ *   cell  host, 9 doubles: the rows a, b, c (Bohr).  Any non-singular cell is
+ *         accepted by the solve; the splat calls need an orthorhombic (diagonal)
+ *         cell.
+ *   dims  host, 3 int32: Na, Nb, Nc, each >= 1, <= 4096 and 7-smooth.
+ *   precision  HARTREE_FP64 or HARTREE_FP32.
+ *   opts  host, nullable.
+ * On success *out receives the plan (host memory owned by the library until
+ * hartree_plan_destroy). */
+hartree_status hartree_plan_create(hartree_plan *out, const double cell[9], const int32_t dims[3],
+                                   int32_t precision, const hartree_plan_opts *opts);
+
+/* Create a plan for nprob independent cells solved together (the batched
+ * workload: many densities on uneven grids).  cells: host, nprob x 9 doubles;
+ * dims: host, nprob x 3 int32.  Grid arrays of a batched plan are the
+ * problems' grids concatenated in problem order (offsets from
+ * hartree_plan_grid_offset); energies are nprob doubles. */
+hartree_status hartree_plan_create_batched(hartree_plan *out, int32_t nprob, const double *cells,
+                                           const int32_t *dims, int32_t precision,
+                                           const hartree_plan_opts *opts);
+
+void hartree_plan_destroy(hartree_plan plan);
+
+/* Number of problems (1 for a single plan) and the element offset of problem
+ * p's grid in a concatenated grid array; offset(nprob) is the total. */
+hartree_status hartree_plan_nprob(hartree_plan plan, int32_t *nprob);
+hartree_status hartree_plan_grid_offset(hartree_plan plan, int32_t p, int64_t *offset);
+
+/* Workspace: bytes needed (host out), then bind a device allocation of at
+ * least that many bytes, 256-byte aligned.  Binding uploads the FP64-generated
+ * twiddle tables with a synchronous copy; it is the only call that
+ * synchronizes.  Rebinding replaces the previous workspace. */
+hartree_status hartree_workspace_size(hartree_plan plan, size_t *bytes);
+hartree_status hartree_bind_workspace(hartree_plan plan, void *workspace, size_t bytes);
+
+/* Hartree potential and energy, Eq. (6) and the E_Hartree term of Eq. (7)
+ * (Sec. 2.1), on the periodic grid with the G = 0 term dropped:
+ *   V = F^-1 [K F rho],  K(G) = 4 pi / |G|^2,  K(0) = 0,
+ *   E_H = 1/2 sum_r rho(r) V(r) dV,  dV = |det cell| / (Na Nb Nc).
+ * rho (in) and v (out) are grids of the plan's precision; v may not alias
+ * rho.  e_h (nullable) receives E_H as double (one per problem).  The
+ * transform runs along c, then b, then a and back, the layout order of
+ * Sec. 3.2.4.  On an even axis the Nyquist index is taken as the average of
+ * its two aliases (+N/2 and -N/2), which keeps the operator symmetric in any
+ * cell. */
+hartree_status hartree_solve(hartree_plan plan, const void *rho, void *v, double *e_h, void *stream);
+
+/* E_H only (the forward half of the transform; no potential written). */
+hartree_status hartree_energy(hartree_plan plan, const void *rho, double *e_h, void *stream);
+
+/* Gradient of a loss L(V, E_H) with respect to rho, given the upstream
+ * gradients grad_v = dL/dV (grid, nullable = zero) and grad_e = dL/dE_H
+ * (device doubles, one per problem, nullable = zero):
+ *   grad_rho = P (grad_v + grad_e * dV * rho),  P = F^-1 K F symmetric.
+ * rho may be NULL only when grad_e is NULL.  grad_rho may not alias the
+ * inputs.  Not in the paper: it follows from the symmetry of P. */
+hartree_status hartree_backward(hartree_plan plan, const void *grad_v, const double *grad_e, const void *rho,
+                                void *grad_rho, void *stream);
+
+/* Gaussian atomic density on the grid (stands in for the density of Eq. (9)):
+ *   rho(r) = sum_a Z_a (2 pi s_a^2)^(-3/2) sum_L exp(-|r - R_a - L|^2 / (2 s_a^2))  [- Q / Omega]
+ * over lattice vectors L, truncated per axis at cutoff_sigmas * s_a; Q = sum Z_a.
+ *   natoms  atom count (host int; for a batched plan the total over problems),
+ *   pos     natoms x 3 Cartesian positions (any, wrapped into the cell),
+ *   Z, sigma  natoms charges and widths (sigma > 0, <= max_sigma),
+ *   atom_offsets  batched plans only: host, nprob + 1 int32 prefix offsets of
+ *           each problem's atoms (NULL for single plans),
+ *   rho_out grid of the plan's precision (overwritten),
+ *   subtract_background  nonzero subtracts Q / Omega (a neutral cell).
+ * Needs an orthorhombic cell (HARTREE_ERR_UNSUPPORTED otherwise). */
+hartree_status hartree_splat(hartree_plan plan, int32_t natoms, const double *pos, const double *Z,
+                             const double *sigma, const int32_t *atom_offsets, void *rho_out,
+                             int32_t subtract_background, void *stream);
+
+/* Adjoint of the splat with respect to atom positions:
+ *   grad_pos[a] = sum_r grad_rho(r) d rho(r) / d R_a
+ *               = Z_a (2 pi s_a^2)^(-3/2) / s_a^2 sum_r grad_rho(r) sum_L g(d) d,
+ *   d = r - R_a - L,  g(d) = exp(-|d|^2 / (2 s_a^2)),
+ * with the splat's truncation.  With grad_rho = dV * V this is dE_H/dR_a, the
+ * negative Hartree force (the Hartree part of the forces of Sec. 5.2.5).
+ * grad_pos: natoms x 3 doubles (overwritten).  Summation order is fixed, so
+ * results are bitwise reproducible for a given plan. */
+hartree_status hartree_splat_adjoint(hartree_plan plan, int32_t natoms, const double *pos, const double *Z,
+                                     const double *sigma, const int32_t *atom_offsets, const void *grad_rho,
+                                     double *grad_pos, void *stream);
+
+/* Kernel groups timed by the profiling calls below. */
+typedef enum {
+    HARTREE_K_R2C = 0,        /* P1 forward: r2c along c */
+    HARTREE_K_R2C_BWD = 1,    /* P1 backward: forms grad_v + grad_e dV rho, r2c along c */
+    HARTREE_K_FFT_B = 2,      /* P2: FFT along b */
+    HARTREE_K_FFT_A = 3,      /* P3 with the E_H partials: FFT along a, x K/N, inverse along a */
+    HARTREE_K_FFT_A_BWD = 4,  /* P3 without the energy (backward, or no e_h requested) */
+    HARTREE_K_FFT_A_EONLY = 5,/* P3 of hartree_energy: FFT along a and the E_H partials */
+    HARTREE_K_FFT_B_INV = 6,  /* P4: inverse FFT along b */
+    HARTREE_K_C2R = 7,        /* P5: c2r along c */
+    HARTREE_K_FINALIZE = 8,   /* E_H fixed-order reduction */
+    HARTREE_K_BIN = 9,        /* atom binning (prep, count, scan, fill, sort) */
+    HARTREE_K_SPLAT = 10,     /* splat gather */
+    HARTREE_K_ADJOINT = 11,   /* splat adjoint per-brick partials */
+    HARTREE_K_ADJOINT_FINAL = 12, /* per-atom fixed-order reduction */
+    HARTREE_K_COUNT = 13
+} hartree_kernel_id;
+
+/* Profiling: between begin and end every kernel group enqueued by this plan is
+ * bracketed by HIP events on its stream.  end waits for the last event and
+ * writes, per hartree_kernel_id, the summed duration in milliseconds and the
+ * number of launches (host arrays of HARTREE_K_COUNT entries). */
+hartree_status hartree_profile_begin(hartree_plan plan);
+hartree_status hartree_profile_end(hartree_plan plan, double *total_ms, int64_t *launches);
+
+/* Read (synchronously) and clear the device status word (HARTREE_DEV_* bits). */
+hartree_status hartree_device_status(hartree_plan plan, uint32_t *bits, void *stream);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char *hartree_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HARTREE_H */

@@ -1,0 +1,732 @@
+// C ABI of the Hartree library: plan creation and validation, workspace
+// layout, twiddle generation, and the enqueue of every pass.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/hartree.h"
+#include "fft_core.hpp"
+#include "kernels.hpp"
+
+using namespace hartree;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+hartree_status fail(hartree_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+hartree_status fail(hartree_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+hartree_status ok()
+{
+    g_last_error.clear();
+    return HARTREE_OK;
+}
+
+hartree_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(HARTREE_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Stage radices for a length: 8s first (a 2-power remainder of 2 becomes a
+// 4, of 1 becomes 4 x 4 in place of one 8 when possible), then 5, 3 and 7.
+bool factorize(int n, std::vector<int> &r)
+{
+    r.clear();
+    int m = n, e2 = 0;
+    while (m % 2 == 0) {
+        m /= 2;
+        ++e2;
+    }
+    int n8 = e2 / 3, rem = e2 % 3;
+    if (rem == 1 && n8 >= 1) {
+        --n8;
+        for (int i = 0; i < n8; ++i) r.push_back(8);
+        r.push_back(4);
+        r.push_back(4);
+    } else {
+        for (int i = 0; i < n8; ++i) r.push_back(8);
+        if (rem == 1) r.push_back(2);
+        if (rem == 2) r.push_back(4);
+    }
+    for (int p : {5, 3, 7}) {
+        while (m % p == 0) {
+            m /= p;
+            r.push_back(p);
+        }
+    }
+    return m == 1 && int(r.size()) <= kMaxStages;
+}
+
+// cos and sin of 2 pi t / n with the angle reduced exactly to the first
+// octant in integer arithmetic before calling std::cos / std::sin.
+void unit_root(long t, long n, double &c, double &s)
+{
+    t %= n;
+    if (t < 0) t += n;
+    const long u = 4 * t;
+    const long q = u / n;      // quadrant
+    long r = u - q * n;        // angle within the quadrant: (pi/2) r / n
+    bool swap = false;
+    if (2 * r > n) {           // use the complement for the upper half of the quadrant
+        r = n - r;
+        swap = true;
+    }
+    const double th = 1.5707963267948966192313216916397514 * double(r) / double(n);
+    double cc = std::cos(th), ss = std::sin(th);
+    if (swap) std::swap(cc, ss);
+    switch (q) {
+    case 0: c = cc; s = ss; break;
+    case 1: c = -ss; s = cc; break;
+    case 2: c = -cc; s = -ss; break;
+    default: c = ss; s = -cc; break;
+    }
+}
+
+struct Launch {
+    int nmax;
+    int maxn;
+    TileList tl;
+};
+
+}  // namespace
+
+struct hartree_plan_s {
+    int fp64 = 0;
+    int nprob = 0;
+    bool splat_ok = false;
+    double cutoff = 0.0;
+    double max_sigma = 0.0;
+    int max_atoms = 0;
+    std::vector<ProbDesc> desc;
+    std::vector<double> twiddles;  // interleaved (re, im), FP64
+    int64_t spec_count = 0;        // complex elements
+    int64_t grid_total = 0;        // real elements
+    std::vector<int64_t> grid_offsets;
+    int nparts = 0;
+    int64_t nbricks = 0;
+    int64_t capacity = 0;
+    std::vector<Launch> lr2c, lb, la;  // P1/P5 (axis c), P2/P4 (axis b), P3 (axis a)
+    // workspace layout
+    size_t o_status = 0, o_desc = 0, o_tw = 0, o_spec = 0, o_parts = 0, o_qsum = 0, o_info = 0, o_counts = 0,
+           o_offsets = 0, o_cursor = 0, o_list = 0, o_lists = 0, o_bpart = 0, ws_size = 0;
+    unsigned char *ws = nullptr;
+    // profiling: events bracketing each kernel group
+    struct ProfRec {
+        int id;
+        hipEvent_t a, b;
+    };
+    bool prof = false;
+    std::vector<hipEvent_t> pool;
+    size_t pool_used = 0;
+    std::vector<ProfRec> recs;
+    ~hartree_plan_s()
+    {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+bool is_smooth(int n)
+{
+    if (n < 1 || n > kMaxN) return false;
+    for (int p : {2, 3, 5, 7})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+void add_launch(std::vector<Launch> &v, int nmax, int n, int prob, int tiles)
+{
+    for (auto &l : v) {
+        if (l.nmax == nmax && l.tl.count < kMaxProb) {
+            l.tl.prob[l.tl.count] = prob;
+            l.tl.start[l.tl.count + 1] = l.tl.start[l.tl.count] + tiles;
+            l.tl.count++;
+            l.tl.total += tiles;
+            if (n > l.maxn) l.maxn = n;
+            return;
+        }
+    }
+    Launch l;
+    std::memset(&l, 0, sizeof(l));
+    l.nmax = nmax;
+    l.maxn = n;
+    l.tl.count = 1;
+    l.tl.prob[0] = prob;
+    l.tl.start[0] = 0;
+    l.tl.start[1] = tiles;
+    l.tl.total = tiles;
+    v.push_back(l);
+}
+
+hartree_status create(hartree_plan *out, int nprob, const double *cells, const int32_t *dims, int32_t precision,
+                      const hartree_plan_opts *opts)
+{
+    if (!out) return fail(HARTREE_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!cells || !dims) return fail(HARTREE_ERR_ARG, "cell or dims is NULL");
+    if (nprob < 1 || nprob > kMaxProb) return fail(HARTREE_ERR_ARG, "nprob must be in [1, %d]", kMaxProb);
+    if (precision != HARTREE_FP64 && precision != HARTREE_FP32)
+        return fail(HARTREE_ERR_ARG, "precision must be HARTREE_FP64 or HARTREE_FP32");
+    hartree_plan_opts opt;
+    std::memset(&opt, 0, sizeof(opt));
+    if (opts) {
+        opt = *opts;
+        for (int i = 0; i < 7; ++i)
+            if (opt.reserved[i] != 0) return fail(HARTREE_ERR_ARG, "opts.reserved must be zero");
+        if (!(opt.cutoff_sigmas >= 0.0) || !(opt.max_sigma >= 0.0) || opt.max_atoms < 0)
+            return fail(HARTREE_ERR_ARG, "negative or NaN option");
+    }
+    auto p = new hartree_plan_s();
+    p->fp64 = precision == HARTREE_FP64;
+    p->nprob = nprob;
+    p->cutoff = opt.cutoff_sigmas > 0.0 ? opt.cutoff_sigmas : (p->fp64 ? 8.0 : 6.0);
+    p->max_sigma = opt.max_sigma > 0.0 ? opt.max_sigma : 1.0;
+    p->max_atoms = opt.max_atoms > 0 ? opt.max_atoms : 65536;
+    p->desc.resize(nprob);
+    std::map<int, int> tw_off;
+    p->splat_ok = true;
+    int64_t grid = 0, spec = 0, bricks = 0;
+    int64_t cap_per_atom = 0;
+    for (int q = 0; q < nprob; ++q) {
+        const double *A = cells + 9 * q;
+        const int32_t *N = dims + 3 * q;
+        for (int x = 0; x < 3; ++x) {
+            if (!is_smooth(N[x])) {
+                delete p;
+                return fail(HARTREE_ERR_DIMS, "problem %d: dimension %d is %d; need 1..%d with prime factors 2, 3, 5, 7",
+                            q, x, N[x], kMaxN);
+            }
+        }
+        for (int i = 0; i < 9; ++i) {
+            if (!std::isfinite(A[i])) {
+                delete p;
+                return fail(HARTREE_ERR_CELL, "problem %d: non-finite cell entry", q);
+            }
+        }
+        const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                           A[2] * (A[3] * A[7] - A[4] * A[6]);
+        const double n0 = std::sqrt(A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
+        const double n1 = std::sqrt(A[3] * A[3] + A[4] * A[4] + A[5] * A[5]);
+        const double n2 = std::sqrt(A[6] * A[6] + A[7] * A[7] + A[8] * A[8]);
+        if (!(std::fabs(det) > 1e-10 * n0 * n1 * n2) || !(std::fabs(det) > 0.0)) {
+            delete p;
+            return fail(HARTREE_ERR_CELL, "problem %d: singular or degenerate cell (det %g)", q, det);
+        }
+        ProbDesc &d = p->desc[q];
+        std::memset(&d, 0, sizeof(d));
+        for (int x = 0; x < 3; ++x) {
+            const int n = N[x];
+            AxisPlan &ap = d.ax[x];
+            std::vector<int> rad;
+            if (!factorize(n, rad)) {
+                delete p;
+                return fail(HARTREE_ERR_DIMS, "problem %d: cannot factor %d", q, n);
+            }
+            ap.n = n;
+            ap.nstages = int(rad.size());
+            int ns = 1;
+            for (size_t s = 0; s < rad.size(); ++s) {
+                ap.radix[s] = rad[s];
+                ap.ns[s] = make_fastdiv(uint32_t(ns));
+                ap.twstride[s] = n / (ns * rad[s]);
+                ns *= rad[s];
+            }
+            auto it = tw_off.find(n);
+            if (it == tw_off.end()) {
+                const int off = int(p->twiddles.size() / 2);
+                tw_off[n] = off;
+                for (int t = 0; t < n; ++t) {
+                    double c, s;
+                    unit_root(t, n, c, s);
+                    p->twiddles.push_back(c);
+                    p->twiddles.push_back(-s);  // W_n^t = exp(-2 pi i t / n)
+                }
+                ap.tw_off = off;
+            } else {
+                ap.tw_off = it->second;
+            }
+        }
+        d.dims[0] = N[0];
+        d.dims[1] = N[1];
+        d.dims[2] = N[2];
+        d.dims[3] = N[2] / 2 + 1;
+        d.div_nh = make_fastdiv(uint32_t(d.dims[3]));
+        d.div_nc = make_fastdiv(uint32_t(N[2]));
+        d.npts = int64_t(N[0]) * N[1] * N[2];
+        d.grid_off = grid;
+        d.spec_off = spec;
+        p->grid_offsets.push_back(grid);
+        grid += d.npts;
+        spec += int64_t(N[0]) * N[1] * d.dims[3];
+        // B = 2 pi inv(A)^T: row i = 2 pi (a_j x a_k) / det
+        const double *a0 = A, *a1 = A + 3, *a2 = A + 6;
+        const double c12[3] = {a1[1] * a2[2] - a1[2] * a2[1], a1[2] * a2[0] - a1[0] * a2[2],
+                               a1[0] * a2[1] - a1[1] * a2[0]};
+        const double c20[3] = {a2[1] * a0[2] - a2[2] * a0[1], a2[2] * a0[0] - a2[0] * a0[2],
+                               a2[0] * a0[1] - a2[1] * a0[0]};
+        const double c01[3] = {a0[1] * a1[2] - a0[2] * a1[1], a0[2] * a1[0] - a0[0] * a1[2],
+                               a0[0] * a1[1] - a0[1] * a1[0]};
+        const double tp = 6.283185307179586476925286766559;
+        for (int k = 0; k < 3; ++k) {
+            d.B[k] = tp * c12[k] / det;
+            d.B[3 + k] = tp * c20[k] / det;
+            d.B[6 + k] = tp * c01[k] / det;
+        }
+        for (int k = 0; k < 9; ++k) d.Bf[k] = float(d.B[k]);
+        const bool ortho = A[1] == 0.0 && A[2] == 0.0 && A[3] == 0.0 && A[5] == 0.0 && A[6] == 0.0 && A[7] == 0.0;
+        d.ortho = ortho ? 1 : 0;
+        const double omega = std::fabs(det);
+        d.inv_n = 1.0 / double(d.npts);
+        d.dv = omega / double(d.npts);
+        d.eh_scale = omega / (2.0 * double(d.npts) * double(d.npts));
+        d.L[0] = A[0];
+        d.L[1] = A[4];
+        d.L[2] = A[8];
+        if (!ortho || A[0] <= 0.0 || A[4] <= 0.0 || A[8] <= 0.0) p->splat_ok = false;
+        // pass tiles
+        const int cc = length_class(N[2]), cb = length_class(N[1]), ca = length_class(N[0]);
+        const int pc = pass_pencils(p->fp64, cc), pb = pass_pencils(p->fp64, cb), pa = pass_pencils(p->fp64, ca);
+        const int64_t rows = int64_t(N[0]) * N[1];
+        const int64_t t1 = (rows + 2 * pc - 1) / (2 * pc);
+        const int64_t t2 = int64_t(N[0]) * ((d.dims[3] + pb - 1) / pb);
+        const int64_t t3 = (int64_t(N[1]) * d.dims[3] + pa - 1) / pa;
+        if (t1 > (1 << 30) || t2 > (1 << 30) || t3 > (1 << 30)) {
+            delete p;
+            return fail(HARTREE_ERR_DIMS, "problem %d: grid too large", q);
+        }
+        add_launch(p->lr2c, cc, N[2], q, int(t1));
+        add_launch(p->lb, cb, N[1], q, int(t2));
+        add_launch(p->la, ca, N[0], q, int(t3));
+        d.part_off = p->nparts;
+        d.nparts = int(t3);
+        p->nparts += int(t3);
+        // splat bricks
+        const int bsz[3] = {kBI, kBJ, kBK};
+        int64_t per_atom = 1;
+        for (int x = 0; x < 3; ++x) {
+            d.nbricks[x] = (N[x] + bsz[x] - 1) / bsz[x];
+            const double h = std::fabs(A[4 * x]) / N[x];
+            const double w = std::floor(2.0 * p->cutoff * p->max_sigma / (h > 0 ? h : 1.0)) + 1.0;
+            int64_t nbx = d.nbricks[x];
+            if (w < N[x]) {
+                const int64_t bnd = int64_t(std::ceil((w - 1.0) / bsz[x])) + 2;
+                if (bnd < nbx) nbx = bnd;
+            }
+            per_atom *= nbx;
+        }
+        d.brick_off = bricks;
+        bricks += int64_t(d.nbricks[0]) * d.nbricks[1] * d.nbricks[2];
+        if (per_atom > cap_per_atom) cap_per_atom = per_atom;
+    }
+    p->grid_offsets.push_back(grid);
+    p->grid_total = grid;
+    p->spec_count = spec;
+    p->nbricks = p->splat_ok ? bricks : 0;
+    p->capacity = p->splat_ok ? int64_t(p->max_atoms) * cap_per_atom : 0;
+    if (p->capacity > int64_t(INT32_MAX)) {
+        const int64_t cap = p->capacity;
+        delete p;
+        return fail(HARTREE_ERR_ARG, "splat bins (%lld entries) exceed 2^31; lower max_atoms or max_sigma",
+                    (long long)cap);
+    }
+    // workspace layout
+    const size_t cx = p->fp64 ? 16 : 8;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    p->o_status = take(sizeof(DeviceStatus));
+    p->o_desc = take(sizeof(ProbDesc) * nprob);
+    p->o_tw = take(cx * (p->twiddles.size() / 2));
+    p->o_spec = take(cx * size_t(p->spec_count));
+    p->o_parts = take(8 * size_t(p->nparts + 1));
+    p->o_qsum = take(8 * size_t(nprob));
+    if (p->splat_ok) {
+        p->o_info = take(sizeof(AtomInfo) * size_t(p->max_atoms));
+        p->o_counts = take(4 * size_t(p->nbricks + 1));
+        p->o_offsets = take(4 * size_t(p->nbricks + 1));
+        p->o_cursor = take(4 * size_t(p->nbricks + 1));
+        p->o_list = take(4 * size_t(p->capacity));
+        p->o_lists = take(4 * size_t(p->capacity));
+        p->o_bpart = take(24 * size_t(p->capacity));
+    }
+    p->ws_size = o;
+    *out = p;
+    return ok();
+}
+
+hartree_status check_ws(hartree_plan p)
+{
+    if (!p) return fail(HARTREE_ERR_ARG, "plan is NULL");
+    if (!p->ws) return fail(HARTREE_ERR_WORKSPACE, "no workspace bound (hartree_bind_workspace)");
+    return HARTREE_OK;
+}
+
+constexpr size_t kMaxProfRecs = 1 << 16;
+
+hipEvent_t next_event(hartree_plan p)
+{
+    if (p->pool_used == p->pool.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        p->pool.push_back(e);
+    }
+    return p->pool[p->pool_used++];
+}
+
+// run f(); while profiling, bracket it with events on stream s
+template <typename F>
+hipError_t timed(hartree_plan p, int id, hipStream_t s, F f)
+{
+    if (!p->prof || p->recs.size() >= kMaxProfRecs) return f();
+    hipEvent_t a = next_event(p), b = next_event(p);
+    if (!a || !b) return f();
+    hipError_t e = hipEventRecord(a, s);
+    if (e != hipSuccess) return e;
+    e = f();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, s);
+    if (e != hipSuccess) return e;
+    p->recs.push_back({id, a, b});
+    return hipSuccess;
+}
+
+PassArgs base_args(hartree_plan p)
+{
+    PassArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.desc = reinterpret_cast<const ProbDesc *>(p->ws + p->o_desc);
+    a.tw = p->ws + p->o_tw;
+    a.spec = p->ws + p->o_spec;
+    a.partials = reinterpret_cast<double *>(p->ws + p->o_parts);
+    return a;
+}
+
+int kernel_id(PassKind kind)
+{
+    switch (kind) {
+    case PASS_R2C_FWD: return HARTREE_K_R2C;
+    case PASS_R2C_BWD: return HARTREE_K_R2C_BWD;
+    case PASS_C2R: return HARTREE_K_C2R;
+    case PASS_B_FWD: return HARTREE_K_FFT_B;
+    case PASS_B_INV: return HARTREE_K_FFT_B_INV;
+    case PASS_A_FULL: return HARTREE_K_FFT_A;
+    case PASS_A_NOENERGY: return HARTREE_K_FFT_A_BWD;
+    default: return HARTREE_K_FFT_A_EONLY;
+    }
+}
+
+hipError_t run_group(hartree_plan p, const std::vector<Launch> &groups, PassKind kind, PassArgs a, hipStream_t s)
+{
+    return timed(p, kernel_id(kind), s, [&]() {
+        for (const Launch &l : groups) {
+            a.tl = l.tl;
+            hipError_t e = run_pass(p->fp64, kind, l.nmax, l.maxn, l.tl.total, s, a);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    });
+}
+
+SplatArgs splat_args(hartree_plan p, int32_t natoms, const double *pos, const double *Z, const double *sigma,
+                     const int32_t *atom_offsets)
+{
+    SplatArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.desc = reinterpret_cast<const ProbDesc *>(p->ws + p->o_desc);
+    a.nprob = p->nprob;
+    a.natoms = natoms;
+    if (p->nprob == 1) {
+        a.atom_off[0] = 0;
+        a.atom_off[1] = natoms;
+    } else {
+        for (int i = 0; i <= p->nprob; ++i) a.atom_off[i] = atom_offsets[i];
+    }
+    a.pos = pos;
+    a.Z = Z;
+    a.sigma = sigma;
+    a.cutoff = p->cutoff;
+    a.max_sigma = p->max_sigma;
+    a.info = reinterpret_cast<AtomInfo *>(p->ws + p->o_info);
+    a.counts = reinterpret_cast<int32_t *>(p->ws + p->o_counts);
+    a.offsets = reinterpret_cast<int32_t *>(p->ws + p->o_offsets);
+    a.cursor = reinterpret_cast<int32_t *>(p->ws + p->o_cursor);
+    a.list = reinterpret_cast<int32_t *>(p->ws + p->o_list);
+    a.list_sorted = reinterpret_cast<int32_t *>(p->ws + p->o_lists);
+    a.bpart = reinterpret_cast<double *>(p->ws + p->o_bpart);
+    a.capacity = p->capacity;
+    a.nbricks_total = p->nbricks;
+    a.status = reinterpret_cast<DeviceStatus *>(p->ws + p->o_status);
+    a.fp64 = p->fp64;
+    a.qsum = reinterpret_cast<double *>(p->ws + p->o_qsum);
+    return a;
+}
+
+hartree_status check_atoms(hartree_plan p, int32_t natoms, const double *pos, const double *Z, const double *sigma,
+                           const int32_t *atom_offsets)
+{
+    if (!p->splat_ok)
+        return fail(HARTREE_ERR_UNSUPPORTED, "the splat needs orthorhombic (diagonal, positive) cells");
+    if (natoms < 0) return fail(HARTREE_ERR_ARG, "natoms < 0");
+    if (natoms > p->max_atoms)
+        return fail(HARTREE_ERR_ARG, "natoms %d exceeds the plan's max_atoms %d", natoms, p->max_atoms);
+    if (natoms > 0 && (!pos || !Z || !sigma)) return fail(HARTREE_ERR_ARG, "pos, Z or sigma is NULL");
+    if (p->nprob > 1) {
+        if (!atom_offsets) return fail(HARTREE_ERR_ARG, "batched plans need atom_offsets");
+        if (atom_offsets[0] != 0 || atom_offsets[p->nprob] != natoms)
+            return fail(HARTREE_ERR_ARG, "atom_offsets must start at 0 and end at natoms");
+        for (int i = 0; i < p->nprob; ++i)
+            if (atom_offsets[i + 1] < atom_offsets[i]) return fail(HARTREE_ERR_ARG, "atom_offsets must not decrease");
+    } else if (atom_offsets) {
+        if (atom_offsets[0] != 0 || atom_offsets[1] != natoms)
+            return fail(HARTREE_ERR_ARG, "atom_offsets must be {0, natoms}");
+    }
+    return HARTREE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hartree_status hartree_plan_create(hartree_plan *out, const double cell[9], const int32_t dims[3], int32_t precision,
+                                   const hartree_plan_opts *opts)
+{
+    return create(out, 1, cell, dims, precision, opts);
+}
+
+hartree_status hartree_plan_create_batched(hartree_plan *out, int32_t nprob, const double *cells, const int32_t *dims,
+                                           int32_t precision, const hartree_plan_opts *opts)
+{
+    return create(out, nprob, cells, dims, precision, opts);
+}
+
+void hartree_plan_destroy(hartree_plan plan) { delete plan; }
+
+hartree_status hartree_plan_nprob(hartree_plan plan, int32_t *nprob)
+{
+    if (!plan || !nprob) return fail(HARTREE_ERR_ARG, "NULL argument");
+    *nprob = plan->nprob;
+    return ok();
+}
+
+hartree_status hartree_plan_grid_offset(hartree_plan plan, int32_t p, int64_t *offset)
+{
+    if (!plan || !offset) return fail(HARTREE_ERR_ARG, "NULL argument");
+    if (p < 0 || p > plan->nprob) return fail(HARTREE_ERR_ARG, "problem index %d out of range", p);
+    *offset = plan->grid_offsets[p];
+    return ok();
+}
+
+hartree_status hartree_workspace_size(hartree_plan plan, size_t *bytes)
+{
+    if (!plan || !bytes) return fail(HARTREE_ERR_ARG, "NULL argument");
+    *bytes = plan->ws_size;
+    return ok();
+}
+
+hartree_status hartree_bind_workspace(hartree_plan plan, void *workspace, size_t bytes)
+{
+    if (!plan || !workspace) return fail(HARTREE_ERR_ARG, "NULL argument");
+    if (bytes < plan->ws_size)
+        return fail(HARTREE_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu needed", bytes,
+                    plan->ws_size);
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return fail(HARTREE_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    unsigned char *ws = static_cast<unsigned char *>(workspace);
+    hipError_t e = hipMemcpy(ws + plan->o_desc, plan->desc.data(), sizeof(ProbDesc) * plan->nprob,
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "uploading plan descriptors");
+    const size_t ntw = plan->twiddles.size() / 2;
+    if (plan->fp64) {
+        e = hipMemcpy(ws + plan->o_tw, plan->twiddles.data(), 16 * ntw, hipMemcpyHostToDevice);
+    } else {
+        std::vector<float> f(plan->twiddles.size());
+        for (size_t i = 0; i < f.size(); ++i) f[i] = float(plan->twiddles[i]);
+        e = hipMemcpy(ws + plan->o_tw, f.data(), 8 * ntw, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) return hip_fail(e, "uploading twiddles");
+    DeviceStatus st;
+    std::memset(&st, 0, sizeof(st));
+    e = hipMemcpy(ws + plan->o_status, &st, sizeof(st), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "clearing the status word");
+    plan->ws = ws;
+    return ok();
+}
+
+hartree_status hartree_solve(hartree_plan plan, const void *rho, void *v, double *e_h, void *stream)
+{
+    hartree_status st = check_ws(plan);
+    if (st != HARTREE_OK) return st;
+    if (!rho || !v) return fail(HARTREE_ERR_ARG, "rho or v is NULL");
+    if (rho == v) return fail(HARTREE_ERR_ARG, "v may not alias rho");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    PassArgs a = base_args(plan);
+    a.in = rho;
+    a.out = v;
+    hipError_t e;
+    if ((e = run_group(plan, plan->lr2c, PASS_R2C_FWD, a, s)) != hipSuccess) return hip_fail(e, "P1");
+    if ((e = run_group(plan, plan->lb, PASS_B_FWD, a, s)) != hipSuccess) return hip_fail(e, "P2");
+    if ((e = run_group(plan, plan->la, e_h ? PASS_A_FULL : PASS_A_NOENERGY, a, s)) != hipSuccess)
+        return hip_fail(e, "P3");
+    if ((e = run_group(plan, plan->lb, PASS_B_INV, a, s)) != hipSuccess) return hip_fail(e, "P4");
+    if ((e = run_group(plan, plan->lr2c, PASS_C2R, a, s)) != hipSuccess) return hip_fail(e, "P5");
+    if (e_h && (e = timed(plan, HARTREE_K_FINALIZE, s, [&]() {
+                    return run_finalize(a.desc, a.partials, e_h, plan->nprob, s);
+                })) != hipSuccess)
+        return hip_fail(e, "E_H finalize");
+    return ok();
+}
+
+hartree_status hartree_energy(hartree_plan plan, const void *rho, double *e_h, void *stream)
+{
+    hartree_status st = check_ws(plan);
+    if (st != HARTREE_OK) return st;
+    if (!rho || !e_h) return fail(HARTREE_ERR_ARG, "rho or e_h is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    PassArgs a = base_args(plan);
+    a.in = rho;
+    hipError_t e;
+    if ((e = run_group(plan, plan->lr2c, PASS_R2C_FWD, a, s)) != hipSuccess) return hip_fail(e, "P1");
+    if ((e = run_group(plan, plan->lb, PASS_B_FWD, a, s)) != hipSuccess) return hip_fail(e, "P2");
+    if ((e = run_group(plan, plan->la, PASS_A_ENERGY, a, s)) != hipSuccess) return hip_fail(e, "P3");
+    if ((e = timed(plan, HARTREE_K_FINALIZE, s, [&]() { return run_finalize(a.desc, a.partials, e_h, plan->nprob, s); })) !=
+        hipSuccess)
+        return hip_fail(e, "E_H finalize");
+    return ok();
+}
+
+hartree_status hartree_backward(hartree_plan plan, const void *grad_v, const double *grad_e, const void *rho,
+                                void *grad_rho, void *stream)
+{
+    hartree_status st = check_ws(plan);
+    if (st != HARTREE_OK) return st;
+    if (!grad_rho) return fail(HARTREE_ERR_ARG, "grad_rho is NULL");
+    if (grad_e && !rho) return fail(HARTREE_ERR_ARG, "rho is needed when grad_e is given");
+    if (grad_rho == grad_v || grad_rho == rho) return fail(HARTREE_ERR_ARG, "grad_rho may not alias an input");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    PassArgs a = base_args(plan);
+    a.in = grad_v;
+    a.in2 = rho;
+    a.grad_e = grad_e;
+    a.out = grad_rho;
+    hipError_t e;
+    if ((e = run_group(plan, plan->lr2c, PASS_R2C_BWD, a, s)) != hipSuccess) return hip_fail(e, "P1");
+    if ((e = run_group(plan, plan->lb, PASS_B_FWD, a, s)) != hipSuccess) return hip_fail(e, "P2");
+    if ((e = run_group(plan, plan->la, PASS_A_NOENERGY, a, s)) != hipSuccess) return hip_fail(e, "P3");
+    if ((e = run_group(plan, plan->lb, PASS_B_INV, a, s)) != hipSuccess) return hip_fail(e, "P4");
+    if ((e = run_group(plan, plan->lr2c, PASS_C2R, a, s)) != hipSuccess) return hip_fail(e, "P5");
+    return ok();
+}
+
+hartree_status hartree_splat(hartree_plan plan, int32_t natoms, const double *pos, const double *Z,
+                             const double *sigma, const int32_t *atom_offsets, void *rho_out,
+                             int32_t subtract_background, void *stream)
+{
+    hartree_status st = check_ws(plan);
+    if (st != HARTREE_OK) return st;
+    if ((st = check_atoms(plan, natoms, pos, Z, sigma, atom_offsets)) != HARTREE_OK) return st;
+    if (!rho_out) return fail(HARTREE_ERR_ARG, "rho_out is NULL");
+    SplatArgs a = splat_args(plan, natoms, pos, Z, sigma, atom_offsets);
+    a.rho = rho_out;
+    a.subtract_background = subtract_background ? 1 : 0;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = timed(plan, HARTREE_K_BIN, s, [&]() { return run_bin(a, s); });
+    if (e != hipSuccess) return hip_fail(e, "atom binning");
+    e = timed(plan, HARTREE_K_SPLAT, s, [&]() { return run_gather(a, s); });
+    if (e != hipSuccess) return hip_fail(e, "splat");
+    return ok();
+}
+
+hartree_status hartree_splat_adjoint(hartree_plan plan, int32_t natoms, const double *pos, const double *Z,
+                                     const double *sigma, const int32_t *atom_offsets, const void *grad_rho,
+                                     double *grad_pos, void *stream)
+{
+    hartree_status st = check_ws(plan);
+    if (st != HARTREE_OK) return st;
+    if ((st = check_atoms(plan, natoms, pos, Z, sigma, atom_offsets)) != HARTREE_OK) return st;
+    if (!grad_rho || (natoms > 0 && !grad_pos)) return fail(HARTREE_ERR_ARG, "grad_rho or grad_pos is NULL");
+    SplatArgs a = splat_args(plan, natoms, pos, Z, sigma, atom_offsets);
+    a.grad_rho = grad_rho;
+    a.grad_pos = grad_pos;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = timed(plan, HARTREE_K_BIN, s, [&]() { return run_bin(a, s); });
+    if (e != hipSuccess) return hip_fail(e, "atom binning");
+    e = timed(plan, HARTREE_K_ADJOINT, s, [&]() { return run_adjoint(a, s); });
+    if (e != hipSuccess) return hip_fail(e, "splat adjoint");
+    e = timed(plan, HARTREE_K_ADJOINT_FINAL, s, [&]() { return run_adjoint_final(a, s); });
+    if (e != hipSuccess) return hip_fail(e, "splat adjoint reduction");
+    return ok();
+}
+
+hartree_status hartree_device_status(hartree_plan plan, uint32_t *bits, void *stream)
+{
+    hartree_status st = check_ws(plan);
+    if (st != HARTREE_OK) return st;
+    if (!bits) return fail(HARTREE_ERR_ARG, "bits is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint32_t v = 0;
+    hipError_t e = hipMemcpyAsync(&v, plan->ws + plan->o_status, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "reading the status word");
+    const uint32_t zero = 0;
+    e = hipMemcpy(plan->ws + plan->o_status, &zero, 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "clearing the status word");
+    *bits = v;
+    return ok();
+}
+
+hartree_status hartree_profile_begin(hartree_plan plan)
+{
+    if (!plan) return fail(HARTREE_ERR_ARG, "plan is NULL");
+    plan->recs.clear();
+    plan->pool_used = 0;
+    plan->prof = true;
+    return ok();
+}
+
+hartree_status hartree_profile_end(hartree_plan plan, double *total_ms, int64_t *launches)
+{
+    if (!plan || !total_ms || !launches) return fail(HARTREE_ERR_ARG, "NULL argument");
+    plan->prof = false;
+    for (int i = 0; i < HARTREE_K_COUNT; ++i) {
+        total_ms[i] = 0.0;
+        launches[i] = 0;
+    }
+    if (!plan->recs.empty()) {
+        hipError_t e = hipEventSynchronize(plan->recs.back().b);
+        if (e != hipSuccess) return hip_fail(e, "waiting for the profiling events");
+    }
+    for (const auto &r : plan->recs) {
+        float ms = 0.0f;
+        hipError_t e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) return hip_fail(e, "reading a profiling event");
+        total_ms[r.id] += ms;
+        launches[r.id] += 1;
+    }
+    plan->recs.clear();
+    plan->pool_used = 0;
+    return ok();
+}
+
+const char *hartree_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

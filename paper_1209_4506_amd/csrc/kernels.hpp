@@ -1,0 +1,79 @@
+// Launch interface between the host library and the kernels.
+#pragma once
+
+#include "common.hpp"
+
+namespace hartree {
+
+// Work items of one launch: tiles of several problems, concatenated.
+struct TileList {
+    int32_t count;                 // problems in this launch
+    int32_t total;                 // total tiles
+    int32_t prob[kMaxProb];
+    int32_t start[kMaxProb + 1];   // prefix tile counts
+};
+
+enum PassKind {
+    PASS_R2C_FWD,
+    PASS_R2C_BWD,
+    PASS_C2R,
+    PASS_B_FWD,
+    PASS_B_INV,
+    PASS_A_FULL,
+    PASS_A_NOENERGY,
+    PASS_A_ENERGY
+};
+
+struct PassArgs {
+    const ProbDesc *desc;
+    const void *tw;        // twiddle tables (complex, plan precision)
+    void *spec;            // half spectrum (workspace)
+    const void *in;        // real-grid input of P1 (rho, or grad_v in the backward; nullable there)
+    const void *in2;       // rho for the backward P1
+    void *out;             // real-grid output of P5
+    double *partials;      // E_H partial slots
+    const double *grad_e;  // backward: dL/dE_H per problem (nullable)
+    TileList tl;
+};
+
+int length_class(int n);
+int pass_pencils(int fp64, int nmax);
+hipError_t run_pass(int fp64, PassKind kind, int nmax, int maxn, int grid, hipStream_t s, const PassArgs &a);
+hipError_t run_finalize(const ProbDesc *desc, const double *partials, double *e_h, int nprob, hipStream_t s);
+
+// ---------------------------------------------------------------- splat
+
+struct SplatArgs {
+    const ProbDesc *desc;
+    int32_t nprob;
+    int32_t natoms;
+    int32_t atom_off[kMaxProb + 1];  // prefix atom counts per problem
+    const double *pos;
+    const double *Z;
+    const double *sigma;
+    double cutoff;          // truncation radius in sigmas
+    double max_sigma;
+    AtomInfo *info;         // natoms
+    int32_t *counts;        // nbricks_total + 1
+    int32_t *offsets;       // nbricks_total + 1
+    int32_t *cursor;        // nbricks_total
+    int32_t *list;          // capacity
+    int32_t *list_sorted;   // capacity
+    double *bpart;          // capacity x 3 (adjoint partials)
+    int64_t capacity;
+    int64_t nbricks_total;
+    DeviceStatus *status;
+    int32_t subtract_background;
+    int32_t fp64;
+    void *rho;              // splat output grid
+    const void *grad_rho;   // adjoint input grid
+    double *grad_pos;       // adjoint output
+    double *qsum;           // nprob: total charge per problem
+};
+
+hipError_t run_bin(const SplatArgs &a, hipStream_t s);
+hipError_t run_gather(const SplatArgs &a, hipStream_t s);
+hipError_t run_adjoint(const SplatArgs &a, hipStream_t s);
+hipError_t run_adjoint_final(const SplatArgs &a, hipStream_t s);
+
+}  // namespace hartree

@@ -1,0 +1,473 @@
+// Gaussian atomic density on the grid (splat) and its adjoint (forces).
+//
+// The density of each atom is a product of three 1-D periodic Gaussians in
+// an orthorhombic cell, so every contribution factorizes into per-axis
+// tables.  The grid is cut into bricks of 8 x 8 x 32 points (the analogue of
+// the paper's structure A / structure C idea, Sec. 3.2.2: the points touched
+// by one atom's sphere, and a box around a group of atoms); each brick is one
+// workgroup that gathers the atoms whose truncation window overlaps it.
+//
+// Binning is deterministic: every atom adds itself to the bricks its window
+// touches (integer atomics), the per-brick lists are then sorted by atom
+// index, and every sum below runs in a fixed order, so results do not depend
+// on scheduling.
+//
+//   prep    per atom: wrapped position, weight, window [lo, hi] per axis
+//   charge  per problem: Q = sum Z (fixed order), for the background Q / Omega
+//   count   per atom: +1 on each touched brick
+//   scan    exclusive prefix sum of the brick counts
+//   fill    per atom: write its index into each touched brick's list
+//   sort    per brick: order the list by atom index
+//   gather  per brick: rho = sum over its atoms of w gx(i) gy(j) gz(k) [- Q/Omega]
+//   adjoint per brick: partial sum_r grad_rho(r) g(r) d(r) for each of its atoms
+//   final   per atom: fixed-order sum of its partials over the touched bricks
+#include "fft_core.hpp"
+#include "kernels.hpp"
+
+namespace hartree {
+
+constexpr int kChunk = 32;  // atoms staged in LDS at a time
+
+__device__ __forceinline__ int find_prob_atom(const SplatArgs &a, int atom)
+{
+    int p = 0;
+    while (p + 1 < a.nprob && atom >= a.atom_off[p + 1]) ++p;
+    return p;
+}
+
+__device__ __forceinline__ int wrapi(int i, int n)
+{
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+// bricks touched along one axis: circular range [start, start + count) mod nb
+__device__ __forceinline__ void axis_bricks(int lo, int hi, int n, int bsz, int nb, int &start, int &count)
+{
+    if (hi < lo) {  // invalid atom: touches nothing
+        start = 0;
+        count = 0;
+        return;
+    }
+    if (hi - lo + 1 >= n) {
+        start = 0;
+        count = nb;
+        return;
+    }
+    const int s = wrapi(lo, n), e = wrapi(hi, n);
+    const int bs = s / bsz, be = e / bsz;
+    start = bs;
+    if (s <= e)
+        count = be - bs + 1;
+    else
+        count = (be >= bs) ? nb : (nb - bs) + be + 1;
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
+{
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_atom_prep(SplatArgs a)
+{
+    const int atom = blockIdx.x * blockDim.x + threadIdx.x;
+    if (atom >= a.natoms) return;
+    const int prob = find_prob_atom(a, atom);
+    const ProbDesc &d = a.desc[prob];
+    AtomInfo in;
+    in.prob = prob;
+    in.pad = 0;
+    const double s = a.sigma[atom], z = a.Z[atom];
+    bool ok = isfinite(s) && s > 0.0 && isfinite(z);
+    for (int x = 0; x < 3; ++x) ok = ok && isfinite(a.pos[3 * atom + x]);
+    if (ok && s > a.max_sigma) {
+        atomicOr(&a.status->bits, 0x2u);
+        ok = false;
+    } else if (!ok) {
+        atomicOr(&a.status->bits, 0x1u);
+    }
+    if (!ok) {
+        for (int x = 0; x < 3; ++x) {
+            in.X[x] = 0.0;
+            in.lo[x] = 1;
+            in.hi[x] = 0;
+        }
+        in.w = 0.0;
+        in.inv2s2 = 0.0;
+        a.info[atom] = in;
+        return;
+    }
+    const double rc = a.cutoff * s;
+    for (int x = 0; x < 3; ++x) {
+        const double L = d.L[x];
+        double X = a.pos[3 * atom + x];
+        X -= floor(X / L) * L;
+        if (X >= L) X -= L;
+        if (X < 0.0) X = 0.0;
+        const double h = L / d.dims[x];
+        in.X[x] = X;
+        in.lo[x] = int(ceil((X - rc) / h));
+        in.hi[x] = int(floor((X + rc) / h));
+    }
+    in.w = z * pow(6.283185307179586476925286766559 * s * s, -1.5);
+    in.inv2s2 = 1.0 / (2.0 * s * s);
+    a.info[atom] = in;
+}
+
+__global__ __launch_bounds__(256) void k_charge(SplatArgs a, double *qsum)
+{
+    __shared__ double red[256];
+    const int p = blockIdx.x;
+    double s = 0.0;
+    for (int i = a.atom_off[p] + threadIdx.x; i < a.atom_off[p + 1]; i += 256) s += a.Z[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) qsum[p] = red[0];
+}
+
+template <int MODE>  // 0: count, 1: fill
+__global__ void k_brick_visit(SplatArgs a)
+{
+    const int atom = blockIdx.x * blockDim.x + threadIdx.x;
+    if (atom >= a.natoms) return;
+    const AtomInfo in = a.info[atom];
+    const ProbDesc &d = a.desc[in.prob];
+    const int bsz[3] = {kBI, kBJ, kBK};
+    int st[3], ct[3];
+    for (int x = 0; x < 3; ++x) axis_bricks(in.lo[x], in.hi[x], d.dims[x], bsz[x], d.nbricks[x], st[x], ct[x]);
+    for (int u = 0; u < ct[0]; ++u) {
+        const int bi = (st[0] + u) % d.nbricks[0];
+        for (int v = 0; v < ct[1]; ++v) {
+            const int bj = (st[1] + v) % d.nbricks[1];
+            for (int w = 0; w < ct[2]; ++w) {
+                const int bk = (st[2] + w) % d.nbricks[2];
+                const int64_t b = d.brick_off + (int64_t(bi) * d.nbricks[1] + bj) * d.nbricks[2] + bk;
+                if (MODE == 0) {
+                    atomicAdd(&a.counts[b], 1);
+                } else {
+                    const int slot = atomicAdd(&a.cursor[b], 1);
+                    const int64_t idx = int64_t(a.offsets[b]) + slot;
+                    if (idx < a.capacity) a.list[idx] = atom;
+                }
+            }
+        }
+    }
+}
+
+// exclusive scan of counts[0..n) into offsets[0..n]; one workgroup
+__global__ __launch_bounds__(1024) void k_scan(SplatArgs a)
+{
+    __shared__ int64_t part[1024];
+    const int64_t n = a.nbricks_total;
+    const int t = threadIdx.x;
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t b0 = t * per, b1 = (b0 + per < n) ? b0 + per : n;
+    int64_t s = 0;
+    for (int64_t i = b0; i < b1; ++i) s += a.counts[i];
+    part[t] = s;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over the 1024 segment sums
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t v = (t >= off) ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t run = part[t] - s;
+    for (int64_t i = b0; i < b1; ++i) {
+        const int64_t c = a.counts[i];
+        a.offsets[i] = int32_t(run < a.capacity ? run : a.capacity);
+        run += c;
+    }
+    if (t == 1023) {
+        const int64_t total = part[1023];
+        a.offsets[n] = int32_t(total < a.capacity ? total : a.capacity);
+        if (total > a.capacity) atomicOr(&a.status->bits, 0x4u);
+    }
+}
+
+// one wavefront per brick: rank every entry (atom indices are distinct)
+__global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a)
+{
+    const int64_t b = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (b >= a.nbricks_total) return;
+    const int64_t off = a.offsets[b];
+    const int cnt = int(a.offsets[b + 1] - off);
+    for (int e = lane; e < cnt; e += 64) {
+        const int v = a.list[off + e];
+        int rank = 0;
+        for (int j = 0; j < cnt; ++j) rank += (a.list[off + j] < v) ? 1 : 0;
+        a.list_sorted[off + rank] = v;
+    }
+}
+
+__device__ __forceinline__ int brick_prob(const SplatArgs &a, int64_t b)
+{
+    int p = 0;
+    while (p + 1 < a.nprob && b >= a.desc[p + 1].brick_off) ++p;
+    return p;
+}
+
+template <typename T>
+__device__ __forceinline__ T expT(T x);
+template <>
+__device__ __forceinline__ float expT<float>(float x) { return expf(x); }
+template <>
+__device__ __forceinline__ double expT<double>(double x) { return exp(x); }
+
+// 1-D periodic Gaussian factor along one axis at wrapped index ig:
+// g = sum over unwrapped i' = ig (mod n) in [lo, hi] of exp(-(i' h - X)^2 / (2 s^2)),
+// gd = the same sum weighted by the displacement (i' h - X).  The exponent is
+// formed in double (positions near L lose digits in float) and evaluated in T.
+template <typename T, bool WITH_D>
+__device__ __forceinline__ void axis_factor_t(int ig, int n, double h, double X, int lo, int hi, double inv2s2, T &g,
+                                              T &gd)
+{
+    g = T(0);
+    gd = T(0);
+    if (hi < lo || ig >= n) return;
+    for (int ip = lo + wrapi(ig - lo, n); ip <= hi; ip += n) {
+        const double dd = double(ip) * h - X;
+        const T e = expT<T>(T(-dd * dd * inv2s2));
+        g += e;
+        if (WITH_D) gd += e * T(dd);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBrickThreads) void k_splat_gather(SplatArgs a, const double *qsum)
+{
+    __shared__ T gx[kChunk][kBI], gy[kChunk][kBJ];
+    __shared__ __align__(16) T gz[kChunk][kBK];
+    const int64_t b = blockIdx.x;
+    const int prob = brick_prob(a, b);
+    const ProbDesc &d = a.desc[prob];
+    const int64_t lb = b - d.brick_off;
+    const int bk = int(lb % d.nbricks[2]);
+    const int bj = int((lb / d.nbricks[2]) % d.nbricks[1]);
+    const int bi = int(lb / (int64_t(d.nbricks[2]) * d.nbricks[1]));
+    const int t = threadIdx.x;
+    const int ci = (t & 63) >> 3, cj = t & 7, strip = t >> 6;
+    const int i = bi * kBI + ci, j = bj * kBJ + cj, k0 = bk * kBK + strip * kStrip;
+    const int64_t off = a.offsets[b];
+    const int cnt = int(a.offsets[b + 1] - off);
+    const double h[3] = {d.L[0] / d.dims[0], d.L[1] / d.dims[1], d.L[2] / d.dims[2]};
+
+    T acc[kStrip];
+#pragma unroll
+    for (int r = 0; r < kStrip; ++r) acc[r] = T(0);
+
+    for (int c0 = 0; c0 < cnt; c0 += kChunk) {
+        const int nc = (cnt - c0) < kChunk ? (cnt - c0) : kChunk;
+        // tables: per atom 8 + 8 + 32 entries
+        for (int e = t; e < nc * (kBI + kBJ + kBK); e += kBrickThreads) {
+            const int s = e / (kBI + kBJ + kBK), q = e % (kBI + kBJ + kBK);
+            const AtomInfo in = a.info[a.list_sorted[off + c0 + s]];
+            T g, gd;
+            if (q < kBI) {
+                axis_factor_t<T, false>(bi * kBI + q, d.dims[0], h[0], in.X[0], in.lo[0], in.hi[0], in.inv2s2, g, gd);
+                gx[s][q] = g * T(in.w);
+            } else if (q < kBI + kBJ) {
+                const int qq = q - kBI;
+                axis_factor_t<T, false>(bj * kBJ + qq, d.dims[1], h[1], in.X[1], in.lo[1], in.hi[1], in.inv2s2, g, gd);
+                gy[s][qq] = g;
+            } else {
+                const int qq = q - kBI - kBJ;
+                axis_factor_t<T, false>(bk * kBK + qq, d.dims[2], h[2], in.X[2], in.lo[2], in.hi[2], in.inv2s2, g, gd);
+                gz[s][qq] = g;
+            }
+        }
+        __syncthreads();
+        for (int s = 0; s < nc; ++s) {
+            const T c = gx[s][ci] * gy[s][cj];
+#pragma unroll
+            for (int r = 0; r < kStrip; ++r) acc[r] += c * gz[s][strip * kStrip + r];
+        }
+        __syncthreads();
+    }
+    if (i >= d.dims[0] || j >= d.dims[1]) return;
+    const T bg = a.subtract_background ? T(qsum[prob] / (d.L[0] * d.L[1] * d.L[2])) : T(0);
+    T *out = reinterpret_cast<T *>(a.rho) + d.grid_off + (int64_t(i) * d.dims[1] + j) * d.dims[2];
+#pragma unroll
+    for (int r = 0; r < kStrip; ++r)
+        if (k0 + r < d.dims[2]) out[k0 + r] = acc[r] - bg;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum_t(T v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBrickThreads) void k_splat_adjoint(SplatArgs a)
+{
+    __shared__ T gx[kChunk][kBI], gdx[kChunk][kBI], gy[kChunk][kBJ], gdy[kChunk][kBJ];
+    __shared__ __align__(16) T gz[kChunk][kBK];
+    __shared__ __align__(16) T gdz[kChunk][kBK];
+    __shared__ T red[4][kChunk][3];
+    const int64_t b = blockIdx.x;
+    const int prob = brick_prob(a, b);
+    const ProbDesc &d = a.desc[prob];
+    const int64_t lb = b - d.brick_off;
+    const int bk = int(lb % d.nbricks[2]);
+    const int bj = int((lb / d.nbricks[2]) % d.nbricks[1]);
+    const int bi = int(lb / (int64_t(d.nbricks[2]) * d.nbricks[1]));
+    const int t = threadIdx.x;
+    const int ci = (t & 63) >> 3, cj = t & 7, strip = t >> 6;
+    const int i = bi * kBI + ci, j = bj * kBJ + cj, k0 = bk * kBK + strip * kStrip;
+    const int64_t off = a.offsets[b];
+    const int cnt = int(a.offsets[b + 1] - off);
+    if (cnt == 0) return;
+    const double h[3] = {d.L[0] / d.dims[0], d.L[1] / d.dims[1], d.L[2] / d.dims[2]};
+
+    T gr[kStrip];
+    {
+        const bool inb = (i < d.dims[0]) && (j < d.dims[1]);
+        const T *src = reinterpret_cast<const T *>(a.grad_rho) + d.grid_off +
+                       (int64_t(inb ? i : 0) * d.dims[1] + (inb ? j : 0)) * d.dims[2];
+#pragma unroll
+        for (int r = 0; r < kStrip; ++r) gr[r] = (inb && k0 + r < d.dims[2]) ? src[k0 + r] : T(0);
+    }
+
+    for (int c0 = 0; c0 < cnt; c0 += kChunk) {
+        const int nc = (cnt - c0) < kChunk ? (cnt - c0) : kChunk;
+        for (int e = t; e < nc * (kBI + kBJ + kBK); e += kBrickThreads) {
+            const int s = e / (kBI + kBJ + kBK), q = e % (kBI + kBJ + kBK);
+            const AtomInfo in = a.info[a.list_sorted[off + c0 + s]];
+            T g, gd;
+            if (q < kBI) {
+                axis_factor_t<T, true>(bi * kBI + q, d.dims[0], h[0], in.X[0], in.lo[0], in.hi[0], in.inv2s2, g, gd);
+                gx[s][q] = g;
+                gdx[s][q] = gd;
+            } else if (q < kBI + kBJ) {
+                const int qq = q - kBI;
+                axis_factor_t<T, true>(bj * kBJ + qq, d.dims[1], h[1], in.X[1], in.lo[1], in.hi[1], in.inv2s2, g, gd);
+                gy[s][qq] = g;
+                gdy[s][qq] = gd;
+            } else {
+                const int qq = q - kBI - kBJ;
+                axis_factor_t<T, true>(bk * kBK + qq, d.dims[2], h[2], in.X[2], in.lo[2], in.hi[2], in.inv2s2, g, gd);
+                gz[s][qq] = g;
+                gdz[s][qq] = gd;
+            }
+        }
+        __syncthreads();
+        for (int s = 0; s < nc; ++s) {
+            T s0 = T(0), s1 = T(0);
+#pragma unroll
+            for (int r = 0; r < kStrip; ++r) {
+                s0 += gr[r] * gz[s][strip * kStrip + r];
+                s1 += gr[r] * gdz[s][strip * kStrip + r];
+            }
+            const T fx = wave_sum_t<T>(gdx[s][ci] * gy[s][cj] * s0);
+            const T fy = wave_sum_t<T>(gx[s][ci] * gdy[s][cj] * s0);
+            const T fz = wave_sum_t<T>(gx[s][ci] * gy[s][cj] * s1);
+            if ((t & 63) == 0) {
+                red[strip][s][0] = fx;
+                red[strip][s][1] = fy;
+                red[strip][s][2] = fz;
+            }
+        }
+        __syncthreads();
+        for (int e = t; e < nc * 3; e += kBrickThreads) {
+            const int s = e / 3, x = e % 3;
+            const double v = double(red[0][s][x]) + double(red[1][s][x]) + double(red[2][s][x]) + double(red[3][s][x]);
+            const int64_t slot = off + c0 + s;
+            if (slot < a.capacity) a.bpart[slot * 3 + x] = v;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_adjoint_final(SplatArgs a)
+{
+    const int atom = blockIdx.x * blockDim.x + threadIdx.x;
+    if (atom >= a.natoms) return;
+    const AtomInfo in = a.info[atom];
+    const ProbDesc &d = a.desc[in.prob];
+    const int bsz[3] = {kBI, kBJ, kBK};
+    int st[3], ct[3];
+    for (int x = 0; x < 3; ++x) axis_bricks(in.lo[x], in.hi[x], d.dims[x], bsz[x], d.nbricks[x], st[x], ct[x]);
+    double f[3] = {0.0, 0.0, 0.0};
+    for (int u = 0; u < ct[0]; ++u) {
+        const int bi = (st[0] + u) % d.nbricks[0];
+        for (int v = 0; v < ct[1]; ++v) {
+            const int bj = (st[1] + v) % d.nbricks[1];
+            for (int w = 0; w < ct[2]; ++w) {
+                const int bk = (st[2] + w) % d.nbricks[2];
+                const int64_t b = d.brick_off + (int64_t(bi) * d.nbricks[1] + bj) * d.nbricks[2] + bk;
+                // binary search for this atom in the brick's sorted list
+                int64_t lo = a.offsets[b], hi = int64_t(a.offsets[b + 1]) - 1;
+                while (lo <= hi) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    const int v2 = a.list_sorted[mid];
+                    if (v2 == atom) {
+                        f[0] += a.bpart[mid * 3 + 0];
+                        f[1] += a.bpart[mid * 3 + 1];
+                        f[2] += a.bpart[mid * 3 + 2];
+                        break;
+                    }
+                    if (v2 < atom) lo = mid + 1;
+                    else hi = mid - 1;
+                }
+            }
+        }
+    }
+    const double scale = in.w * 2.0 * in.inv2s2;  // Z (2 pi s^2)^(-3/2) / s^2
+    for (int x = 0; x < 3; ++x) a.grad_pos[3 * atom + x] = scale * f[x];
+}
+
+// ------------------------------------------------------------- host side
+
+hipError_t run_bin(const SplatArgs &a, hipStream_t s)
+{
+    const int nb = int((a.natoms + 255) / 256);
+    const int64_t nbt = a.nbricks_total;
+    hipLaunchKernelGGL(k_fill_i32, dim3(1024), dim3(256), 0, s, a.counts, nbt + 1, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1024), dim3(256), 0, s, a.cursor, nbt, 0);
+    hipLaunchKernelGGL(k_charge, dim3(a.nprob), dim3(256), 0, s, a, a.qsum);
+    if (a.natoms > 0) {
+        hipLaunchKernelGGL(k_atom_prep, dim3(nb), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_brick_visit<0>, dim3(nb), dim3(256), 0, s, a);
+    }
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
+    if (a.natoms > 0) hipLaunchKernelGGL(k_brick_visit<1>, dim3(nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_brick_sort, dim3(int((nbt + 3) / 4)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t run_gather(const SplatArgs &a, hipStream_t s)
+{
+    if (a.fp64)
+        hipLaunchKernelGGL(k_splat_gather<double>, dim3(int(a.nbricks_total)), dim3(kBrickThreads), 0, s, a, a.qsum);
+    else
+        hipLaunchKernelGGL(k_splat_gather<float>, dim3(int(a.nbricks_total)), dim3(kBrickThreads), 0, s, a, a.qsum);
+    return hipGetLastError();
+}
+
+hipError_t run_adjoint(const SplatArgs &a, hipStream_t s)
+{
+    if (a.fp64)
+        hipLaunchKernelGGL(k_splat_adjoint<double>, dim3(int(a.nbricks_total)), dim3(kBrickThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_splat_adjoint<float>, dim3(int(a.nbricks_total)), dim3(kBrickThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t run_adjoint_final(const SplatArgs &a, hipStream_t s)
+{
+    if (a.natoms > 0)
+        hipLaunchKernelGGL(k_adjoint_final, dim3(int((a.natoms + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace hartree

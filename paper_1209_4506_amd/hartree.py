@@ -1,0 +1,309 @@
+"""Thin Python binding of libhartree.so (the C ABI declared in include/hartree.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  PyTorch supplies device memory and the current stream.  Importing
+this module loads the library and raises if it is missing -- there is no CPU
+fallback.
+
+Names follow the C ABI:
+
+* ``Plan``                 -- hartree_plan_create[_batched] + workspace binding
+* ``Plan.solve``           -- hartree_solve: V = P rho and E_H (Eq. (6), Eq. (7))
+* ``Plan.energy``          -- hartree_energy
+* ``Plan.backward``        -- hartree_backward: P (grad_v + grad_e dV rho)
+* ``Plan.splat``           -- hartree_splat: Gaussian atomic density
+* ``Plan.splat_adjoint``   -- hartree_splat_adjoint: d/dR of sum grad_rho * rho
+* ``HartreeFn``            -- autograd function (pos -> V, E_H) whose backward
+                              applies the symmetric P and the splat adjoint
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhartree.so")
+
+FP64, FP32 = 0, 1
+STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_DIMS", 3: "ERR_CELL", 4: "ERR_UNSUPPORTED", 5: "ERR_WORKSPACE", 6: "ERR_HIP"}
+DEV_BAD_ATOM, DEV_SIGMA_RANGE, DEV_BIN_OVERFLOW = 0x1, 0x2, 0x4
+
+
+class HartreeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS.get(code, str(code)), msg))
+        self.code = code
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("cutoff_sigmas", ctypes.c_double), ("max_sigma", ctypes.c_double),
+                ("max_atoms", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libhartree.so is not built (run __graft_entry__.build() or "
+                          "python -m paper_1209_4506_amd.build); there is no fallback path")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, d, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    P = ctypes.POINTER
+    sig = {
+        "hartree_plan_create": [P(vp), P(d), P(i32), i32, P(PlanOpts)],
+        "hartree_plan_create_batched": [P(vp), i32, P(d), P(i32), i32, P(PlanOpts)],
+        "hartree_plan_nprob": [vp, P(i32)],
+        "hartree_plan_grid_offset": [vp, i32, P(i64)],
+        "hartree_workspace_size": [vp, P(sz)],
+        "hartree_bind_workspace": [vp, vp, sz],
+        "hartree_solve": [vp, vp, vp, vp, vp],
+        "hartree_energy": [vp, vp, vp, vp],
+        "hartree_backward": [vp, vp, vp, vp, vp, vp],
+        "hartree_splat": [vp, i32, vp, vp, vp, P(i32), vp, i32, vp],
+        "hartree_splat_adjoint": [vp, i32, vp, vp, vp, P(i32), vp, vp, vp],
+        "hartree_device_status": [vp, P(ctypes.c_uint32), vp],
+        "hartree_profile_begin": [vp],
+        "hartree_profile_end": [vp, P(d), P(i64)],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.hartree_plan_destroy.argtypes = [vp]
+    lib.hartree_plan_destroy.restype = None
+    lib.hartree_last_error.argtypes = []
+    lib.hartree_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+LIB = _load()
+
+# every symbol the header declares
+EXPORTED = ["hartree_plan_create", "hartree_plan_create_batched", "hartree_plan_destroy", "hartree_plan_nprob",
+            "hartree_plan_grid_offset", "hartree_workspace_size", "hartree_bind_workspace", "hartree_solve",
+            "hartree_energy", "hartree_backward", "hartree_splat", "hartree_splat_adjoint",
+            "hartree_device_status", "hartree_profile_begin", "hartree_profile_end", "hartree_last_error"]
+
+# hartree_kernel_id order
+KERNELS = ["r2c", "r2c_bwd", "fft_b", "fft_a", "fft_a_bwd", "fft_a_eonly", "fft_b_inv", "c2r", "finalize",
+           "bin", "splat", "adjoint", "adjoint_final"]
+
+
+def _check(code):
+    if code != 0:
+        raise HartreeError(code, LIB.hartree_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _opts(cutoff_sigmas=0.0, max_sigma=0.0, max_atoms=0):
+    o = PlanOpts()
+    o.cutoff_sigmas = float(cutoff_sigmas)
+    o.max_sigma = float(max_sigma)
+    o.max_atoms = int(max_atoms)
+    return o
+
+
+class Plan:
+    """A solve plan for one cell (or a batch of cells) and its bound workspace.
+
+    ``cells``: (3, 3) rows a, b, c in Bohr, or (nprob, 3, 3) for a batch.
+    ``dims``: (Na, Nb, Nc), or (nprob, 3).  ``precision``: "fp32" or "fp64".
+    Grid tensors are C-contiguous (Na, Nb, Nc) of the plan's dtype on the
+    plan's device; a batched plan takes the grids flattened and concatenated.
+    """
+
+    def __init__(self, cells, dims, precision="fp32", device="cuda", cutoff_sigmas=0.0, max_sigma=0.0,
+                 max_atoms=0, bind=True):
+        cells = np.ascontiguousarray(cells, dtype=np.float64)
+        dims = np.ascontiguousarray(dims, dtype=np.int32)
+        self.batched = cells.ndim == 3
+        if not self.batched:
+            cells = cells.reshape(1, 3, 3)
+            dims = dims.reshape(1, 3)
+        self.nprob = cells.shape[0]
+        self.cells = cells
+        self.dims = [tuple(int(v) for v in r) for r in dims]
+        self.precision = precision
+        self.fp = FP64 if precision == "fp64" else FP32
+        self.dtype = torch.float64 if self.fp == FP64 else torch.float32
+        self.device = torch.device(device)
+        h = ctypes.c_void_p()
+        opts = _opts(cutoff_sigmas, max_sigma, max_atoms)
+        cp = cells.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        dp = dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        if self.batched:
+            _check(LIB.hartree_plan_create_batched(ctypes.byref(h), self.nprob, cp, dp, self.fp, ctypes.byref(opts)))
+        else:
+            _check(LIB.hartree_plan_create(ctypes.byref(h), cp, dp, self.fp, ctypes.byref(opts)))
+        self._h = h
+        off = ctypes.c_int64()
+        self.offsets = []
+        for p in range(self.nprob + 1):
+            _check(LIB.hartree_plan_grid_offset(h, p, ctypes.byref(off)))
+            self.offsets.append(int(off.value))
+        self.volumes = np.abs(np.linalg.det(cells))
+        self.workspace = None
+        if bind:
+            self.bind()
+
+    # ------------------------------------------------------------ plumbing
+    def workspace_size(self) -> int:
+        n = ctypes.c_size_t()
+        _check(LIB.hartree_workspace_size(self._h, ctypes.byref(n)))
+        return int(n.value)
+
+    def bind(self, workspace: torch.Tensor = None):
+        need = self.workspace_size()
+        if workspace is None:
+            raw = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+            shift = (-raw.data_ptr()) % 256
+            workspace = raw[shift:shift + need]
+            self._ws_raw = raw
+        _check(LIB.hartree_bind_workspace(self._h, ctypes.c_void_p(workspace.data_ptr()), need))
+        self.workspace = workspace
+        return self
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            LIB.hartree_plan_destroy(h)
+            self._h = None
+
+    def grid_shape(self):
+        return self.dims[0] if not self.batched else (self.offsets[-1],)
+
+    def empty_grid(self):
+        return torch.empty(self.grid_shape(), dtype=self.dtype, device=self.device)
+
+    def _grid(self, t, name):
+        if t is None:
+            return None
+        if t.dtype != self.dtype or t.device.type != "cuda" or not t.is_contiguous():
+            raise TypeError("%s must be a contiguous %s CUDA tensor" % (name, self.dtype))
+        if t.numel() != self.offsets[-1]:
+            raise ValueError("%s has %d elements, the plan's grid has %d" % (name, t.numel(), self.offsets[-1]))
+        return t
+
+    # ------------------------------------------------------------ solve
+    def solve(self, rho, v=None, e_h=None, stream=None):
+        """V = P rho and E_H; returns (V, E_H) (E_H: float64 tensor of nprob)."""
+        self._grid(rho, "rho")
+        v = self.empty_grid() if v is None else self._grid(v, "v")
+        e_h = torch.empty(self.nprob, dtype=torch.float64, device=self.device) if e_h is None else e_h
+        _check(LIB.hartree_solve(self._h, _ptr(rho), _ptr(v), _ptr(e_h), stream or _stream(self.device)))
+        return v, e_h
+
+    def potential(self, rho, v=None, stream=None):
+        """V = P rho without the energy reduction."""
+        self._grid(rho, "rho")
+        v = self.empty_grid() if v is None else self._grid(v, "v")
+        _check(LIB.hartree_solve(self._h, _ptr(rho), _ptr(v), None, stream or _stream(self.device)))
+        return v
+
+    def energy(self, rho, e_h=None, stream=None):
+        self._grid(rho, "rho")
+        e_h = torch.empty(self.nprob, dtype=torch.float64, device=self.device) if e_h is None else e_h
+        _check(LIB.hartree_energy(self._h, _ptr(rho), _ptr(e_h), stream or _stream(self.device)))
+        return e_h
+
+    def backward(self, grad_v=None, grad_e=None, rho=None, out=None, stream=None):
+        """grad_rho = P (grad_v + grad_e * dV * rho)."""
+        self._grid(grad_v, "grad_v")
+        self._grid(rho, "rho")
+        if grad_e is not None:
+            grad_e = grad_e.to(device=self.device, dtype=torch.float64).contiguous().reshape(-1)
+            if grad_e.numel() != self.nprob:
+                raise ValueError("grad_e needs one value per problem")
+        out = self.empty_grid() if out is None else self._grid(out, "out")
+        _check(LIB.hartree_backward(self._h, _ptr(grad_v), _ptr(grad_e), _ptr(rho), _ptr(out),
+                                    stream or _stream(self.device)))
+        return out
+
+    # ------------------------------------------------------------ atoms
+    def _atoms(self, pos, Z, sigma, atom_counts):
+        pos = pos.to(device=self.device, dtype=torch.float64).contiguous().reshape(-1, 3)
+        Z = Z.to(device=self.device, dtype=torch.float64).contiguous().reshape(-1)
+        sigma = sigma.to(device=self.device, dtype=torch.float64).contiguous().reshape(-1)
+        n = pos.shape[0]
+        if Z.numel() != n or sigma.numel() != n:
+            raise ValueError("pos, Z and sigma disagree on the atom count")
+        offs = None
+        if self.batched:
+            if atom_counts is None:
+                raise ValueError("a batched plan needs atom_counts")
+            c = np.concatenate([[0], np.cumsum(np.asarray(atom_counts, dtype=np.int64))]).astype(np.int32)
+            offs = (ctypes.c_int32 * len(c))(*c.tolist())
+        return pos, Z, sigma, n, offs
+
+    def splat(self, pos, Z, sigma, out=None, subtract_background=True, atom_counts=None, stream=None):
+        pos, Z, sigma, n, offs = self._atoms(pos, Z, sigma, atom_counts)
+        out = self.empty_grid() if out is None else self._grid(out, "out")
+        _check(LIB.hartree_splat(self._h, n, _ptr(pos), _ptr(Z), _ptr(sigma), offs, _ptr(out),
+                                 1 if subtract_background else 0, stream or _stream(self.device)))
+        return out
+
+    def splat_adjoint(self, pos, Z, sigma, grad_rho, out=None, atom_counts=None, stream=None):
+        pos, Z, sigma, n, offs = self._atoms(pos, Z, sigma, atom_counts)
+        self._grid(grad_rho, "grad_rho")
+        out = torch.empty((n, 3), dtype=torch.float64, device=self.device) if out is None else out
+        _check(LIB.hartree_splat_adjoint(self._h, n, _ptr(pos), _ptr(Z), _ptr(sigma), offs, _ptr(grad_rho),
+                                         _ptr(out), stream or _stream(self.device)))
+        return out
+
+    def device_status(self) -> int:
+        bits = ctypes.c_uint32()
+        _check(LIB.hartree_device_status(self._h, ctypes.byref(bits), _stream(self.device)))
+        return int(bits.value)
+
+    def profile_begin(self):
+        _check(LIB.hartree_profile_begin(self._h))
+
+    def profile_end(self):
+        """{kernel group: (total ms, launches)} since profile_begin (waits for the GPU)."""
+        ms = (ctypes.c_double * len(KERNELS))()
+        n = (ctypes.c_int64 * len(KERNELS))()
+        _check(LIB.hartree_profile_end(self._h, ms, n))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNELS) if n[i]}
+
+    def dv(self):
+        return [float(self.volumes[p] / (self.offsets[p + 1] - self.offsets[p])) for p in range(self.nprob)]
+
+
+class HartreeFn(torch.autograd.Function):
+    """(pos) -> (V, E_H) through the splat and the Poisson solve.
+
+    Backward: grad_rho = P (grad_V + grad_E dV rho), then the splat adjoint
+    gives dL/dpos.  The real-space density from the forward is kept; its
+    spectrum is recomputed by the backward transform rather than stored.
+    """
+
+    @staticmethod
+    def forward(ctx, pos, Z, sigma, plan, atom_counts=None):
+        rho = plan.splat(pos.detach(), Z, sigma, atom_counts=atom_counts)
+        V, E = plan.solve(rho)
+        ctx.plan = plan
+        ctx.atom_counts = atom_counts
+        ctx.save_for_backward(pos, Z, sigma, rho)
+        return V, E
+
+    @staticmethod
+    def backward(ctx, gV, gE):
+        pos, Z, sigma, rho = ctx.saved_tensors
+        plan = ctx.plan
+        gV = None if gV is None else gV.to(plan.dtype).contiguous()
+        grho = plan.backward(grad_v=gV, grad_e=gE, rho=rho if gE is not None else None)
+        gpos = plan.splat_adjoint(pos.detach(), Z, sigma, grho, atom_counts=ctx.atom_counts)
+        return gpos.to(pos.dtype), None, None, None, None
+
+
+def hartree(pos, Z, sigma, plan, atom_counts=None):
+    """Differentiable (V, E_H) of Gaussian atoms at ``pos`` (see HartreeFn)."""
+    return HartreeFn.apply(pos, Z, sigma, plan, atom_counts)

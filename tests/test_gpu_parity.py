@@ -1,0 +1,214 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every test prints the case it is about to run before touching the GPU.
+Tolerances: FP64 V rel-L2 <= 1e-12, E_H rel <= 1e-12; FP32 V rel-L2 <= 5e-6,
+E_H rel <= 1e-6.  The FP32 inputs are rounded to float first and the oracle
+is fed the same rounded values.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1209_4506_amd import inputs
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a HIP device")]
+
+TOL = {"fp64": dict(v=1e-12, e=1e-12), "fp32": dict(v=5e-6, e=1e-6)}
+CELLS = {
+    "cubic": np.diag([10.0, 10.0, 10.0]),
+    "ortho": np.diag([8.0, 11.0, 13.5]),
+    "triclinic": np.array([[9.0, 0.0, 0.0], [2.5, 8.0, 0.0], [-1.5, 2.0, 10.5]]),
+}
+# several tiles, ragged tails, odd and even Nc, radix 7, a degenerate axis, and
+# every length class up to 1024 on some axis
+DIMS = [(12, 10, 15), (32, 32, 32), (45, 36, 40), (7, 14, 21), (1, 6, 10), (50, 48, 27), (64, 60, 90),
+        (36, 40, 360), (20, 300, 24), (270, 12, 16), (1024, 4, 6), (6, 1024, 4), (4, 6, 1024), (2, 2, 2), (1, 1, 1)]
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel_l2(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def to_dev(x, dtype):
+    return torch.tensor(np.ascontiguousarray(x), device="cuda", dtype=dtype)
+
+
+@pytest.fixture(scope="module")
+def H():
+    import paper_1209_4506_amd.hartree as h
+
+    return h
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dims", DIMS)
+@pytest.mark.parametrize("cellname", ["ortho", "triclinic"])
+def test_solve_parity(H, oracle_mod, prec, dims, cellname):
+    say("case solve", prec, dims, cellname)
+    cell = CELLS[cellname]
+    plan = H.Plan(cell, dims, precision=prec, max_atoms=1)
+    rho = inputs.random_grid(dims, 7).astype(np.float32 if prec == "fp32" else np.float64)
+    V, E = plan.solve(to_dev(rho, plan.dtype))
+    e_only = plan.energy(to_dev(rho, plan.dtype))
+    torch.cuda.synchronize()
+    V_o, e_real, e_recip, _ = oracle_mod.poisson(cell.reshape(9), rho.astype(np.float64))
+    ev = rel_l2(V.double().cpu().numpy(), V_o)
+    ee = abs(float(E[0]) - e_recip) / max(abs(e_recip), 1e-300)
+    say("  V rel-L2 %.3e  E_H rel %.3e" % (ev, ee))
+    assert ev <= TOL[prec]["v"]
+    if np.prod(dims) > 1:
+        assert ee <= TOL[prec]["e"]
+    else:
+        assert float(E[0]) == 0.0 and e_recip == 0.0
+    # the energy-only pass sums the same partials in the same order
+    assert float(e_only[0]) == float(E[0])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dims", [(12, 10, 15), (45, 36, 40), (36, 40, 360)])
+def test_backward_parity(H, oracle_mod, prec, dims):
+    say("case backward", prec, dims)
+    cell = CELLS["triclinic"]
+    plan = H.Plan(cell, dims, precision=prec, max_atoms=1)
+    ft = np.float32 if prec == "fp32" else np.float64
+    rho = inputs.random_grid(dims, 1).astype(ft)
+    gv = inputs.random_grid(dims, 2).astype(ft)
+    ge = 0.7
+    out = plan.backward(grad_v=to_dev(gv, plan.dtype), grad_e=torch.tensor([ge], dtype=torch.float64),
+                        rho=to_dev(rho, plan.dtype))
+    only_e = plan.backward(grad_v=None, grad_e=torch.tensor([ge], dtype=torch.float64), rho=to_dev(rho, plan.dtype))
+    only_v = plan.backward(grad_v=to_dev(gv, plan.dtype))
+    torch.cuda.synchronize()
+    ref = oracle_mod.backward(cell.reshape(9), rho.astype(np.float64), grad_v=gv.astype(np.float64), grad_e=ge)
+    ref_e = oracle_mod.backward(cell.reshape(9), rho.astype(np.float64), grad_v=None, grad_e=ge)
+    ref_v = oracle_mod.backward(cell.reshape(9), rho.astype(np.float64), grad_v=gv.astype(np.float64), grad_e=0.0)
+    for got, want, name in ((out, ref, "both"), (only_e, ref_e, "grad_e"), (only_v, ref_v, "grad_v")):
+        r = rel_l2(got.double().cpu().numpy(), want)
+        say("  %s rel-L2 %.3e" % (name, r))
+        assert r <= TOL[prec]["v"]
+
+
+def _atoms(p, dev="cuda"):
+    return (torch.tensor(p.pos, device=dev), torch.tensor(p.Z, device=dev), torch.tensor(p.sigma, device=dev))
+
+
+SPLAT_CASES = {
+    "cubic32": lambda: inputs.cubic32(),
+    # edges of 8-9 Bohr with sigma up to 1: at 8 sigma the truncation window is
+    # wider than the cell, so several periodic images meet on one grid point
+    "tight_images": lambda: inputs.small_problem((30, 36, 40), 20, seed=3, L=(8.0, 8.5, 9.0)),
+    "ragged": lambda: inputs.small_problem((45, 27, 50), 37, seed=4, L=(12.0, 7.5, 14.0), sig=(0.6, 0.9)),
+}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", list(SPLAT_CASES))
+def test_splat_parity(H, oracle_mod, prec, case):
+    say("case splat", prec, case)
+    p = SPLAT_CASES[case]()
+    plan = H.Plan(p.cell, p.dims, precision=prec, max_atoms=p.natoms)
+    pos, Z, sig = _atoms(p)
+    rho = plan.splat(pos, Z, sig).double().cpu().numpy()
+    rho_nb = plan.splat(pos, Z, sig, subtract_background=False).double().cpu().numpy()
+    assert plan.device_status() == 0
+    ref = oracle_mod.splat(p.cell.reshape(9), p.dims, p.pos, p.Z, p.sigma)
+    ref_nb = oracle_mod.splat(p.cell.reshape(9), p.dims, p.pos, p.Z, p.sigma, subtract_background=False)
+    scale = np.abs(ref_nb).max()
+    e1 = np.abs(rho - ref).max() / scale
+    e2 = np.abs(rho_nb - ref_nb).max() / scale
+    say("  rho max-rel %.3e (background) %.3e (none)" % (e1, e2))
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    assert e1 <= tol and e2 <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", list(SPLAT_CASES))
+def test_splat_adjoint_parity(H, oracle_mod, prec, case):
+    say("case adjoint", prec, case)
+    p = SPLAT_CASES[case]()
+    plan = H.Plan(p.cell, p.dims, precision=prec, max_atoms=p.natoms)
+    pos, Z, sig = _atoms(p)
+    # a smooth field: the Hartree potential of the atoms themselves
+    rho_o = oracle_mod.splat(p.cell.reshape(9), p.dims, p.pos, p.Z, p.sigma)
+    V_o = oracle_mod.poisson(p.cell.reshape(9), rho_o)[0]
+    g = V_o.astype(np.float32 if prec == "fp32" else np.float64)
+    got = plan.splat_adjoint(pos, Z, sig, to_dev(g, plan.dtype)).cpu().numpy()
+    assert plan.device_status() == 0
+    ref = oracle_mod.splat_adjoint(p.cell.reshape(9), p.pos, p.Z, p.sigma, g.astype(np.float64))
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    say("  grad max-rel %.3e" % err)
+    assert err <= (1e-10 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_end_to_end_cubic32(H, oracle_mod, prec):
+    """32^3 cubic cell, 8 Gaussians: splat, V, E_H, and dL/dR for
+    L = E_H + <c, V> dV, all against the oracle."""
+    say("case end-to-end cubic32", prec)
+    p = inputs.cubic32()
+    cell9 = p.cell.reshape(9)
+    plan = H.Plan(p.cell, p.dims, precision=prec, max_atoms=p.natoms)
+    pos, Z, sig = _atoms(p)
+    pos.requires_grad_(True)
+    V, E = H.hartree(pos, Z, sig, plan)
+    c = inputs.random_grid(p.dims, 99)
+    dv = plan.dv()[0]
+    L = E.sum() + (V.double() * to_dev(c, torch.float64)).sum() * dv
+    L.backward()
+    torch.cuda.synchronize()
+    rho_o = oracle_mod.splat(cell9, p.dims, p.pos, p.Z, p.sigma)
+    V_o, _, E_o, _ = oracle_mod.poisson(cell9, rho_o)
+    g_o = oracle_mod.backward(cell9, rho_o, grad_v=c * dv, grad_e=1.0)
+    gp_o = oracle_mod.splat_adjoint(cell9, p.pos, p.Z, p.sigma, g_o)
+    ev = rel_l2(V.detach().double().cpu().numpy(), V_o)
+    ee = abs(float(E[0]) - E_o) / E_o
+    ef = np.abs(pos.grad.cpu().numpy() - gp_o).max() / np.abs(gp_o).max()
+    say("  V %.3e  E_H %.3e  grad %.3e" % (ev, ee, ef))
+    assert ev <= TOL[prec]["v"] and ee <= TOL[prec]["e"]
+    assert ef <= (1e-10 if prec == "fp64" else 1e-4)
+
+
+def test_bitwise_reproducible(H):
+    say("case reproducible diamond180 fp32")
+    p = inputs.diamond180()
+    plan = H.Plan(p.cell, p.dims, precision="fp32", max_atoms=p.natoms)
+    pos, Z, sig = _atoms(p)
+    outs = []
+    for _ in range(2):
+        rho = plan.splat(pos, Z, sig)
+        V, E = plan.solve(rho)
+        g = plan.backward(grad_v=V, grad_e=torch.ones(1, dtype=torch.float64), rho=rho)
+        f = plan.splat_adjoint(pos, Z, sig, g)
+        outs.append([rho.cpu(), V.cpu(), E.cpu(), g.cpu(), f.cpu()])
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+
+
+def test_rejects_arguments(H):
+    say("case argument errors")
+    with pytest.raises(H.HartreeError) as ei:
+        H.Plan(np.eye(3) * 10, (32, 32, 33))
+    assert ei.value.code == 2
+    with pytest.raises(H.HartreeError) as ei:
+        H.Plan(np.zeros((3, 3)), (8, 8, 8))
+    assert ei.value.code == 3
+    tri = H.Plan(CELLS["triclinic"], (8, 8, 8), max_atoms=4)
+    pos = torch.zeros((1, 3), dtype=torch.float64, device="cuda")
+    one = torch.ones(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(H.HartreeError) as ei:
+        tri.splat(pos, one, one)
+    assert ei.value.code == 4
+    plan = H.Plan(np.eye(3) * 8, (8, 8, 8), max_atoms=4, max_sigma=1.0)
+    with pytest.raises(H.HartreeError) as ei:
+        plan.splat(torch.zeros((5, 3), dtype=torch.float64, device="cuda"), torch.ones(5), torch.ones(5))
+    assert ei.value.code == 1
+    # a width beyond max_sigma is caught on the device and reported by the status word
+    plan.splat(pos, one, one * 2.0)
+    assert plan.device_status() & H.DEV_SIGMA_RANGE
+    assert plan.device_status() == 0
