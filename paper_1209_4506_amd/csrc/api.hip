@@ -43,34 +43,40 @@ hartree_status hip_fail(hipError_t e, const char *what)
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Stage radices for a length: 8s first (a 2-power remainder of 2 becomes a
-// 4, of 1 becomes 4 x 4 in place of one 8 when possible), then 5, 3 and 7.
+// Stage radices for a length: the fewest stages over the butterfly radices
+// {16, 12, 10, 9, 8, 7, 6, 5, 4, 3, 2}; among those, the smallest largest
+// radix, then the order found first (larger radices first).
+constexpr int kRadices[] = {16, 12, 10, 9, 8, 7, 6, 5, 4, 3, 2};
+
+void factor_search(int m, std::vector<int> &cur, std::vector<int> &best)
+{
+    if (m == 1) {
+        auto maxr = [](const std::vector<int> &v) {
+            int r = 0;
+            for (int x : v) r = x > r ? x : r;
+            return r;
+        };
+        if (best.empty() || cur.size() < best.size() || (cur.size() == best.size() && maxr(cur) < maxr(best)))
+            best = cur;
+        return;
+    }
+    if (!best.empty() && cur.size() + 1 > best.size()) return;
+    for (int r : kRadices) {
+        if (m % r == 0) {
+            cur.push_back(r);
+            factor_search(m / r, cur, best);
+            cur.pop_back();
+        }
+    }
+}
+
 bool factorize(int n, std::vector<int> &r)
 {
     r.clear();
-    int m = n, e2 = 0;
-    while (m % 2 == 0) {
-        m /= 2;
-        ++e2;
-    }
-    int n8 = e2 / 3, rem = e2 % 3;
-    if (rem == 1 && n8 >= 1) {
-        --n8;
-        for (int i = 0; i < n8; ++i) r.push_back(8);
-        r.push_back(4);
-        r.push_back(4);
-    } else {
-        for (int i = 0; i < n8; ++i) r.push_back(8);
-        if (rem == 1) r.push_back(2);
-        if (rem == 2) r.push_back(4);
-    }
-    for (int p : {5, 3, 7}) {
-        while (m % p == 0) {
-            m /= p;
-            r.push_back(p);
-        }
-    }
-    return m == 1 && int(r.size()) <= kMaxStages;
+    if (n == 1) return true;
+    std::vector<int> cur;
+    factor_search(n, cur, r);
+    return !r.empty() && int(r.size()) <= kMaxStages;
 }
 
 // cos and sin of 2 pi t / n with the angle reduced exactly to the first
@@ -99,8 +105,9 @@ void unit_root(long t, long n, double &c, double &s)
 }
 
 struct Launch {
-    int nmax;
-    int maxn;
+    int plan;    // compiled radix plan (index in HARTREE_PLANS) or -1
+    int p_log2;  // pencils per workgroup, log2
+    int maxn;    // longest pencil in the launch (sizes the LDS tile)
     TileList tl;
 };
 
@@ -124,7 +131,8 @@ struct hartree_plan_s {
     std::vector<Launch> lr2c, lb, la;  // P1/P5 (axis c), P2/P4 (axis b), P3 (axis a)
     // workspace layout
     size_t o_status = 0, o_desc = 0, o_tw = 0, o_spec = 0, o_parts = 0, o_qsum = 0, o_info = 0, o_counts = 0,
-           o_offsets = 0, o_cursor = 0, o_list = 0, o_lists = 0, o_bpart = 0, ws_size = 0;
+           o_offsets = 0, o_cursor = 0, o_list = 0, o_lists = 0, o_bpart = 0, o_slot = 0, o_bsum = 0, ws_size = 0;
+    int32_t cap_pa = 0;
     unsigned char *ws = nullptr;
     // profiling: events bracketing each kernel group
     struct ProfRec {
@@ -151,10 +159,10 @@ bool is_smooth(int n)
     return n == 1;
 }
 
-void add_launch(std::vector<Launch> &v, int nmax, int n, int prob, int tiles)
+void add_launch(std::vector<Launch> &v, int plan, int p_log2, int n, int prob, int tiles)
 {
     for (auto &l : v) {
-        if (l.nmax == nmax && l.tl.count < kMaxProb) {
+        if (l.plan == plan && l.p_log2 == p_log2 && l.tl.count < kMaxProb) {
             l.tl.prob[l.tl.count] = prob;
             l.tl.start[l.tl.count + 1] = l.tl.start[l.tl.count] + tiles;
             l.tl.count++;
@@ -165,7 +173,8 @@ void add_launch(std::vector<Launch> &v, int nmax, int n, int prob, int tiles)
     }
     Launch l;
     std::memset(&l, 0, sizeof(l));
-    l.nmax = nmax;
+    l.plan = plan;
+    l.p_log2 = p_log2;
     l.maxn = n;
     l.tl.count = 1;
     l.tl.prob[0] = prob;
@@ -301,8 +310,16 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
         d.L[2] = A[8];
         if (!ortho || A[0] <= 0.0 || A[4] <= 0.0 || A[8] <= 0.0) p->splat_ok = false;
         // pass tiles
-        const int cc = length_class(N[2]), cb = length_class(N[1]), ca = length_class(N[0]);
-        const int pc = pass_pencils(p->fp64, cc), pb = pass_pencils(p->fp64, cb), pa = pass_pencils(p->fp64, ca);
+        int lp[3];
+        for (int x = 0; x < 3; ++x) {
+            lp[x] = pass_p_log2(p->fp64, N[x], d.ax[x].radix, d.ax[x].nstages);
+            if (lp[x] < 0) {
+                delete p;
+                return fail(HARTREE_ERR_DIMS, "problem %d: length %d needs more threads per pencil than a workgroup has",
+                            q, N[x]);
+            }
+        }
+        const int pa = 1 << lp[0], pb = 1 << lp[1], pc = 1 << lp[2];
         const int64_t rows = int64_t(N[0]) * N[1];
         const int64_t t1 = (rows + 2 * pc - 1) / (2 * pc);
         const int64_t t2 = int64_t(N[0]) * ((d.dims[3] + pb - 1) / pb);
@@ -311,9 +328,11 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
             delete p;
             return fail(HARTREE_ERR_DIMS, "problem %d: grid too large", q);
         }
-        add_launch(p->lr2c, cc, N[2], q, int(t1));
-        add_launch(p->lb, cb, N[1], q, int(t2));
-        add_launch(p->la, ca, N[0], q, int(t3));
+        int pl[3];
+        for (int x = 0; x < 3; ++x) pl[x] = find_plan(d.ax[x].radix, d.ax[x].nstages);
+        add_launch(p->lr2c, pl[2], lp[2], N[2], q, int(t1));
+        add_launch(p->lb, pl[1], lp[1], N[1], q, int(t2));
+        add_launch(p->la, pl[0], lp[0], N[0], q, int(t3));
         d.part_off = p->nparts;
         d.nparts = int(t3);
         p->nparts += int(t3);
@@ -340,6 +359,7 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
     p->spec_count = spec;
     p->nbricks = p->splat_ok ? bricks : 0;
     p->capacity = p->splat_ok ? int64_t(p->max_atoms) * cap_per_atom : 0;
+    p->cap_pa = int32_t(cap_per_atom);
     if (p->capacity > int64_t(INT32_MAX)) {
         const int64_t cap = p->capacity;
         delete p;
@@ -368,6 +388,8 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
         p->o_list = take(4 * size_t(p->capacity));
         p->o_lists = take(4 * size_t(p->capacity));
         p->o_bpart = take(24 * size_t(p->capacity));
+        p->o_slot = take(4 * size_t(p->capacity));
+        p->o_bsum = take(8 * size_t(p->nbricks / 4096 + 2));
     }
     p->ws_size = o;
     *out = p;
@@ -440,7 +462,7 @@ hipError_t run_group(hartree_plan p, const std::vector<Launch> &groups, PassKind
     return timed(p, kernel_id(kind), s, [&]() {
         for (const Launch &l : groups) {
             a.tl = l.tl;
-            hipError_t e = run_pass(p->fp64, kind, l.nmax, l.maxn, l.tl.total, s, a);
+            hipError_t e = run_pass(p->fp64, kind, l.plan, l.p_log2, l.maxn, l.tl.total, s, a);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -473,6 +495,9 @@ SplatArgs splat_args(hartree_plan p, int32_t natoms, const double *pos, const do
     a.list = reinterpret_cast<int32_t *>(p->ws + p->o_list);
     a.list_sorted = reinterpret_cast<int32_t *>(p->ws + p->o_lists);
     a.bpart = reinterpret_cast<double *>(p->ws + p->o_bpart);
+    a.slot_of = reinterpret_cast<int32_t *>(p->ws + p->o_slot);
+    a.bsum = reinterpret_cast<int64_t *>(p->ws + p->o_bsum);
+    a.cap_pa = p->cap_pa;
     a.capacity = p->capacity;
     a.nbricks_total = p->nbricks;
     a.status = reinterpret_cast<DeviceStatus *>(p->ws + p->o_status);

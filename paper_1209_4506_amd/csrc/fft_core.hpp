@@ -1,20 +1,33 @@
-// Mixed-radix (2/3/4/5/7/8) Stockham pencil FFT over an LDS tile, for gfx950.
+// Mixed-radix Stockham pencil FFT for gfx950.
 //
-// A workgroup holds P pencils of one axis in LDS as buf[n][P] (the pencil
-// index runs fastest, so a wavefront's lanes touch consecutive words), plus
-// the length-n twiddle table.  Each Stockham stage of radix R reads R
-// elements per butterfly into registers, applies the twiddles and the
-// radix-R DFT in registers, and writes them back in autosorted order; the
-// output of the last stage is in natural order.  TPP threads share a pencil.
+// A workgroup transforms P pencils of one axis.  Between stages the pencils
+// live in LDS as buf[i * PP + p] (element i of pencil p, PP = P + 1: the pitch
+// is padded by one so that both a row of P consecutive pencils and a run of
+// consecutive elements of one pencil fall on distinct banks).  Threads are
+// (p, tip) with p fastest, TPP threads per pencil.
 //
-// Stage s (radix R, Ns = product of the earlier radices), butterfly j < n/R:
+// Stage s has radix R and Ns = product of the earlier radices; butterfly
+// j < n/R of every pencil computes
 //   k = j mod Ns
-//   v_q = x[j + q n/R] * W_{Ns R}^{q k},        q = 0..R-1
+//   v_q = x[j + q n/R] * W_{Ns R}^{q k},                 q = 0 .. R-1
 //   y[(j div Ns) Ns R + k + q Ns] = DFT_R(v)_q
-// with W_m = exp(-2 pi i / m) (forward) or its conjugate (inverse).
+// with W_m = exp(-2 pi i / m) (forward) or its conjugate (inverse); the output
+// of the last stage is in natural order.  The first stage has no twiddles
+// (Ns = 1) and in the last one (Ns = n/R) the output index is j + q Ns.
+//
+// Where the pencils are strided in memory (the b and a axes), the first stage
+// reads its inputs straight from global memory and the last stage writes its
+// outputs straight back: a wavefront then reads or writes whole runs of P
+// consecutive complex values of each grid row, and the tile passes through
+// LDS only between stages.
+//
+// Radices 2, 3, 4, 5, 7 and 8 are written out; 9, 10 and 16 are built as
+// two-level products of those, so most lengths of interest need at most three
+// stages.
 #pragma once
 
 #include "common.hpp"
+#include "radix_consts.hpp"
 
 namespace hartree {
 
@@ -41,38 +54,8 @@ __device__ __forceinline__ Cx<T> rot(Cx<T> a)
     return INV ? Cx<T>{-a.y, a.x} : Cx<T>{a.y, -a.x};
 }
 
-// cos(2 pi t / R) and sin(2 pi t / R) for the odd radices R = 3, 5, 7
-// (literals to 40 digits; the compiler rounds them to T)
-__host__ __device__ constexpr double odd_cos_base(int R, int t)
-{
-    return t == 0 ? 1.0
-         : R == 3 ? -0.5
-         : R == 5 ? (t == 1 ? 0.3090169943749474241022934171828190588611
-                            : -0.8090169943749474241022934171828190588587)
-         : (t == 1 ? 0.6234898018587335305250048840042398106325
-          : t == 2 ? -0.2225209339563144042889025644967947594652
-                   : -0.9009688679024191262361023195074450511656);
-}
-__host__ __device__ constexpr double odd_sin_base(int R, int t)
-{
-    return t == 0 ? 0.0
-         : R == 3 ? 0.8660254037844386467637231707529361834714
-         : R == 5 ? (t == 1 ? 0.9510565162951535721164393333793821434054
-                            : 0.5877852522924731291687059546390727685988)
-         : (t == 1 ? 0.7818314824680298087084445266740577502321
-          : t == 2 ? 0.9749279121818236070181316829939312172330
-                   : 0.4338837391175581204757683328483587546094);
-}
-template <int R>
-__host__ __device__ constexpr double odd_cos(int t)
-{
-    return (t % R) <= R / 2 ? odd_cos_base(R, t % R) : odd_cos_base(R, R - t % R);
-}
-template <int R>
-__host__ __device__ constexpr double odd_sin(int t)
-{
-    return (t % R) <= R / 2 ? odd_sin_base(R, t % R) : -odd_sin_base(R, R - t % R);
-}
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void butterfly(Cx<T> *a);
 
 // Odd prime radix: pair inputs q and R-q.
 //   y_0 = a_0 + sum_k b_k,  b_k = a_k + a_{R-k},  d_k = a_k - a_{R-k}
@@ -98,8 +81,8 @@ __device__ __forceinline__ void dft_odd(Cx<T> *a)
         Cx<T> t = a[0], u = {T(0), T(0)};
 #pragma unroll
         for (int k = 1; k <= H; ++k) {
-            const T c = T(odd_cos<R>(k * m));
-            const T s = T(odd_sin<R>(k * m));
+            const T c = T(unit_cos(R, k * m));
+            const T s = T(unit_sin(R, k * m));
             t.x += c * b[k].x;
             t.y += c * b[k].y;
             u.x += s * d[k].x;
@@ -124,18 +107,55 @@ __device__ __forceinline__ void dft4(Cx<T> &a0, Cx<T> &a1, Cx<T> &a2, Cx<T> &a3)
     a3 = csub(d02, d13);
 }
 
+// Two-level product radix R = A B: with n = B n1 + n2 and k = k1 + A k2,
+//   X[k] = sum_n2 W_B^(n2 k2) [ W_R^(n2 k1) sum_n1 x[B n1 + n2] W_A^(n1 k1) ].
+template <typename T, int A, int B, bool INV>
+__device__ __forceinline__ void dft_product(Cx<T> *x)
+{
+    constexpr int R = A * B;
+    Cx<T> y[R];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) {
+        Cx<T> t[A];
+#pragma unroll
+        for (int n1 = 0; n1 < A; ++n1) t[n1] = x[B * n1 + n2];
+        butterfly<T, A, INV>(t);
+#pragma unroll
+        for (int k1 = 0; k1 < A; ++k1) {
+            const int e = n2 * k1;
+            if (e == 0) {
+                y[k1 * B + n2] = t[k1];
+            } else {
+                const T c = T(unit_cos(R, e));
+                const T s = T(unit_sin(R, e));
+                y[k1 * B + n2] = cmul(t[k1], Cx<T>{c, INV ? s : -s});
+            }
+        }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+        Cx<T> t[B];
+#pragma unroll
+        for (int n2 = 0; n2 < B; ++n2) t[n2] = y[k1 * B + n2];
+        butterfly<T, B, INV>(t);
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) x[k1 + A * k2] = t[k2];
+    }
+}
+
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void butterfly(Cx<T> *a)
 {
-    if constexpr (R == 2) {
+    if constexpr (R == 1) {
+    } else if constexpr (R == 2) {
         Cx<T> t = a[0];
         a[0] = cadd(t, a[1]);
         a[1] = csub(t, a[1]);
     } else if constexpr (R == 4) {
         dft4<T, INV>(a[0], a[1], a[2], a[3]);
     } else if constexpr (R == 8) {
-        // split into pairs 4 apart: e_q = a_q + a_{q+4}, f_q = (a_q - a_{q+4}) W_8^q;
-        // even outputs are DFT4(e), odd outputs DFT4(f)
+        // pairs 4 apart: e_q = a_q + a_{q+4}, f_q = (a_q - a_{q+4}) W_8^q;
+        // even outputs DFT4(e), odd outputs DFT4(f)
         constexpr T h = T(0.7071067811865475244008443621048490392848);
         Cx<T> e[4], f[4];
 #pragma unroll
@@ -143,7 +163,6 @@ __device__ __forceinline__ void butterfly(Cx<T> *a)
             e[q] = cadd(a[q], a[q + 4]);
             f[q] = csub(a[q], a[q + 4]);
         }
-        // W_8 = (h, -h) forward, (h, h) inverse; W_8^2 = rot; W_8^3 = (-h, -h) / (-h, h)
         f[1] = cmul(f[1], Cx<T>{h, INV ? h : -h});
         f[2] = rot<T, INV>(f[2]);
         f[3] = cmul(f[3], Cx<T>{-h, INV ? h : -h});
@@ -154,73 +173,224 @@ __device__ __forceinline__ void butterfly(Cx<T> *a)
             a[2 * m] = e[m];
             a[2 * m + 1] = f[m];
         }
-    } else {
+    } else if constexpr (R == 3 || R == 5 || R == 7) {
         dft_odd<T, R, INV>(a);
+    } else if constexpr (R == 6) {
+        dft_product<T, 2, 3, INV>(a);
+    } else if constexpr (R == 9) {
+        dft_product<T, 3, 3, INV>(a);
+    } else if constexpr (R == 10) {
+        dft_product<T, 2, 5, INV>(a);
+    } else if constexpr (R == 12) {
+        dft_product<T, 4, 3, INV>(a);
+    } else {
+        static_assert(R == 16, "unsupported radix");
+        dft_product<T, 4, 4, INV>(a);
     }
 }
 
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-// One Stockham stage of radix R over buf[n][P]; thread (p, tip).
-template <typename T, int R, int P, int TPP, int MAXB, bool INV>
-__device__ __forceinline__ void stockham_stage(Cx<T> *buf, const Cx<T> *tw, int n, int twstride,
-                                               const FastDiv &nsd, int p, int tip)
+// ------------------------------------------------------------------ access
+// element i of the thread's pencil in the LDS tile
+// An inverse transform runs the forward stages on conjugated data:
+// F^-1 x = conj(F conj x) (unnormalized), so the accessor that feeds the
+// first stage and the one that takes the last stage's output conjugate when
+// cj is set.
+template <typename T>
+struct LdsPencil {
+    static constexpr bool kLds = true;
+    Cx<T> *buf;
+    int pp, p;
+    bool cj;
+    __device__ __forceinline__ Cx<T> load(int i) const
+    {
+        Cx<T> v = buf[i * pp + p];
+        if (cj) v.y = -v.y;
+        return v;
+    }
+    __device__ __forceinline__ void store(int i, Cx<T> v) const
+    {
+        if (cj) v.y = -v.y;
+        buf[i * pp + p] = v;
+    }
+};
+
+// element i of a strided pencil in global memory (zero beyond the tile edge)
+template <typename T>
+struct GlobalPencil {
+    static constexpr bool kLds = false;
+    Cx<T> *ptr;
+    int64_t stride;
+    bool valid;
+    bool cj;
+    __device__ __forceinline__ Cx<T> load(int i) const
+    {
+        Cx<T> v = valid ? ptr[int64_t(i) * stride] : Cx<T>{T(0), T(0)};
+        if (cj) v.y = -v.y;
+        return v;
+    }
+    __device__ __forceinline__ void store(int i, Cx<T> v) const
+    {
+        if (cj) v.y = -v.y;
+        if (valid) ptr[int64_t(i) * stride] = v;
+    }
+};
+
+// Butterflies per thread a stage holds in registers, by radix: a stage keeps
+// at most 32 complex values per thread in float (16 in double).  The host
+// picks the threads per pencil (tpp) so that every stage of a length fits:
+// ceil((n / R) / tpp) <= MAXB(R).
+template <typename T>
+__host__ __device__ constexpr int stage_maxb(int R)
+{
+    return (sizeof(T) == 4 ? 32 : 16) / R > 0 ? (sizeof(T) == 4 ? 32 : 16) / R : 1;
+}
+
+// One Stockham stage.  Src and Dst are pencil accessors; when both are the
+// same tile, SYNC separates all reads from all writes.
+template <typename T, int R, int MAXB, bool FIRST, bool SYNC, typename Src, typename Dst>
+__device__ __forceinline__ void stage(const Src &src, Dst &dst, const Cx<T> *tw, int n, int twstride,
+                                      const FastDiv &nsd, int tip, int tpp)
 {
     const int nb = n / R;
     Cx<T> v[MAXB][R];
 #pragma unroll
     for (int m = 0; m < MAXB; ++m) {
-        const int j = tip + m * TPP;
+        const int j = tip + m * tpp;
         if (j < nb) {
 #pragma unroll
-            for (int q = 0; q < R; ++q) v[m][q] = buf[(j + q * nb) * P + p];
+            for (int q = 0; q < R; ++q) v[m][q] = src.load(j + q * nb);
         }
     }
-    __syncthreads();
+    if (SYNC) __syncthreads();
 #pragma unroll
     for (int m = 0; m < MAXB; ++m) {
-        const int j = tip + m * TPP;
+        const int j = tip + m * tpp;
         if (j < nb) {
-            const int ns = int(nsd.d);
-            const int jd = int(fdiv(uint32_t(j), nsd));
-            const int k = j - jd * ns;
-            const int tstep = k * twstride;
+            int jd = j, k = 0, ns = 1;
+            if (!FIRST) {
+                ns = int(nsd.d);
+                jd = int(fdiv(uint32_t(j), nsd));
+                k = j - jd * ns;
+                const int tstep = k * twstride;
 #pragma unroll
-            for (int q = 1; q < R; ++q) {
-                Cx<T> w = tw[q * tstep];
-                if (INV) w.y = -w.y;
-                v[m][q] = cmul(v[m][q], w);
+                for (int q = 1; q < R; ++q) v[m][q] = cmul(v[m][q], tw[q * tstep]);
             }
-            butterfly<T, R, INV>(v[m]);
+            butterfly<T, R, false>(v[m]);
             const int base = jd * ns * R + k;
 #pragma unroll
-            for (int q = 0; q < R; ++q) buf[(base + q * ns) * P + p] = v[m][q];
+            for (int q = 0; q < R; ++q) dst.store(base + q * ns, v[m][q]);
         }
     }
-    __syncthreads();
 }
 
-// Full transform of the P pencils in buf (length ap.n <= NMAX).  Callers
-// synchronize before the call; the tile is complete on return.
-template <typename T, int NMAX, int P, int TPP, bool INV>
-__device__ __forceinline__ void fft_tile(Cx<T> *buf, const Cx<T> *tw, const AxisPlan &ap, int p, int tip)
+// Dispatch one stage on its runtime radix.
+template <typename T, bool FIRST, bool SYNC, typename Src, typename Dst>
+__device__ __forceinline__ void stage_any(int r, const Src &src, Dst &dst, const Cx<T> *tw, int n, int twstride,
+                                          const FastDiv &nsd, int tip, int tpp)
+{
+#define HARTREE_STAGE(RR) \
+    stage<T, RR, stage_maxb<T>(RR), FIRST, SYNC>(src, dst, tw, n, twstride, nsd, tip, tpp)
+    switch (r) {
+    case 2: HARTREE_STAGE(2); break;
+    case 3: HARTREE_STAGE(3); break;
+    case 4: HARTREE_STAGE(4); break;
+    case 5: HARTREE_STAGE(5); break;
+    case 7: HARTREE_STAGE(7); break;
+    case 8: HARTREE_STAGE(8); break;
+    case 9: HARTREE_STAGE(9); break;
+    case 10: HARTREE_STAGE(10); break;
+    default: HARTREE_STAGE(16); break;
+    }
+#undef HARTREE_STAGE
+}
+
+// Forward transform of a tile whose first stage reads from `src` and whose
+// last stage writes to `dst` (either may be global memory or the LDS tile;
+// conjugating accessors turn it into the inverse); the stages in between run
+// in place on the LDS tile `lds`.  A single-stage length runs its stage into
+// the tile and then copies it to dst.  On return every thread has finished
+// writing; the caller synchronizes before reading the LDS tile.
+template <typename T, typename Src, typename Dst>
+__device__ __forceinline__ void fft_pencils(const Src &src, Dst &dst, const LdsPencil<T> &lds, const Cx<T> *tw,
+                                            const AxisPlan &ap, int tip, int tpp)
 {
     const int n = ap.n;
-    const int ns_count = ap.nstages;
-    for (int s = 0; s < ns_count; ++s) {
-        const int r = ap.radix[s];
-        const int ts = ap.twstride[s];
-        const FastDiv nsd = ap.ns[s];
-        switch (r) {
-        case 2: stockham_stage<T, 2, P, TPP, cdiv(NMAX / 2, TPP), INV>(buf, tw, n, ts, nsd, p, tip); break;
-        case 3: stockham_stage<T, 3, P, TPP, cdiv(NMAX / 3 + 1, TPP), INV>(buf, tw, n, ts, nsd, p, tip); break;
-        case 4: stockham_stage<T, 4, P, TPP, cdiv(NMAX / 4, TPP), INV>(buf, tw, n, ts, nsd, p, tip); break;
-        case 5: stockham_stage<T, 5, P, TPP, cdiv(NMAX / 5 + 1, TPP), INV>(buf, tw, n, ts, nsd, p, tip); break;
-        case 7: stockham_stage<T, 7, P, TPP, cdiv(NMAX / 7 + 1, TPP), INV>(buf, tw, n, ts, nsd, p, tip); break;
-        default: stockham_stage<T, 8, P, TPP, cdiv(NMAX / 8, TPP), INV>(buf, tw, n, ts, nsd, p, tip); break;
+    const int S = ap.nstages;
+    LdsPencil<T> l = lds;
+    l.cj = false;
+    // a stage that writes where the workgroup still reads (the LDS tile)
+    // separates its reads from its writes with a barrier
+    stage_any<T, true, Src::kLds>(ap.radix[0], src, l, tw, n, ap.twstride[0], ap.ns[0], tip, tpp);
+    __syncthreads();
+    if (S == 1) {
+        for (int i = tip; i < n; i += tpp) dst.store(i, l.load(i));
+        return;
+    }
+    for (int s = 1; s + 1 < S; ++s) {
+        stage_any<T, false, true>(ap.radix[s], l, l, tw, n, ap.twstride[s], ap.ns[s], tip, tpp);
+        __syncthreads();
+    }
+    const int s = S - 1;
+    stage_any<T, false, Dst::kLds>(ap.radix[s], l, dst, tw, n, ap.twstride[s], ap.ns[s], tip, tpp);
+}
+
+// The same transform with the stage radices fixed at compile time (R1..R3 = 0
+// for absent stages).  Each stage then gets registers sized for its own
+// radix; a kernel that switches between radices at run time (fft_pencils)
+// must hold registers for the largest case in every stage, which costs
+// occupancy.
+template <typename T, int R0, int R1, int R2, int R3, typename Src, typename Dst>
+__device__ __forceinline__ void fft_static(const Src &src, Dst &dst, const LdsPencil<T> &lds, const Cx<T> *tw,
+                                           const AxisPlan &ap, int tip, int tpp)
+{
+    constexpr int S = (R0 > 0) + (R1 > 0) + (R2 > 0) + (R3 > 0);
+    const int n = ap.n;
+    LdsPencil<T> l = lds;
+    l.cj = false;
+    stage<T, R0, stage_maxb<T>(R0), true, Src::kLds>(src, l, tw, n, ap.twstride[0], ap.ns[0], tip, tpp);
+    __syncthreads();
+    if constexpr (S == 1) {
+        for (int i = tip; i < n; i += tpp) dst.store(i, l.load(i));
+    } else if constexpr (S == 2) {
+        stage<T, R1, stage_maxb<T>(R1), false, Dst::kLds>(l, dst, tw, n, ap.twstride[1], ap.ns[1], tip, tpp);
+    } else {
+        stage<T, R1, stage_maxb<T>(R1), false, true>(l, l, tw, n, ap.twstride[1], ap.ns[1], tip, tpp);
+        __syncthreads();
+        if constexpr (S == 3) {
+            stage<T, R2, stage_maxb<T>(R2), false, Dst::kLds>(l, dst, tw, n, ap.twstride[2], ap.ns[2], tip, tpp);
+        } else {
+            stage<T, R2, stage_maxb<T>(R2), false, true>(l, l, tw, n, ap.twstride[2], ap.ns[2], tip, tpp);
+            __syncthreads();
+            stage<T, R3, stage_maxb<T>(R3), false, Dst::kLds>(l, dst, tw, n, ap.twstride[3], ap.ns[3], tip, tpp);
         }
     }
 }
+
+// Either form: R0 = 0 selects the run-time radix switch.
+template <typename T, int R0, int R1, int R2, int R3, typename Src, typename Dst>
+__device__ __forceinline__ void fft_any(const Src &src, Dst &dst, const LdsPencil<T> &lds, const Cx<T> *tw,
+                                        const AxisPlan &ap, int tip, int tpp)
+{
+    if constexpr (R0 == 0)
+        fft_pencils<T>(src, dst, lds, tw, ap, tip, tpp);
+    else
+        fft_static<T, R0, R1, R2, R3>(src, dst, lds, tw, ap, tip, tpp);
+}
+
+// Radix plans with their own compiled kernels: the stage radices that the
+// plan search picks for common lengths (32, 48, 60, 64, 72, 90, 96, 120, 128,
+// 150, 160, 180, 192, 200, 210, 240, 256, 288, 300, 320, 360, 384, 400, 420,
+// 480, 512, 576, 600, 640, 720, 768, 800, 840, 960, 1024, 2048).  Other
+// lengths run the run-time radix switch.
+#define HARTREE_PLANS(X)                                                                                  \
+    X(8, 4, 0, 0) X(16, 3, 0, 0) X(5, 4, 3, 0) X(8, 8, 0, 0) X(9, 8, 0, 0) X(10, 9, 0, 0) X(8, 4, 3, 0)   \
+    X(8, 5, 3, 0) X(16, 8, 0, 0) X(10, 5, 3, 0) X(16, 10, 0, 0) X(9, 5, 4, 0) X(8, 8, 3, 0)              \
+    X(8, 5, 5, 0) X(10, 7, 3, 0) X(10, 8, 3, 0) X(16, 16, 0, 0) X(9, 8, 4, 0) X(10, 10, 3, 0)            \
+    X(8, 8, 5, 0) X(9, 8, 5, 0) X(16, 8, 3, 0) X(10, 10, 4, 0) X(7, 5, 4, 3) X(16, 10, 3, 0)             \
+    X(8, 8, 8, 0) X(9, 8, 8, 0) X(8, 5, 5, 3) X(10, 8, 8, 0) X(10, 9, 8, 0) X(16, 16, 3, 0)              \
+    X(10, 10, 8, 0) X(8, 7, 5, 3) X(8, 8, 5, 3) X(16, 16, 4, 0) X(16, 16, 8, 0)
 
 // Blocks are dispatched round-robin over the 8 XCDs (each with its own L2);
 // renumber them so that consecutive work items land on the same XCD, where

@@ -1,0 +1,103 @@
+// Host-side dispatch of the grid passes and the E_H finalize kernel.
+#include "fft_passes.hpp"
+
+namespace hartree {
+
+hipError_t run_r2c_f32(int, int, int, hipStream_t, const PassArgs &);
+hipError_t run_r2c_f64(int, int, int, hipStream_t, const PassArgs &);
+hipError_t run_c2r_f32(int, int, int, hipStream_t, const PassArgs &);
+hipError_t run_c2r_f64(int, int, int, hipStream_t, const PassArgs &);
+hipError_t run_b_f32(int, int, int, hipStream_t, const PassArgs &);
+hipError_t run_b_f64(int, int, int, hipStream_t, const PassArgs &);
+hipError_t run_a_f32(int, int, int, hipStream_t, const PassArgs &);
+hipError_t run_a_f64(int, int, int, hipStream_t, const PassArgs &);
+
+// ---------------------------------------------------------------- E_H
+// one workgroup per problem: fixed-order sum of that problem's partials
+__global__ __launch_bounds__(256) void k_finalize(const ProbDesc *desc, const double *partials, double *e_h)
+{
+    __shared__ double red[256];
+    const ProbDesc &d = desc[blockIdx.x];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < d.nparts; i += 256) s += partials[d.part_off + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) e_h[blockIdx.x] = d.eh_scale * red[0];
+}
+
+// Pencils per workgroup for a length and its stage radices (log2; -1 if the
+// length does not fit): enough threads per pencil that every stage's
+// butterflies fit the registers, at most 64 pencils, and a tile that leaves
+// room for two workgroups per CU.
+int pass_p_log2(int fp64, int n, const int *radix, int nstages)
+{
+    int tpp = 1;
+    for (int s = 0; s < nstages; ++s) {
+        const int nb = n / radix[s];
+        const int mb = fp64 ? stage_maxb<double>(radix[s]) : stage_maxb<float>(radix[s]);
+        const int need = (nb + mb - 1) / mb;
+        while (tpp < need) tpp <<= 1;
+    }
+    if (tpp > kPassThreads) return -1;
+    int P = kPassThreads / tpp;
+    if (P > 64) P = 64;
+    const size_t cx = fp64 ? 16 : 8;
+    while (P > 1 && size_t(n) * (P + 1) * cx > 80 * 1024) P >>= 1;
+    int l = 0;
+    while ((1 << l) < P) ++l;
+    return l;
+}
+
+// index of a radix sequence in HARTREE_PLANS, or -1
+int find_plan(const int *radix, int nstages)
+{
+#define HARTREE_ROW(R0, R1, R2, R3) {R0, R1, R2, R3},
+    static const int plans[][4] = {HARTREE_PLANS(HARTREE_ROW)};
+#undef HARTREE_ROW
+    const int np = int(sizeof(plans) / sizeof(plans[0]));
+    for (int i = 0; i < np; ++i) {
+        bool same = true;
+        for (int s = 0; s < 4; ++s) same = same && plans[i][s] == (s < nstages ? radix[s] : 0);
+        if (same && nstages <= 4) return i;
+    }
+    return -1;
+}
+
+hipError_t run_pass(int fp64, PassKind kind, int plan, int p_log2, int maxn, int grid, hipStream_t s,
+                    const PassArgs &a0)
+{
+    PassArgs a = a0;
+    a.mode = 0;
+    a.inv = 0;
+    a.p_log2 = p_log2;
+    switch (kind) {
+    case PASS_R2C_FWD: return fp64 ? run_r2c_f64(plan, maxn, grid, s, a) : run_r2c_f32(plan, maxn, grid, s, a);
+    case PASS_R2C_BWD:
+        a.mode = 1;
+        return fp64 ? run_r2c_f64(plan, maxn, grid, s, a) : run_r2c_f32(plan, maxn, grid, s, a);
+    case PASS_C2R: return fp64 ? run_c2r_f64(plan, maxn, grid, s, a) : run_c2r_f32(plan, maxn, grid, s, a);
+    case PASS_B_FWD: return fp64 ? run_b_f64(plan, maxn, grid, s, a) : run_b_f32(plan, maxn, grid, s, a);
+    case PASS_B_INV:
+        a.inv = 1;
+        return fp64 ? run_b_f64(plan, maxn, grid, s, a) : run_b_f32(plan, maxn, grid, s, a);
+    case PASS_A_FULL: return fp64 ? run_a_f64(plan, maxn, grid, s, a) : run_a_f32(plan, maxn, grid, s, a);
+    case PASS_A_NOENERGY:
+        a.mode = 1;
+        return fp64 ? run_a_f64(plan, maxn, grid, s, a) : run_a_f32(plan, maxn, grid, s, a);
+    default:
+        a.mode = 2;
+        return fp64 ? run_a_f64(plan, maxn, grid, s, a) : run_a_f32(plan, maxn, grid, s, a);
+    }
+}
+
+hipError_t run_finalize(const ProbDesc *desc, const double *partials, double *e_h, int nprob, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(nprob), dim3(256), 0, s, desc, partials, e_h);
+    return hipGetLastError();
+}
+
+}  // namespace hartree

@@ -1,0 +1,361 @@
+// The five grid passes of the Hartree solve and the E_H finalize.
+//
+// Layouts: the real grid is [Na][Nb][Nc] (c fastest); the half spectrum kept
+// in the workspace is [Na][Nb][Nh], Nh = Nc/2 + 1, and is transformed in
+// place.  The passes follow the calculation flow of Sec. 3.2.4 (abc -> cab ->
+// cba -> cab -> abc): on one GPU each change of "local axis" becomes a pass
+// that streams the grid through one workgroup's LDS, transforming pencils
+// along that axis.
+//
+//   P1  r2c along c      real grid -> half spectrum   (two real rows per complex pencil)
+//   P2  FFT along b      in place
+//   P3  FFT along a, x K(G)/N, E_H partials, inverse FFT along a   (fused; in place)
+//   P4  inverse FFT along b
+//   P5  c2r along c      half spectrum -> real grid
+//
+// K(G) = 4 pi / |G|^2 with K(0) = 0 (Eq. (6) in a neutral periodic cell);
+// E_H = Omega / (2 N^2) sum_m w(m_c) K |X|^2, w = 1 on the m_c = 0 and
+// Nyquist planes, 2 elsewhere (the half spectrum stands for both halves).
+#pragma once
+
+#include "fft_core.hpp"
+#include "kernels.hpp"
+
+namespace hartree {
+
+// A workgroup has 256 threads: P pencils (P = 1 << p_log2, chosen by the
+// host per launch) with tpp = 256 / P threads each; the LDS tile holds
+// n (P + 1) complex values.
+constexpr int kPassThreads = 256;
+
+__device__ __forceinline__ void find_item(const TileList &tl, int item, int &prob, int &tile)
+{
+    int i = 0;
+    while (i + 1 < tl.count && item >= tl.start[i + 1]) ++i;
+    prob = tl.prob[i];
+    tile = item - tl.start[i];
+}
+
+template <typename T>
+__device__ __forceinline__ void load_twiddles(Cx<T> *dst, const Cx<T> *src, int n, int tid, int nt)
+{
+    for (int i = tid; i < n; i += nt) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------- P1
+// mode 0: x = rho.  mode 1 (backward): x = grad_v + grad_e * dV * rho.
+template <typename T, int R0, int R1, int R2, int R3>
+__global__ __launch_bounds__(256) void k_r2c(PassArgs a)
+{
+    constexpr int NT = kPassThreads;
+    const int P = 1 << a.p_log2, TPP = NT >> a.p_log2, PP = P + 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    int prob, tile;
+    find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
+    const ProbDesc &d = a.desc[prob];
+    const int n = d.dims[2], nh = d.dims[3];
+    const int64_t nrows = int64_t(d.dims[0]) * d.dims[1];
+    const int64_t row0 = int64_t(tile) * 2 * P;
+    const int rows = int((nrows - row0) < 2 * P ? (nrows - row0) : 2 * P);
+    Cx<T> *buf = reinterpret_cast<Cx<T> *>(smem);
+    Cx<T> *tw = buf + n * PP;
+    const int tid = threadIdx.x;
+    load_twiddles(tw, reinterpret_cast<const Cx<T> *>(a.tw) + d.ax[2].tw_off, n, tid, NT);
+
+    // rows 2q and 2q+1 become the real and imaginary parts of pencil q
+    const int64_t g0 = d.grid_off + row0 * n;
+    const T *src = reinterpret_cast<const T *>(a.in) + g0;
+    const T *rho = reinterpret_cast<const T *>(a.in2) + g0;
+    const int mode = a.mode;
+    T scale = T(0);
+    if (mode == 1 && a.grad_e != nullptr) scale = T(a.grad_e[prob] * d.dv);
+    const int total = rows * n;
+    T *bufr = reinterpret_cast<T *>(buf);
+    for (int e = tid; e < 2 * P * n; e += NT) {
+        const int row = int(fdiv(uint32_t(e), d.div_nc));
+        const int k = e - row * n;
+        T v = T(0);
+        if (e < total) {
+            if (mode == 0) {
+                v = src[e];
+            } else {
+                if (a.in != nullptr) v = src[e];
+                if (a.grad_e != nullptr) v += scale * rho[e];
+            }
+        }
+        bufr[2 * (k * PP + (row >> 1)) + (row & 1)] = v;
+    }
+    __syncthreads();
+    const int p = tid & (P - 1), tip = tid >> a.p_log2;
+    const LdsPencil<T> lp{buf, PP, p, false};
+    if (d.ax[2].nstages > 0) {
+        LdsPencil<T> out = lp;
+        fft_any<T, R0, R1, R2, R3>(lp, out, lp, tw, d.ax[2], tip, TPP);
+        __syncthreads();
+    }
+
+    // X[k] = (Z[k] + conj Z[n-k]) / 2,  Y[k] = (Z[k] - conj Z[n-k]) / (2i)
+    Cx<T> *dst = reinterpret_cast<Cx<T> *>(a.spec) + d.spec_off + row0 * nh;
+    const int totalh = rows * nh;
+    for (int e = tid; e < totalh; e += NT) {
+        const int row = int(fdiv(uint32_t(e), d.div_nh));
+        const int k = e - row * nh;
+        const int q = row >> 1;
+        const Cx<T> A = buf[k * PP + q];
+        const Cx<T> B = buf[(k == 0 ? 0 : n - k) * PP + q];
+        Cx<T> X;
+        if ((row & 1) == 0)
+            X = {T(0.5) * (A.x + B.x), T(0.5) * (A.y - B.y)};
+        else
+            X = {T(0.5) * (A.y + B.y), T(0.5) * (B.x - A.x)};
+        dst[e] = X;
+    }
+}
+
+// ---------------------------------------------------------------- P5
+template <typename T, int R0, int R1, int R2, int R3>
+__global__ __launch_bounds__(256) void k_c2r(PassArgs a)
+{
+    constexpr int NT = kPassThreads;
+    const int P = 1 << a.p_log2, TPP = NT >> a.p_log2, PP = P + 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    int prob, tile;
+    find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
+    const ProbDesc &d = a.desc[prob];
+    const int n = d.dims[2], nh = d.dims[3];
+    const int64_t nrows = int64_t(d.dims[0]) * d.dims[1];
+    const int64_t row0 = int64_t(tile) * 2 * P;
+    const int rows = int((nrows - row0) < 2 * P ? (nrows - row0) : 2 * P);
+    Cx<T> *buf = reinterpret_cast<Cx<T> *>(smem);
+    Cx<T> *tw = buf + n * PP;
+    const int tid = threadIdx.x;
+    load_twiddles(tw, reinterpret_cast<const Cx<T> *>(a.tw) + d.ax[2].tw_off, n, tid, NT);
+
+    // Z[k] = X[k] + i Y[k] over the full length, with X[n-k] = conj X[k]; the
+    // imaginary parts of the k = 0 and Nyquist bins are dropped (they vanish
+    // in exact arithmetic: the inverse of a Hermitian spectrum is real)
+    const Cx<T> *src = reinterpret_cast<const Cx<T> *>(a.spec) + d.spec_off + row0 * nh;
+    for (int e = tid; e < P * n; e += NT) {
+        const int q = int(fdiv(uint32_t(e), d.div_nc));
+        const int k = e - q * n;
+        const bool ve = 2 * q < rows, vo = 2 * q + 1 < rows;
+        const bool mirror = k >= nh;
+        const int kk = mirror ? n - k : k;
+        Cx<T> xe = ve ? src[(2 * q) * nh + kk] : Cx<T>{T(0), T(0)};
+        Cx<T> xo = vo ? src[(2 * q + 1) * nh + kk] : Cx<T>{T(0), T(0)};
+        if (mirror) {
+            xe.y = -xe.y;
+            xo.y = -xo.y;
+        }
+        if (k == 0 || 2 * k == n) {
+            xe.y = T(0);
+            xo.y = T(0);
+        }
+        buf[k * PP + q] = Cx<T>{xe.x - xo.y, xe.y + xo.x};
+    }
+    __syncthreads();
+    const int p = tid & (P - 1), tip = tid >> a.p_log2;
+    const LdsPencil<T> lp{buf, PP, p, true};
+    if (d.ax[2].nstages > 0) {
+        LdsPencil<T> out = lp;
+        fft_any<T, R0, R1, R2, R3>(lp, out, lp, tw, d.ax[2], tip, TPP);
+        __syncthreads();
+    }
+
+    T *dst = reinterpret_cast<T *>(a.out) + d.grid_off + row0 * n;
+    const T *bufr = reinterpret_cast<const T *>(buf);
+    const int total = rows * n;
+    for (int e = tid; e < total; e += NT) {
+        const int row = int(fdiv(uint32_t(e), d.div_nc));
+        const int k = e - row * n;
+        dst[e] = bufr[2 * (k * PP + (row >> 1)) + (row & 1)];
+    }
+}
+
+// ---------------------------------------------------------------- P2 / P4
+// pencils along b: (a, h) for fixed a, P consecutive h per tile; the first
+// stage reads the tile from the spectrum and the last writes it back
+template <typename T, int R0, int R1, int R2, int R3>
+__global__ __launch_bounds__(256) void k_fft_b(PassArgs a)
+{
+    constexpr int NT = kPassThreads;
+    const int P = 1 << a.p_log2, TPP = NT >> a.p_log2, PP = P + 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    int prob, tile;
+    find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
+    const ProbDesc &d = a.desc[prob];
+    const int n = d.dims[1], nh = d.dims[3];
+    if (d.ax[1].nstages == 0) return;  // a length-1 axis: identity
+    const int tpo = (nh + P - 1) / P;
+    const int outer = tile / tpo;
+    const int h0 = (tile - outer * tpo) * P;
+    const int valid = (nh - h0) < P ? (nh - h0) : P;
+    Cx<T> *buf = reinterpret_cast<Cx<T> *>(smem);
+    Cx<T> *tw = buf + n * PP;
+    const int tid = threadIdx.x;
+    load_twiddles(tw, reinterpret_cast<const Cx<T> *>(a.tw) + d.ax[1].tw_off, n, tid, NT);
+    __syncthreads();
+    const int p = tid & (P - 1), tip = tid >> a.p_log2;
+    Cx<T> *g = reinterpret_cast<Cx<T> *>(a.spec) + d.spec_off + int64_t(outer) * n * nh + h0 + p;
+    GlobalPencil<T> gp{g, nh, p < valid, a.inv != 0};
+    const LdsPencil<T> lp{buf, PP, p, false};
+    fft_any<T, R0, R1, R2, R3>(gp, gp, lp, tw, d.ax[1], tip, TPP);
+}
+
+// ---------------------------------------------------------------- P3
+// K for one spectral index; the signed index of an axis is m (2m < N), m - N
+// (2m > N), and at the Nyquist index of an even axis both +N/2 and -N/2 are
+// averaged (no effect on an orthorhombic cell, where |G|^2 is even per axis).
+template <typename T>
+__device__ __forceinline__ T kernel_value(const ProbDesc &d, int ma, int mb, int mc)
+{
+    const int Na = d.dims[0], Nb = d.dims[1], Nc = d.dims[2];
+    const T *B = nullptr;
+    if constexpr (sizeof(T) == 4) B = reinterpret_cast<const T *>(d.Bf);
+    else B = reinterpret_cast<const T *>(d.B);
+    const int sa = (2 * ma < Na) ? ma : ma - Na;
+    const int sb = (2 * mb < Nb) ? mb : mb - Nb;
+    const int sc = mc;
+    const bool nyq = !d.ortho && ((2 * ma == Na) || (2 * mb == Nb) || (2 * mc == Nc));
+    const T fourpi = T(12.566370614359172953850573533118);
+    if (!nyq) {
+        const T ga = T(sa), gb = T(sb), gc = T(sc);
+        const T gx = ga * B[0] + gb * B[3] + gc * B[6];
+        const T gy = ga * B[1] + gb * B[4] + gc * B[7];
+        const T gz = ga * B[2] + gb * B[5] + gc * B[8];
+        const T g2 = gx * gx + gy * gy + gz * gz;
+        return (g2 > T(0)) ? fourpi / g2 : T(0);
+    }
+    // average over the aliases of each Nyquist axis
+    const int na = (2 * ma == Na) ? 2 : 1, nb = (2 * mb == Nb) ? 2 : 1, nc = (2 * mc == Nc) ? 2 : 1;
+    T sum = T(0);
+    for (int i = 0; i < na; ++i)
+        for (int j = 0; j < nb; ++j)
+            for (int k = 0; k < nc; ++k) {
+                const T ga = T(i ? -sa : sa), gb = T(j ? -sb : sb), gc = T(k ? -sc : sc);
+                const T gx = ga * B[0] + gb * B[3] + gc * B[6];
+                const T gy = ga * B[1] + gb * B[4] + gc * B[7];
+                const T gz = ga * B[2] + gb * B[5] + gc * B[8];
+                const T g2 = gx * gx + gy * gy + gz * gz;
+                sum += (g2 > T(0)) ? fourpi / g2 : T(0);
+            }
+    return sum / T(na * nb * nc);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Destination of the last forward stage along a: element m_a of the thread's
+// column is multiplied by K(G)/N on its way into the LDS tile, and (energy)
+// w(m_c) K |X|^2 is accumulated in double.
+template <typename T>
+struct KernelMultiply {
+    static constexpr bool kLds = true;
+    Cx<T> *buf;
+    int pp, p;
+    const ProbDesc *d;
+    int mb, mc;
+    bool energy;
+    T invn;
+    double wgt;
+    double acc;
+    __device__ __forceinline__ void store(int i, Cx<T> v)
+    {
+        const T K = kernel_value<T>(*d, i, mb, mc);
+        if (energy) acc += wgt * double(K * (v.x * v.x + v.y * v.y));
+        buf[i * pp + p] = cscale(v, K * invn);
+    }
+};
+
+// mode 0: forward, energy, multiply, inverse.  mode 1: no energy.
+// mode 2: forward and energy only (no potential).
+// pencils along a: column (b, h) of the flattened [Nb][Nh] plane
+template <typename T, int R0, int R1, int R2, int R3>
+__global__ __launch_bounds__(256) void k_fft_a(PassArgs a)
+{
+    constexpr int NT = kPassThreads;
+    const int P = 1 << a.p_log2, TPP = NT >> a.p_log2, PP = P + 1;
+    const int mode = a.mode;
+    const bool energy = mode != 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[NT / 64];
+    int prob, tile;
+    find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
+    const ProbDesc &d = a.desc[prob];
+    const int n = d.dims[0], nh = d.dims[3], Nc = d.dims[2];
+    const int ncol = d.dims[1] * nh;
+    const int col0 = tile * P;
+    const int valid = (ncol - col0) < P ? (ncol - col0) : P;
+    Cx<T> *buf = reinterpret_cast<Cx<T> *>(smem);
+    Cx<T> *tw = buf + n * PP;
+    const int tid = threadIdx.x;
+    load_twiddles(tw, reinterpret_cast<const Cx<T> *>(a.tw) + d.ax[0].tw_off, n, tid, NT);
+    __syncthreads();
+    const int p = tid & (P - 1), tip = tid >> a.p_log2;
+    const int col = col0 + (p < valid ? p : 0);
+    const int mb = int(fdiv(uint32_t(col), d.div_nh));
+    const int mc = col - mb * nh;
+    Cx<T> *g = reinterpret_cast<Cx<T> *>(a.spec) + d.spec_off + col0 + p;
+    GlobalPencil<T> gp{g, ncol, p < valid, false};
+    const LdsPencil<T> lp{buf, PP, p, false};
+    KernelMultiply<T> km{buf, PP, p, &d, mb, mc, energy && p < valid, T(d.inv_n),
+                         (mc == 0 || 2 * mc == Nc) ? 1.0 : 2.0, 0.0};
+    if (d.ax[0].nstages == 0) {
+        // length-1 axis: the multiply alone
+        if (tip == 0) km.store(0, gp.load(0));
+    } else {
+        fft_any<T, R0, R1, R2, R3>(gp, km, lp, tw, d.ax[0], tip, TPP);
+    }
+    __syncthreads();
+    if (energy) {
+        const double acc = wave_sum(km.acc);
+        if ((tid & 63) == 0) red[tid >> 6] = acc;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+            for (int w = 0; w < NT / 64; ++w) s += red[w];
+            a.partials[d.part_off + tile] = s;
+        }
+    }
+    if (mode == 2) return;
+    // inverse along a: conjugate on the way in and on the way out
+    const LdsPencil<T> lpc{buf, PP, p, true};
+    GlobalPencil<T> gpc{g, ncol, p < valid, true};
+    if (d.ax[0].nstages == 0) {
+        if (tip == 0) gp.store(0, lp.load(0));
+    } else {
+        fft_any<T, R0, R1, R2, R3>(lpc, gpc, lp, tw, d.ax[0], tip, TPP);
+    }
+}
+
+// ------------------------------------------------------------- launchers
+
+template <typename F>
+static hipError_t launch_pass(F kern, int grid, size_t lds, hipStream_t s, const PassArgs &a)
+{
+    if (grid <= 0) return hipSuccess;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+// A launcher runs plan < 0 through the run-time radix kernel and otherwise
+// entry `plan` of HARTREE_PLANS.  The LDS holds the tile and its twiddle
+// table: n (P + 1) + n complex values.
+typedef hipError_t (*PassLaunchFn)(int grid, size_t lds, hipStream_t s, const PassArgs &a);
+
+template <typename T>
+inline size_t pass_lds_bytes(const PassArgs &a, int maxn)
+{
+    return sizeof(Cx<T>) * (size_t((1 << a.p_log2) + 1) * maxn + maxn);
+}
+
+}  // namespace hartree

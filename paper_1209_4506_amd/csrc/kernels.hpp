@@ -33,12 +33,16 @@ struct PassArgs {
     void *out;             // real-grid output of P5
     double *partials;      // E_H partial slots
     const double *grad_e;  // backward: dL/dE_H per problem (nullable)
+    int32_t mode;          // P1: 0 forward, 1 backward;  P3: 0 energy + potential, 1 potential, 2 energy
+    int32_t inv;           // P2/P4: 1 for the inverse transform
+    int32_t p_log2;        // pencils per workgroup, log2
     TileList tl;
 };
 
-int length_class(int n);
-int pass_pencils(int fp64, int nmax);
-hipError_t run_pass(int fp64, PassKind kind, int nmax, int maxn, int grid, hipStream_t s, const PassArgs &a);
+int pass_p_log2(int fp64, int n, const int *radix, int nstages);
+int find_plan(const int *radix, int nstages);
+hipError_t run_pass(int fp64, PassKind kind, int plan, int p_log2, int maxn, int grid, hipStream_t s,
+                    const PassArgs &a);
 hipError_t run_finalize(const ProbDesc *desc, const double *partials, double *e_h, int nprob, hipStream_t s);
 
 // ---------------------------------------------------------------- splat
@@ -59,8 +63,11 @@ struct SplatArgs {
     int32_t *cursor;        // nbricks_total
     int32_t *list;          // capacity
     int32_t *list_sorted;   // capacity
+    int32_t *slot_of;       // max_atoms x cap_pa: sorted-list slot of each (atom, touched brick)
+    int64_t *bsum;          // per scan block: count sums
     double *bpart;          // capacity x 3 (adjoint partials)
     int64_t capacity;
+    int32_t cap_pa;         // most bricks one atom can touch
     int64_t nbricks_total;
     DeviceStatus *status;
     int32_t subtract_background;

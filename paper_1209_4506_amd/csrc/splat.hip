@@ -130,68 +130,133 @@ __global__ __launch_bounds__(256) void k_charge(SplatArgs a, double *qsum)
     if (threadIdx.x == 0) qsum[p] = red[0];
 }
 
-template <int MODE>  // 0: count, 1: fill
-__global__ void k_brick_visit(SplatArgs a)
+// Bricks touched by one atom, enumerated t = 0 .. ntouch-1 in a fixed order:
+// t = (u * ct[1] + v) * ct[2] + w over the circular ranges of the three axes.
+struct Touch {
+    int st[3], ct[3];
+    __device__ int ntouch() const { return ct[0] * ct[1] * ct[2]; }
+};
+
+__device__ __forceinline__ Touch atom_touch(const AtomInfo &in, const ProbDesc &d)
 {
-    const int atom = blockIdx.x * blockDim.x + threadIdx.x;
+    Touch t;
+    const int bsz[3] = {kBI, kBJ, kBK};
+    for (int x = 0; x < 3; ++x) axis_bricks(in.lo[x], in.hi[x], d.dims[x], bsz[x], d.nbricks[x], t.st[x], t.ct[x]);
+    return t;
+}
+
+__device__ __forceinline__ int64_t touch_brick(const Touch &t, const ProbDesc &d, int i)
+{
+    const int w = i % t.ct[2];
+    const int uv = i / t.ct[2];
+    const int v = uv % t.ct[1], u = uv / t.ct[1];
+    const int bi = (t.st[0] + u) % d.nbricks[0];
+    const int bj = (t.st[1] + v) % d.nbricks[1];
+    const int bk = (t.st[2] + w) % d.nbricks[2];
+    return d.brick_off + (int64_t(bi) * d.nbricks[1] + bj) * d.nbricks[2] + bk;
+}
+
+// index t of brick (bi, bj, bk) in the atom's enumeration
+__device__ __forceinline__ int touch_index(const Touch &t, const ProbDesc &d, int64_t lb)
+{
+    const int bk = int(lb % d.nbricks[2]);
+    const int bj = int((lb / d.nbricks[2]) % d.nbricks[1]);
+    const int bi = int(lb / (int64_t(d.nbricks[2]) * d.nbricks[1]));
+    const int u = (bi - t.st[0] + d.nbricks[0]) % d.nbricks[0];
+    const int v = (bj - t.st[1] + d.nbricks[1]) % d.nbricks[1];
+    const int w = (bk - t.st[2] + d.nbricks[2]) % d.nbricks[2];
+    return (u * t.ct[1] + v) * t.ct[2] + w;
+}
+
+// one wavefront per atom, lanes over the bricks it touches
+template <int MODE>  // 0: count, 1: fill
+__global__ __launch_bounds__(256) void k_brick_visit(SplatArgs a)
+{
+    const int atom = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (atom >= a.natoms) return;
     const AtomInfo in = a.info[atom];
     const ProbDesc &d = a.desc[in.prob];
-    const int bsz[3] = {kBI, kBJ, kBK};
-    int st[3], ct[3];
-    for (int x = 0; x < 3; ++x) axis_bricks(in.lo[x], in.hi[x], d.dims[x], bsz[x], d.nbricks[x], st[x], ct[x]);
-    for (int u = 0; u < ct[0]; ++u) {
-        const int bi = (st[0] + u) % d.nbricks[0];
-        for (int v = 0; v < ct[1]; ++v) {
-            const int bj = (st[1] + v) % d.nbricks[1];
-            for (int w = 0; w < ct[2]; ++w) {
-                const int bk = (st[2] + w) % d.nbricks[2];
-                const int64_t b = d.brick_off + (int64_t(bi) * d.nbricks[1] + bj) * d.nbricks[2] + bk;
-                if (MODE == 0) {
-                    atomicAdd(&a.counts[b], 1);
-                } else {
-                    const int slot = atomicAdd(&a.cursor[b], 1);
-                    const int64_t idx = int64_t(a.offsets[b]) + slot;
-                    if (idx < a.capacity) a.list[idx] = atom;
-                }
-            }
+    const Touch t = atom_touch(in, d);
+    const int nt = t.ntouch();
+    for (int i = lane; i < nt; i += 64) {
+        const int64_t b = touch_brick(t, d, i);
+        if (MODE == 0) {
+            atomicAdd(&a.counts[b], 1);
+        } else {
+            const int slot = atomicAdd(&a.cursor[b], 1);
+            const int64_t idx = int64_t(a.offsets[b]) + slot;
+            if (idx < a.capacity) a.list[idx] = atom;
         }
     }
 }
 
-// exclusive scan of counts[0..n) into offsets[0..n]; one workgroup
-__global__ __launch_bounds__(1024) void k_scan(SplatArgs a)
+// exclusive scan of counts[0..n) into offsets[0..n] in three steps over
+// blocks of kScanBlock entries: block sums, then each block scans its own
+// entries after adding the sums of the blocks before it
+constexpr int kScanBlock = 4096;
+
+__global__ __launch_bounds__(256) void k_scan_sums(SplatArgs a)
 {
-    __shared__ int64_t part[1024];
-    const int64_t n = a.nbricks_total;
-    const int t = threadIdx.x;
-    const int64_t per = (n + 1023) / 1024;
-    const int64_t b0 = t * per, b1 = (b0 + per < n) ? b0 + per : n;
+    __shared__ int64_t red[256];
+    const int64_t b0 = int64_t(blockIdx.x) * kScanBlock;
     int64_t s = 0;
-    for (int64_t i = b0; i < b1; ++i) s += a.counts[i];
+    for (int i = threadIdx.x; i < kScanBlock; i += 256) {
+        const int64_t e = b0 + i;
+        if (e < a.nbricks_total) s += a.counts[e];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.bsum[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_scan_blocks(SplatArgs a)
+{
+    __shared__ int64_t part[256];
+    __shared__ int64_t base;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        int64_t s = 0;
+        for (int b = 0; b < int(blockIdx.x); ++b) s += a.bsum[b];
+        base = s;
+    }
+    // each thread owns kScanBlock / 256 = 16 consecutive entries
+    constexpr int PER = kScanBlock / 256;
+    const int64_t e0 = int64_t(blockIdx.x) * kScanBlock + t * PER;
+    int32_t c[PER];
+    int64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        c[i] = (e0 + i < a.nbricks_total) ? a.counts[e0 + i] : 0;
+        s += c[i];
+    }
     part[t] = s;
     __syncthreads();
-    // Hillis-Steele inclusive scan over the 1024 segment sums
-    for (int off = 1; off < 1024; off <<= 1) {
+    for (int off = 1; off < 256; off <<= 1) {
         const int64_t v = (t >= off) ? part[t - off] : 0;
         __syncthreads();
         part[t] += v;
         __syncthreads();
     }
-    int64_t run = part[t] - s;
-    for (int64_t i = b0; i < b1; ++i) {
-        const int64_t c = a.counts[i];
-        a.offsets[i] = int32_t(run < a.capacity ? run : a.capacity);
-        run += c;
+    int64_t run = base + part[t] - s;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        if (e0 + i < a.nbricks_total) a.offsets[e0 + i] = int32_t(run < a.capacity ? run : a.capacity);
+        run += c[i];
     }
-    if (t == 1023) {
-        const int64_t total = part[1023];
-        a.offsets[n] = int32_t(total < a.capacity ? total : a.capacity);
-        if (total > a.capacity) atomicOr(&a.status->bits, 0x4u);
+    if (blockIdx.x == gridDim.x - 1 && t == 255) {
+        a.offsets[a.nbricks_total] = int32_t(run < a.capacity ? run : a.capacity);
+        if (run > a.capacity) atomicOr(&a.status->bits, 0x4u);
     }
 }
 
-// one wavefront per brick: rank every entry (atom indices are distinct)
+// one wavefront per brick: order the list by atom index (indices are
+// distinct, so an entry's rank is the count of smaller ones), and record
+// each entry's final slot under (atom, brick) for the adjoint's reduction
 __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a)
 {
     const int64_t b = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
@@ -199,11 +264,19 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a)
     if (b >= a.nbricks_total) return;
     const int64_t off = a.offsets[b];
     const int cnt = int(a.offsets[b + 1] - off);
+    const int prob = [&] {
+        int p = 0;
+        while (p + 1 < a.nprob && b >= a.desc[p + 1].brick_off) ++p;
+        return p;
+    }();
+    const ProbDesc &d = a.desc[prob];
     for (int e = lane; e < cnt; e += 64) {
         const int v = a.list[off + e];
         int rank = 0;
         for (int j = 0; j < cnt; ++j) rank += (a.list[off + j] < v) ? 1 : 0;
         a.list_sorted[off + rank] = v;
+        const Touch t = atom_touch(a.info[v], d);
+        a.slot_of[int64_t(v) * a.cap_pa + touch_index(t, d, b - d.brick_off)] = int32_t(off + rank);
     }
 }
 
@@ -388,42 +461,39 @@ __global__ __launch_bounds__(kBrickThreads) void k_splat_adjoint(SplatArgs a)
     }
 }
 
-__global__ void k_adjoint_final(SplatArgs a)
+// one wavefront per atom: lanes sum its per-brick partials (slots from the
+// sort) in a fixed order, then a fixed butterfly combines the lanes
+__global__ __launch_bounds__(256) void k_adjoint_final(SplatArgs a)
 {
-    const int atom = blockIdx.x * blockDim.x + threadIdx.x;
+    const int atom = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (atom >= a.natoms) return;
     const AtomInfo in = a.info[atom];
     const ProbDesc &d = a.desc[in.prob];
-    const int bsz[3] = {kBI, kBJ, kBK};
-    int st[3], ct[3];
-    for (int x = 0; x < 3; ++x) axis_bricks(in.lo[x], in.hi[x], d.dims[x], bsz[x], d.nbricks[x], st[x], ct[x]);
-    double f[3] = {0.0, 0.0, 0.0};
-    for (int u = 0; u < ct[0]; ++u) {
-        const int bi = (st[0] + u) % d.nbricks[0];
-        for (int v = 0; v < ct[1]; ++v) {
-            const int bj = (st[1] + v) % d.nbricks[1];
-            for (int w = 0; w < ct[2]; ++w) {
-                const int bk = (st[2] + w) % d.nbricks[2];
-                const int64_t b = d.brick_off + (int64_t(bi) * d.nbricks[1] + bj) * d.nbricks[2] + bk;
-                // binary search for this atom in the brick's sorted list
-                int64_t lo = a.offsets[b], hi = int64_t(a.offsets[b + 1]) - 1;
-                while (lo <= hi) {
-                    const int64_t mid = (lo + hi) >> 1;
-                    const int v2 = a.list_sorted[mid];
-                    if (v2 == atom) {
-                        f[0] += a.bpart[mid * 3 + 0];
-                        f[1] += a.bpart[mid * 3 + 1];
-                        f[2] += a.bpart[mid * 3 + 2];
-                        break;
-                    }
-                    if (v2 < atom) lo = mid + 1;
-                    else hi = mid - 1;
-                }
-            }
+    const Touch t = atom_touch(in, d);
+    const int nt = t.ntouch();
+    double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+    const int32_t *slots = a.slot_of + int64_t(atom) * a.cap_pa;
+    for (int i = lane; i < nt; i += 64) {
+        const int64_t s = slots[i];
+        if (s >= 0 && s < a.capacity) {
+            f0 += a.bpart[s * 3 + 0];
+            f1 += a.bpart[s * 3 + 1];
+            f2 += a.bpart[s * 3 + 2];
         }
     }
-    const double scale = in.w * 2.0 * in.inv2s2;  // Z (2 pi s^2)^(-3/2) / s^2
-    for (int x = 0; x < 3; ++x) a.grad_pos[3 * atom + x] = scale * f[x];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        f0 += __shfl_xor(f0, off, 64);
+        f1 += __shfl_xor(f1, off, 64);
+        f2 += __shfl_xor(f2, off, 64);
+    }
+    if (lane == 0) {
+        const double scale = in.w * 2.0 * in.inv2s2;  // Z (2 pi s^2)^(-3/2) / s^2
+        a.grad_pos[3 * atom + 0] = scale * f0;
+        a.grad_pos[3 * atom + 1] = scale * f1;
+        a.grad_pos[3 * atom + 2] = scale * f2;
+    }
 }
 
 // ------------------------------------------------------------- host side
@@ -435,12 +505,15 @@ hipError_t run_bin(const SplatArgs &a, hipStream_t s)
     hipLaunchKernelGGL(k_fill_i32, dim3(1024), dim3(256), 0, s, a.counts, nbt + 1, 0);
     hipLaunchKernelGGL(k_fill_i32, dim3(1024), dim3(256), 0, s, a.cursor, nbt, 0);
     hipLaunchKernelGGL(k_charge, dim3(a.nprob), dim3(256), 0, s, a, a.qsum);
+    const int nw = int((a.natoms + 3) / 4);  // one wavefront per atom
+    const int nsb = int((nbt + kScanBlock - 1) / kScanBlock);
     if (a.natoms > 0) {
         hipLaunchKernelGGL(k_atom_prep, dim3(nb), dim3(256), 0, s, a);
-        hipLaunchKernelGGL(k_brick_visit<0>, dim3(nb), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_brick_visit<0>, dim3(nw), dim3(256), 0, s, a);
     }
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
-    if (a.natoms > 0) hipLaunchKernelGGL(k_brick_visit<1>, dim3(nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_scan_sums, dim3(nsb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(nsb), dim3(256), 0, s, a);
+    if (a.natoms > 0) hipLaunchKernelGGL(k_brick_visit<1>, dim3(nw), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_brick_sort, dim3(int((nbt + 3) / 4)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
@@ -465,8 +538,7 @@ hipError_t run_adjoint(const SplatArgs &a, hipStream_t s)
 
 hipError_t run_adjoint_final(const SplatArgs &a, hipStream_t s)
 {
-    if (a.natoms > 0)
-        hipLaunchKernelGGL(k_adjoint_final, dim3(int((a.natoms + 255) / 256)), dim3(256), 0, s, a);
+    if (a.natoms > 0) hipLaunchKernelGGL(k_adjoint_final, dim3(int((a.natoms + 3) / 4)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
