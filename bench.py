@@ -36,7 +36,23 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-atoms", type=int, default=512, help="atoms in the CPU-oracle sample")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (to calibrate HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration(torch):
+    """Three device-to-device copies of 512 MiB each: the reference a byte
+    counter (FETCH_SIZE, WRITE_SIZE) is scaled by."""
+    n = 128 * 1024 * 1024
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n,
+                      "launches": 3}), flush=True)
 
 
 def source_hash():
@@ -163,6 +179,10 @@ def main():
               "design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
+
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
 
     import paper_1209_4506_amd.hartree as H
     from paper_1209_4506_amd import inputs

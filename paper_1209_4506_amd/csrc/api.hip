@@ -44,39 +44,47 @@ hartree_status hip_fail(hipError_t e, const char *what)
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Stage radices for a length: the fewest stages over the butterfly radices
-// {16, 12, 10, 9, 8, 7, 6, 5, 4, 3, 2}; among those, the smallest largest
-// radix, then the order found first (larger radices first).
-constexpr int kRadices[] = {16, 12, 10, 9, 8, 7, 6, 5, 4, 3, 2};
+// the kernels implement, {16, 10, 9, 8, 7, 5, 4, 3, 2}; among those, the
+// smallest largest radix, then the order found first (larger radices first).
+constexpr int kRadices[] = {16, 10, 9, 8, 7, 5, 4, 3, 2};
 
-void factor_search(int m, std::vector<int> &cur, std::vector<int> &best)
+// a plan fits when every stage's butterflies fit one workgroup's registers
+bool plan_fits(int n, int fp64, const std::vector<int> &r)
+{
+    return pass_p_log2(fp64, n, r.data(), int(r.size())) >= 0;
+}
+
+void factor_search(int n, int m, int fp64, std::vector<int> &cur, std::vector<int> &best)
 {
     if (m == 1) {
         auto maxr = [](const std::vector<int> &v) {
-            int r = 0;
-            for (int x : v) r = x > r ? x : r;
-            return r;
+            int x = 0;
+            for (int y : v) x = y > x ? y : x;
+            return x;
         };
+        if (!plan_fits(n, fp64, cur)) return;
         if (best.empty() || cur.size() < best.size() || (cur.size() == best.size() && maxr(cur) < maxr(best)))
             best = cur;
         return;
     }
     if (!best.empty() && cur.size() + 1 > best.size()) return;
+    if (int(cur.size()) >= kMaxStages) return;
     for (int r : kRadices) {
         if (m % r == 0) {
             cur.push_back(r);
-            factor_search(m / r, cur, best);
+            factor_search(n, m / r, fp64, cur, best);
             cur.pop_back();
         }
     }
 }
 
-bool factorize(int n, std::vector<int> &r)
+bool factorize(int n, int fp64, std::vector<int> &r)
 {
     r.clear();
     if (n == 1) return true;
     std::vector<int> cur;
-    factor_search(n, cur, r);
-    return !r.empty() && int(r.size()) <= kMaxStages;
+    factor_search(n, n, fp64, cur, r);
+    return !r.empty();
 }
 
 // cos and sin of 2 pi t / n with the angle reduced exactly to the first
@@ -244,7 +252,7 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
             const int n = N[x];
             AxisPlan &ap = d.ax[x];
             std::vector<int> rad;
-            if (!factorize(n, rad)) {
+            if (!factorize(n, p->fp64, rad)) {
                 delete p;
                 return fail(HARTREE_ERR_DIMS, "problem %d: cannot factor %d", q, n);
             }

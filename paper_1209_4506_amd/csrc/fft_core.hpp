@@ -238,13 +238,14 @@ struct GlobalPencil {
 };
 
 // Butterflies per thread a stage holds in registers, by radix: a stage keeps
-// at most 32 complex values per thread in float (16 in double).  The host
+// at most 32 complex values per thread in float (21 in double, enough for
+// every 7-smooth length up to 4096 at 256 threads per pencil).  The host
 // picks the threads per pencil (tpp) so that every stage of a length fits:
 // ceil((n / R) / tpp) <= MAXB(R).
 template <typename T>
 __host__ __device__ constexpr int stage_maxb(int R)
 {
-    return (sizeof(T) == 4 ? 32 : 16) / R > 0 ? (sizeof(T) == 4 ? 32 : 16) / R : 1;
+    return (sizeof(T) == 4 ? 32 : 21) / R > 0 ? (sizeof(T) == 4 ? 32 : 21) / R : 1;
 }
 
 // One Stockham stage.  Src and Dst are pencil accessors; when both are the
@@ -301,7 +302,8 @@ __device__ __forceinline__ void stage_any(int r, const Src &src, Dst &dst, const
     case 8: HARTREE_STAGE(8); break;
     case 9: HARTREE_STAGE(9); break;
     case 10: HARTREE_STAGE(10); break;
-    default: HARTREE_STAGE(16); break;
+    case 16: HARTREE_STAGE(16); break;
+    default: break;  // not produced by the plan search
     }
 #undef HARTREE_STAGE
 }

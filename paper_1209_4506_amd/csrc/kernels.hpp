@@ -82,5 +82,7 @@ hipError_t run_bin(const SplatArgs &a, hipStream_t s);
 hipError_t run_gather(const SplatArgs &a, hipStream_t s);
 hipError_t run_adjoint(const SplatArgs &a, hipStream_t s);
 hipError_t run_adjoint_final(const SplatArgs &a, hipStream_t s);
+hipError_t run_gather_mfma(const SplatArgs &a, hipStream_t s);
+hipError_t run_adjoint_mfma(const SplatArgs &a, hipStream_t s);
 
 }  // namespace hartree

@@ -21,47 +21,9 @@
 //   gather  per brick: rho = sum over its atoms of w gx(i) gy(j) gz(k) [- Q/Omega]
 //   adjoint per brick: partial sum_r grad_rho(r) g(r) d(r) for each of its atoms
 //   final   per atom: fixed-order sum of its partials over the touched bricks
-#include "fft_core.hpp"
-#include "kernels.hpp"
+#include "splat_common.hpp"
 
 namespace hartree {
-
-constexpr int kChunk = 32;  // atoms staged in LDS at a time
-
-__device__ __forceinline__ int find_prob_atom(const SplatArgs &a, int atom)
-{
-    int p = 0;
-    while (p + 1 < a.nprob && atom >= a.atom_off[p + 1]) ++p;
-    return p;
-}
-
-__device__ __forceinline__ int wrapi(int i, int n)
-{
-    int r = i % n;
-    return r < 0 ? r + n : r;
-}
-
-// bricks touched along one axis: circular range [start, start + count) mod nb
-__device__ __forceinline__ void axis_bricks(int lo, int hi, int n, int bsz, int nb, int &start, int &count)
-{
-    if (hi < lo) {  // invalid atom: touches nothing
-        start = 0;
-        count = 0;
-        return;
-    }
-    if (hi - lo + 1 >= n) {
-        start = 0;
-        count = nb;
-        return;
-    }
-    const int s = wrapi(lo, n), e = wrapi(hi, n);
-    const int bs = s / bsz, be = e / bsz;
-    start = bs;
-    if (s <= e)
-        count = be - bs + 1;
-    else
-        count = (be >= bs) ? nb : (nb - bs) + be + 1;
-}
 
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
 {
@@ -280,42 +242,10 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a)
     }
 }
 
-__device__ __forceinline__ int brick_prob(const SplatArgs &a, int64_t b)
-{
-    int p = 0;
-    while (p + 1 < a.nprob && b >= a.desc[p + 1].brick_off) ++p;
-    return p;
-}
-
-template <typename T>
-__device__ __forceinline__ T expT(T x);
-template <>
-__device__ __forceinline__ float expT<float>(float x) { return expf(x); }
-template <>
-__device__ __forceinline__ double expT<double>(double x) { return exp(x); }
-
-// 1-D periodic Gaussian factor along one axis at wrapped index ig:
-// g = sum over unwrapped i' = ig (mod n) in [lo, hi] of exp(-(i' h - X)^2 / (2 s^2)),
-// gd = the same sum weighted by the displacement (i' h - X).  The exponent is
-// formed in double (positions near L lose digits in float) and evaluated in T.
-template <typename T, bool WITH_D>
-__device__ __forceinline__ void axis_factor_t(int ig, int n, double h, double X, int lo, int hi, double inv2s2, T &g,
-                                              T &gd)
-{
-    g = T(0);
-    gd = T(0);
-    if (hi < lo || ig >= n) return;
-    for (int ip = lo + wrapi(ig - lo, n); ip <= hi; ip += n) {
-        const double dd = double(ip) * h - X;
-        const T e = expT<T>(T(-dd * dd * inv2s2));
-        g += e;
-        if (WITH_D) gd += e * T(dd);
-    }
-}
-
 template <typename T>
 __global__ __launch_bounds__(kBrickThreads) void k_splat_gather(SplatArgs a, const double *qsum)
 {
+    __shared__ StagedAtom atoms[kChunk];
     __shared__ T gx[kChunk][kBI], gy[kChunk][kBJ];
     __shared__ __align__(16) T gz[kChunk][kBK];
     const int64_t b = blockIdx.x;
@@ -339,20 +269,22 @@ __global__ __launch_bounds__(kBrickThreads) void k_splat_gather(SplatArgs a, con
     for (int c0 = 0; c0 < cnt; c0 += kChunk) {
         const int nc = (cnt - c0) < kChunk ? (cnt - c0) : kChunk;
         // tables: per atom 8 + 8 + 32 entries
+        stage_atoms(atoms, a, d, off, c0, nc, t);
+        __syncthreads();
         for (int e = t; e < nc * (kBI + kBJ + kBK); e += kBrickThreads) {
             const int s = e / (kBI + kBJ + kBK), q = e % (kBI + kBJ + kBK);
-            const AtomInfo in = a.info[a.list_sorted[off + c0 + s]];
+            const StagedAtom &in = atoms[s];
             T g, gd;
             if (q < kBI) {
-                axis_factor_t<T, false>(bi * kBI + q, d.dims[0], h[0], in.X[0], in.lo[0], in.hi[0], in.inv2s2, g, gd);
+                staged_factor<T, false>(bi * kBI + q, d.dims[0], h[0], in, 0, g, gd);
                 gx[s][q] = g * T(in.w);
             } else if (q < kBI + kBJ) {
                 const int qq = q - kBI;
-                axis_factor_t<T, false>(bj * kBJ + qq, d.dims[1], h[1], in.X[1], in.lo[1], in.hi[1], in.inv2s2, g, gd);
+                staged_factor<T, false>(bj * kBJ + qq, d.dims[1], h[1], in, 1, g, gd);
                 gy[s][qq] = g;
             } else {
                 const int qq = q - kBI - kBJ;
-                axis_factor_t<T, false>(bk * kBK + qq, d.dims[2], h[2], in.X[2], in.lo[2], in.hi[2], in.inv2s2, g, gd);
+                staged_factor<T, false>(bk * kBK + qq, d.dims[2], h[2], in, 2, g, gd);
                 gz[s][qq] = g;
             }
         }
@@ -383,6 +315,7 @@ __device__ __forceinline__ T wave_sum_t(T v)
 template <typename T>
 __global__ __launch_bounds__(kBrickThreads) void k_splat_adjoint(SplatArgs a)
 {
+    __shared__ StagedAtom atoms[kChunk];
     __shared__ T gx[kChunk][kBI], gdx[kChunk][kBI], gy[kChunk][kBJ], gdy[kChunk][kBJ];
     __shared__ __align__(16) T gz[kChunk][kBK];
     __shared__ __align__(16) T gdz[kChunk][kBK];
@@ -413,22 +346,24 @@ __global__ __launch_bounds__(kBrickThreads) void k_splat_adjoint(SplatArgs a)
 
     for (int c0 = 0; c0 < cnt; c0 += kChunk) {
         const int nc = (cnt - c0) < kChunk ? (cnt - c0) : kChunk;
+        stage_atoms(atoms, a, d, off, c0, nc, t);
+        __syncthreads();
         for (int e = t; e < nc * (kBI + kBJ + kBK); e += kBrickThreads) {
             const int s = e / (kBI + kBJ + kBK), q = e % (kBI + kBJ + kBK);
-            const AtomInfo in = a.info[a.list_sorted[off + c0 + s]];
+            const StagedAtom &in = atoms[s];
             T g, gd;
             if (q < kBI) {
-                axis_factor_t<T, true>(bi * kBI + q, d.dims[0], h[0], in.X[0], in.lo[0], in.hi[0], in.inv2s2, g, gd);
+                staged_factor<T, true>(bi * kBI + q, d.dims[0], h[0], in, 0, g, gd);
                 gx[s][q] = g;
                 gdx[s][q] = gd;
             } else if (q < kBI + kBJ) {
                 const int qq = q - kBI;
-                axis_factor_t<T, true>(bj * kBJ + qq, d.dims[1], h[1], in.X[1], in.lo[1], in.hi[1], in.inv2s2, g, gd);
+                staged_factor<T, true>(bj * kBJ + qq, d.dims[1], h[1], in, 1, g, gd);
                 gy[s][qq] = g;
                 gdy[s][qq] = gd;
             } else {
                 const int qq = q - kBI - kBJ;
-                axis_factor_t<T, true>(bk * kBK + qq, d.dims[2], h[2], in.X[2], in.lo[2], in.hi[2], in.inv2s2, g, gd);
+                staged_factor<T, true>(bk * kBK + qq, d.dims[2], h[2], in, 2, g, gd);
                 gz[s][qq] = g;
                 gdz[s][qq] = gd;
             }
@@ -518,21 +453,18 @@ hipError_t run_bin(const SplatArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// FP32 runs on the matrix cores (splat_mfma.hip); FP64 on the vector units
 hipError_t run_gather(const SplatArgs &a, hipStream_t s)
 {
-    if (a.fp64)
-        hipLaunchKernelGGL(k_splat_gather<double>, dim3(int(a.nbricks_total)), dim3(kBrickThreads), 0, s, a, a.qsum);
-    else
-        hipLaunchKernelGGL(k_splat_gather<float>, dim3(int(a.nbricks_total)), dim3(kBrickThreads), 0, s, a, a.qsum);
+    if (!a.fp64) return run_gather_mfma(a, s);
+    hipLaunchKernelGGL(k_splat_gather<double>, dim3(int(a.nbricks_total)), dim3(kBrickThreads), 0, s, a, a.qsum);
     return hipGetLastError();
 }
 
 hipError_t run_adjoint(const SplatArgs &a, hipStream_t s)
 {
-    if (a.fp64)
-        hipLaunchKernelGGL(k_splat_adjoint<double>, dim3(int(a.nbricks_total)), dim3(kBrickThreads), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_splat_adjoint<float>, dim3(int(a.nbricks_total)), dim3(kBrickThreads), 0, s, a);
+    if (!a.fp64) return run_adjoint_mfma(a, s);
+    hipLaunchKernelGGL(k_splat_adjoint<double>, dim3(int(a.nbricks_total)), dim3(kBrickThreads), 0, s, a);
     return hipGetLastError();
 }
 

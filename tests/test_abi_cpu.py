@@ -99,3 +99,30 @@ def test_batched_plan_offsets(lib):
     assert lib.hartree_plan_grid_offset(h, len(probs) + 1, ctypes.byref(off)) == 1
     lib.hartree_plan_destroy.argtypes = [vp]
     lib.hartree_plan_destroy(h)
+
+
+def _smooth(limit):
+    out = []
+    for n in range(1, limit + 1):
+        m = n
+        for p in (2, 3, 5, 7):
+            while m % p == 0:
+                m //= p
+        if m == 1:
+            out.append(n)
+    return out
+
+
+def test_every_smooth_length_gets_a_plan(lib):
+    """Every 7-smooth axis length up to 4096 has a stage plan that fits the
+    kernels, in both precisions; other lengths are refused."""
+    vp = ctypes.c_void_p
+    lib.hartree_plan_destroy.argtypes = [vp]
+    cube = np.eye(3) * 10
+    for prec in (0, 1):
+        for n in _smooth(4096):
+            rc, h = _create(lib, cube, (n, 1, 1), prec=prec)
+            assert rc == 0, (n, prec, lib.hartree_last_error())
+            lib.hartree_plan_destroy(h)
+    for n in (11, 13, 22, 4097, 4099):
+        assert _create(lib, cube, (1, n, 1))[0] == 2
