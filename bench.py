@@ -2,6 +2,7 @@
 """Hartree solves/sec on one MI355X: the 360^3 diamond workload, FP32 fwd+bwd.
 
 One step (one "solve") is the whole hot path on one batch of synthetic input:
+  bin        atoms into bricks (once, shared by splat and adjoint)
   splat      rho = sum of 4096 Gaussians (Z = 4, sigma = 0.8 Bohr) - Q/Omega
   solve      V = P rho, E_H                         (P1 .. P5 + E_H finalize)
   backward   grad_rho = P (c dV + 1 * dV * rho)     (loss L = E_H + <c, V> dV)
@@ -87,10 +88,11 @@ class Step:
 
     def __call__(self):
         p = self.plan
-        p.splat(self.pos, self.Z, self.sig, out=self.rho)
+        token = p.bind_atoms(self.pos, self.Z, self.sig)   # binning shared by splat and adjoint
+        p.splat_bound(token, out=self.rho)
         p.solve(self.rho, v=self.V, e_h=self.E)
         p.backward(grad_v=self.gv, grad_e=self.ge, rho=self.rho, out=self.grho)
-        p.splat_adjoint(self.pos, self.Z, self.sig, self.grho, out=self.gpos)
+        p.splat_adjoint_bound(token, self.grho, out=self.gpos)
 
     def timed(self, steps, warmup, profile=False):
         torch = self.torch

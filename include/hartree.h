@@ -190,6 +190,25 @@ typedef enum {
 hartree_status hartree_profile_begin(hartree_plan plan);
 hartree_status hartree_profile_end(hartree_plan plan, double *total_ms, int64_t *launches);
 
+/* Atom binning shared by a splat and its adjoint.  hartree_splat and
+ * hartree_splat_adjoint each bin their atoms into bricks of the grid (sorted
+ * per-brick lists and per-atom 1-D factor tables in the workspace) before
+ * their main kernels.  When both run on the same atoms -- a forward splat and
+ * the backward pass of the same positions -- the binning can be done once:
+ *   hartree_atoms_bind  bins the atoms (same arguments as hartree_splat) and
+ *                       returns a token (host out) naming this binding;
+ *   hartree_splat_bound / hartree_splat_adjoint_bound  run on the binding
+ *                       named by the token, and return HARTREE_ERR_ARG when
+ *                       the workspace has been rebound since (any bind, or an
+ *                       unbound splat or adjoint call, replaces the binding).
+ * The atom arrays must not change on the device while a binding is used. */
+hartree_status hartree_atoms_bind(hartree_plan plan, int32_t natoms, const double *pos, const double *Z,
+                                  const double *sigma, const int32_t *atom_offsets, uint64_t *token, void *stream);
+hartree_status hartree_splat_bound(hartree_plan plan, uint64_t token, void *rho_out, int32_t subtract_background,
+                                   void *stream);
+hartree_status hartree_splat_adjoint_bound(hartree_plan plan, uint64_t token, const void *grad_rho, double *grad_pos,
+                                           void *stream);
+
 /* Read (synchronously) and clear the device status word (HARTREE_DEV_* bits). */
 hartree_status hartree_device_status(hartree_plan plan, uint32_t *bits, void *stream);
 

@@ -51,7 +51,7 @@ constexpr int kRadices[] = {16, 10, 9, 8, 7, 5, 4, 3, 2};
 // a plan fits when every stage's butterflies fit one workgroup's registers
 bool plan_fits(int n, int fp64, const std::vector<int> &r)
 {
-    return pass_p_log2(fp64, n, r.data(), int(r.size())) >= 0;
+    return pass_p_log2(fp64, n, r.data(), int(r.size()), 64) >= 0;
 }
 
 void factor_search(int n, int m, int fp64, std::vector<int> &cur, std::vector<int> &best)
@@ -139,8 +139,10 @@ struct hartree_plan_s {
     std::vector<Launch> lr2c, lb, la;  // P1/P5 (axis c), P2/P4 (axis b), P3 (axis a)
     // workspace layout
     size_t o_status = 0, o_desc = 0, o_tw = 0, o_spec = 0, o_parts = 0, o_qsum = 0, o_info = 0, o_counts = 0,
-           o_offsets = 0, o_cursor = 0, o_list = 0, o_lists = 0, o_bpart = 0, o_slot = 0, o_bsum = 0, ws_size = 0;
+           o_offsets = 0, o_cursor = 0, o_list = 0, o_lists = 0, o_bpart = 0, o_slot = 0, o_bsum = 0, o_tab = 0,
+           ws_size = 0;
     int32_t cap_pa = 0;
+    int32_t wcap = 0;  // per-atom factor table row length
     unsigned char *ws = nullptr;
     // profiling: events bracketing each kernel group
     struct ProfRec {
@@ -151,6 +153,12 @@ struct hartree_plan_s {
     std::vector<hipEvent_t> pool;
     size_t pool_used = 0;
     std::vector<ProfRec> recs;
+    // current atom binding (hartree_atoms_bind)
+    uint64_t bind_token = 0;
+    bool bound = false;
+    int32_t bound_natoms = 0;
+    const double *bound_pos = nullptr, *bound_Z = nullptr, *bound_sigma = nullptr;
+    std::vector<int32_t> bound_offsets;
     ~hartree_plan_s()
     {
         for (hipEvent_t e : pool) (void)hipEventDestroy(e);
@@ -221,6 +229,7 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
     p->splat_ok = true;
     int64_t grid = 0, spec = 0, bricks = 0;
     int64_t cap_per_atom = 0;
+    int64_t wcap = 1;
     for (int q = 0; q < nprob; ++q) {
         const double *A = cells + 9 * q;
         const int32_t *N = dims + 3 * q;
@@ -320,7 +329,9 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
         // pass tiles
         int lp[3];
         for (int x = 0; x < 3; ++x) {
-            lp[x] = pass_p_log2(p->fp64, N[x], d.ax[x].radix, d.ax[x].nstages);
+            // strided axes (a, b): up to 64 pencils side by side; the c axis:
+            // at most 16 pencils, so at least 16 threads run along each one
+            lp[x] = pass_p_log2(p->fp64, N[x], d.ax[x].radix, d.ax[x].nstages, x == 2 ? 16 : 64);
             if (lp[x] < 0) {
                 delete p;
                 return fail(HARTREE_ERR_DIMS, "problem %d: length %d needs more threads per pencil than a workgroup has",
@@ -351,6 +362,9 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
             d.nbricks[x] = (N[x] + bsz[x] - 1) / bsz[x];
             const double h = std::fabs(A[4 * x]) / N[x];
             const double w = std::floor(2.0 * p->cutoff * p->max_sigma / (h > 0 ? h : 1.0)) + 1.0;
+            // factor table row: the window width, or the whole axis when it wraps
+            const int64_t row = w < N[x] ? int64_t(w) : int64_t(N[x]);
+            if (row > wcap) wcap = row;
             int64_t nbx = d.nbricks[x];
             if (w < N[x]) {
                 const int64_t bnd = int64_t(std::ceil((w - 1.0) / bsz[x])) + 2;
@@ -368,6 +382,7 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
     p->nbricks = p->splat_ok ? bricks : 0;
     p->capacity = p->splat_ok ? int64_t(p->max_atoms) * cap_per_atom : 0;
     p->cap_pa = int32_t(cap_per_atom);
+    p->wcap = int32_t(wcap);
     if (p->capacity > int64_t(INT32_MAX)) {
         const int64_t cap = p->capacity;
         delete p;
@@ -397,6 +412,7 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
         p->o_lists = take(4 * size_t(p->capacity));
         p->o_bpart = take(24 * size_t(p->capacity));
         p->o_slot = take(4 * size_t(p->capacity));
+        p->o_tab = take(2 * (p->fp64 ? 8 : 4) * size_t(p->max_atoms) * 3 * size_t(p->wcap));
         p->o_bsum = take(8 * size_t(p->nbricks / 4096 + 2));
     }
     p->ws_size = o;
@@ -506,6 +522,8 @@ SplatArgs splat_args(hartree_plan p, int32_t natoms, const double *pos, const do
     a.slot_of = reinterpret_cast<int32_t *>(p->ws + p->o_slot);
     a.bsum = reinterpret_cast<int64_t *>(p->ws + p->o_bsum);
     a.cap_pa = p->cap_pa;
+    a.tab = p->ws + p->o_tab;
+    a.wcap = p->wcap;
     a.capacity = p->capacity;
     a.nbricks_total = p->nbricks;
     a.status = reinterpret_cast<DeviceStatus *>(p->ws + p->o_status);
@@ -662,6 +680,11 @@ hartree_status hartree_backward(hartree_plan plan, const void *grad_v, const dou
     a.grad_e = grad_e;
     a.out = grad_rho;
     hipError_t e;
+    if (!grad_v && !grad_e) {  // no upstream gradient: the result is zero
+        if ((e = run_zero(grad_rho, size_t(plan->grid_total) * (plan->fp64 ? 8 : 4), s)) != hipSuccess)
+            return hip_fail(e, "zeroing grad_rho");
+        return ok();
+    }
     if ((e = run_group(plan, plan->lr2c, PASS_R2C_BWD, a, s)) != hipSuccess) return hip_fail(e, "P1");
     if ((e = run_group(plan, plan->lb, PASS_B_FWD, a, s)) != hipSuccess) return hip_fail(e, "P2");
     if ((e = run_group(plan, plan->la, PASS_A_NOENERGY, a, s)) != hipSuccess) return hip_fail(e, "P3");
@@ -670,44 +693,94 @@ hartree_status hartree_backward(hartree_plan plan, const void *grad_v, const dou
     return ok();
 }
 
-hartree_status hartree_splat(hartree_plan plan, int32_t natoms, const double *pos, const double *Z,
-                             const double *sigma, const int32_t *atom_offsets, void *rho_out,
-                             int32_t subtract_background, void *stream)
+hartree_status hartree_atoms_bind(hartree_plan plan, int32_t natoms, const double *pos, const double *Z,
+                                  const double *sigma, const int32_t *atom_offsets, uint64_t *token, void *stream)
 {
     hartree_status st = check_ws(plan);
     if (st != HARTREE_OK) return st;
     if ((st = check_atoms(plan, natoms, pos, Z, sigma, atom_offsets)) != HARTREE_OK) return st;
-    if (!rho_out) return fail(HARTREE_ERR_ARG, "rho_out is NULL");
     SplatArgs a = splat_args(plan, natoms, pos, Z, sigma, atom_offsets);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    plan->bound = false;
+    hipError_t e = timed(plan, HARTREE_K_BIN, s, [&]() { return run_bin(a, s); });
+    if (e != hipSuccess) return hip_fail(e, "atom binning");
+    plan->bound = true;
+    plan->bind_token += 1;
+    plan->bound_natoms = natoms;
+    plan->bound_pos = pos;
+    plan->bound_Z = Z;
+    plan->bound_sigma = sigma;
+    plan->bound_offsets.assign(a.atom_off, a.atom_off + plan->nprob + 1);
+    if (token) *token = plan->bind_token;
+    return ok();
+}
+
+namespace {
+hartree_status bound_args(hartree_plan plan, uint64_t token, SplatArgs &a)
+{
+    hartree_status st = check_ws(plan);
+    if (st != HARTREE_OK) return st;
+    if (!plan->bound || token != plan->bind_token)
+        return fail(HARTREE_ERR_ARG, "atom binding %llu is not current (current %llu)", (unsigned long long)token,
+                    (unsigned long long)plan->bind_token);
+    a = splat_args(plan, plan->bound_natoms, plan->bound_pos, plan->bound_Z, plan->bound_sigma,
+                   plan->nprob > 1 ? plan->bound_offsets.data() : nullptr);
+    return HARTREE_OK;
+}
+}  // namespace
+
+hartree_status hartree_splat_bound(hartree_plan plan, uint64_t token, void *rho_out, int32_t subtract_background,
+                                   void *stream)
+{
+    SplatArgs a;
+    hartree_status st = bound_args(plan, token, a);
+    if (st != HARTREE_OK) return st;
+    if (!rho_out) return fail(HARTREE_ERR_ARG, "rho_out is NULL");
     a.rho = rho_out;
     a.subtract_background = subtract_background ? 1 : 0;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = timed(plan, HARTREE_K_BIN, s, [&]() { return run_bin(a, s); });
-    if (e != hipSuccess) return hip_fail(e, "atom binning");
-    e = timed(plan, HARTREE_K_SPLAT, s, [&]() { return run_gather(a, s); });
+    hipError_t e = timed(plan, HARTREE_K_SPLAT, s, [&]() { return run_gather(a, s); });
     if (e != hipSuccess) return hip_fail(e, "splat");
     return ok();
+}
+
+hartree_status hartree_splat_adjoint_bound(hartree_plan plan, uint64_t token, const void *grad_rho, double *grad_pos,
+                                           void *stream)
+{
+    SplatArgs a;
+    hartree_status st = bound_args(plan, token, a);
+    if (st != HARTREE_OK) return st;
+    if (!grad_rho || (a.natoms > 0 && !grad_pos)) return fail(HARTREE_ERR_ARG, "grad_rho or grad_pos is NULL");
+    a.grad_rho = grad_rho;
+    a.grad_pos = grad_pos;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = timed(plan, HARTREE_K_ADJOINT, s, [&]() { return run_adjoint(a, s); });
+    if (e != hipSuccess) return hip_fail(e, "splat adjoint");
+    e = timed(plan, HARTREE_K_ADJOINT_FINAL, s, [&]() { return run_adjoint_final(a, s); });
+    if (e != hipSuccess) return hip_fail(e, "splat adjoint reduction");
+    return ok();
+}
+
+hartree_status hartree_splat(hartree_plan plan, int32_t natoms, const double *pos, const double *Z,
+                             const double *sigma, const int32_t *atom_offsets, void *rho_out,
+                             int32_t subtract_background, void *stream)
+{
+    if (!rho_out) return fail(HARTREE_ERR_ARG, "rho_out is NULL");
+    uint64_t token = 0;
+    hartree_status st = hartree_atoms_bind(plan, natoms, pos, Z, sigma, atom_offsets, &token, stream);
+    if (st != HARTREE_OK) return st;
+    return hartree_splat_bound(plan, token, rho_out, subtract_background, stream);
 }
 
 hartree_status hartree_splat_adjoint(hartree_plan plan, int32_t natoms, const double *pos, const double *Z,
                                      const double *sigma, const int32_t *atom_offsets, const void *grad_rho,
                                      double *grad_pos, void *stream)
 {
-    hartree_status st = check_ws(plan);
-    if (st != HARTREE_OK) return st;
-    if ((st = check_atoms(plan, natoms, pos, Z, sigma, atom_offsets)) != HARTREE_OK) return st;
     if (!grad_rho || (natoms > 0 && !grad_pos)) return fail(HARTREE_ERR_ARG, "grad_rho or grad_pos is NULL");
-    SplatArgs a = splat_args(plan, natoms, pos, Z, sigma, atom_offsets);
-    a.grad_rho = grad_rho;
-    a.grad_pos = grad_pos;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = timed(plan, HARTREE_K_BIN, s, [&]() { return run_bin(a, s); });
-    if (e != hipSuccess) return hip_fail(e, "atom binning");
-    e = timed(plan, HARTREE_K_ADJOINT, s, [&]() { return run_adjoint(a, s); });
-    if (e != hipSuccess) return hip_fail(e, "splat adjoint");
-    e = timed(plan, HARTREE_K_ADJOINT_FINAL, s, [&]() { return run_adjoint_final(a, s); });
-    if (e != hipSuccess) return hip_fail(e, "splat adjoint reduction");
-    return ok();
+    uint64_t token = 0;
+    hartree_status st = hartree_atoms_bind(plan, natoms, pos, Z, sigma, atom_offsets, &token, stream);
+    if (st != HARTREE_OK) return st;
+    return hartree_splat_adjoint_bound(plan, token, grad_rho, grad_pos, stream);
 }
 
 hartree_status hartree_device_status(hartree_plan plan, uint32_t *bits, void *stream)

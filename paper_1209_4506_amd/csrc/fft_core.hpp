@@ -216,6 +216,27 @@ struct LdsPencil {
     }
 };
 
+// element i of the thread's pencil in a pencil-major LDS tile
+// (buf[p * ldp + i]), used where threads run along the pencil
+template <typename T>
+struct LdsRow {
+    static constexpr bool kLds = true;
+    Cx<T> *buf;
+    int ldp, p;
+    bool cj;
+    __device__ __forceinline__ Cx<T> load(int i) const
+    {
+        Cx<T> v = buf[p * ldp + i];
+        if (cj) v.y = -v.y;
+        return v;
+    }
+    __device__ __forceinline__ void store(int i, Cx<T> v) const
+    {
+        if (cj) v.y = -v.y;
+        buf[p * ldp + i] = v;
+    }
+};
+
 // element i of a strided pencil in global memory (zero beyond the tile edge)
 template <typename T>
 struct GlobalPencil {
@@ -314,13 +335,13 @@ __device__ __forceinline__ void stage_any(int r, const Src &src, Dst &dst, const
 // in place on the LDS tile `lds`.  A single-stage length runs its stage into
 // the tile and then copies it to dst.  On return every thread has finished
 // writing; the caller synchronizes before reading the LDS tile.
-template <typename T, typename Src, typename Dst>
-__device__ __forceinline__ void fft_pencils(const Src &src, Dst &dst, const LdsPencil<T> &lds, const Cx<T> *tw,
+template <typename T, typename Src, typename Dst, typename L>
+__device__ __forceinline__ void fft_pencils(const Src &src, Dst &dst, const L &lds, const Cx<T> *tw,
                                             const AxisPlan &ap, int tip, int tpp)
 {
     const int n = ap.n;
     const int S = ap.nstages;
-    LdsPencil<T> l = lds;
+    L l = lds;
     l.cj = false;
     // a stage that writes where the workgroup still reads (the LDS tile)
     // separates its reads from its writes with a barrier
@@ -343,13 +364,13 @@ __device__ __forceinline__ void fft_pencils(const Src &src, Dst &dst, const LdsP
 // radix; a kernel that switches between radices at run time (fft_pencils)
 // must hold registers for the largest case in every stage, which costs
 // occupancy.
-template <typename T, int R0, int R1, int R2, int R3, typename Src, typename Dst>
-__device__ __forceinline__ void fft_static(const Src &src, Dst &dst, const LdsPencil<T> &lds, const Cx<T> *tw,
+template <typename T, int R0, int R1, int R2, int R3, typename Src, typename Dst, typename L>
+__device__ __forceinline__ void fft_static(const Src &src, Dst &dst, const L &lds, const Cx<T> *tw,
                                            const AxisPlan &ap, int tip, int tpp)
 {
     constexpr int S = (R0 > 0) + (R1 > 0) + (R2 > 0) + (R3 > 0);
     const int n = ap.n;
-    LdsPencil<T> l = lds;
+    L l = lds;
     l.cj = false;
     stage<T, R0, stage_maxb<T>(R0), true, Src::kLds>(src, l, tw, n, ap.twstride[0], ap.ns[0], tip, tpp);
     __syncthreads();
@@ -371,8 +392,8 @@ __device__ __forceinline__ void fft_static(const Src &src, Dst &dst, const LdsPe
 }
 
 // Either form: R0 = 0 selects the run-time radix switch.
-template <typename T, int R0, int R1, int R2, int R3, typename Src, typename Dst>
-__device__ __forceinline__ void fft_any(const Src &src, Dst &dst, const LdsPencil<T> &lds, const Cx<T> *tw,
+template <typename T, int R0, int R1, int R2, int R3, typename Src, typename Dst, typename L>
+__device__ __forceinline__ void fft_any(const Src &src, Dst &dst, const L &lds, const Cx<T> *tw,
                                         const AxisPlan &ap, int tip, int tpp)
 {
     if constexpr (R0 == 0)

@@ -33,7 +33,7 @@ __global__ __launch_bounds__(256) void k_finalize(const ProbDesc *desc, const do
 // length does not fit): enough threads per pencil that every stage's
 // butterflies fit the registers, at most 64 pencils, and a tile that leaves
 // room for two workgroups per CU.
-int pass_p_log2(int fp64, int n, const int *radix, int nstages)
+int pass_p_log2(int fp64, int n, const int *radix, int nstages, int max_p)
 {
     int tpp = 1;
     for (int s = 0; s < nstages; ++s) {
@@ -44,9 +44,9 @@ int pass_p_log2(int fp64, int n, const int *radix, int nstages)
     }
     if (tpp > kPassThreads) return -1;
     int P = kPassThreads / tpp;
-    if (P > 64) P = 64;
+    if (P > max_p) P = max_p;
     const size_t cx = fp64 ? 16 : 8;
-    while (P > 1 && size_t(n) * (P + 1) * cx > 80 * 1024) P >>= 1;
+    while (P > 1 && size_t(row_pitch(n) > n + 1 ? row_pitch(n) : n + 1) * (P + 1) * cx > 80 * 1024) P >>= 1;
     int l = 0;
     while ((1 << l) < P) ++l;
     return l;
@@ -92,6 +92,19 @@ hipError_t run_pass(int fp64, PassKind kind, int plan, int p_log2, int maxn, int
         a.mode = 2;
         return fp64 ? run_a_f64(plan, maxn, grid, s, a) : run_a_f32(plan, maxn, grid, s, a);
     }
+}
+
+__global__ void k_zero_bytes(uint32_t *p, size_t nwords)
+{
+    for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < nwords; i += size_t(gridDim.x) * blockDim.x)
+        p[i] = 0u;
+}
+
+// zero a device array (byte count a multiple of 4) with a kernel
+hipError_t run_zero(void *p, size_t bytes, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_bytes, dim3(2048), dim3(256), 0, s, static_cast<uint32_t *>(p), bytes / 4);
+    return hipGetLastError();
 }
 
 hipError_t run_finalize(const ProbDesc *desc, const double *partials, double *e_h, int nprob, hipStream_t s)

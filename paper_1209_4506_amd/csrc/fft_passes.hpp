@@ -28,6 +28,22 @@ namespace hartree {
 // n (P + 1) complex values.
 constexpr int kPassThreads = 256;
 
+// 16-byte vectors of reals for the contiguous real-grid rows
+template <typename T>
+struct VecW;
+template <>
+struct VecW<float> {
+    static constexpr int W = 4;
+    typedef float V __attribute__((ext_vector_type(4)));
+    __device__ static V zero() { return V{0.0f, 0.0f, 0.0f, 0.0f}; }
+};
+template <>
+struct VecW<double> {
+    static constexpr int W = 2;
+    typedef double V __attribute__((ext_vector_type(2)));
+    __device__ static V zero() { return V{0.0, 0.0}; }
+};
+
 __device__ __forceinline__ void find_item(const TileList &tl, int item, int &prob, int &tile)
 {
     int i = 0;
@@ -42,57 +58,121 @@ __device__ __forceinline__ void load_twiddles(Cx<T> *dst, const Cx<T> *src, int 
     for (int i = tid; i < n; i += nt) dst[i] = src[i];
 }
 
+// ------------------------------------------------------ c-axis accessors
+// The c axis is contiguous: threads run along a pencil (tip fastest), so the
+// first stage of P1 reads, and the last stage of P5 writes, consecutive
+// points of two real grid rows straight from and to global memory.  A
+// complex pencil packs rows 2q (real part) and 2q + 1 (imaginary part).
+
+// P1 input: element i of the pair.  MODE 0: x = rho;  1: x = grad_v + s rho;
+// 2: x = s rho (no grad_v).  A row beyond the grid reads a valid row of the
+// tile and is weighted by zero, so the loads carry no branches.
+template <typename T, int MODE>
+struct RealPairIn {
+    static constexpr bool kLds = false;
+    const T *r0, *r1;       // rows 2q and 2q + 1 of the source (grad_v, or rho in MODE 0)
+    const T *h0, *h1;       // the same rows of rho (MODE 1, 2)
+    T w0, w1;               // 1 for rows inside the grid, 0 beyond
+    T s0, s1;               // scale of rho, times w
+    __device__ __forceinline__ Cx<T> load(int i) const
+    {
+        if constexpr (MODE == 0) return Cx<T>{w0 * r0[i], w1 * r1[i]};
+        else if constexpr (MODE == 1) return Cx<T>{w0 * r0[i] + s0 * h0[i], w1 * r1[i] + s1 * h1[i]};
+        else return Cx<T>{s0 * h0[i], s1 * h1[i]};
+    }
+};
+
+// P5 input: Z[i] = X[i] + i Y[i] from the half-spectrum rows of X and Y,
+// with X[n - i] = conj X[i] beyond the stored half; the imaginary parts of
+// the 0 and Nyquist bins are dropped (zero in exact arithmetic for the
+// inverse of a Hermitian spectrum).  Conjugated: P5 runs the inverse.
+template <typename T>
+struct HermitianPairIn {
+    static constexpr bool kLds = false;
+    const Cx<T> *x0, *x1;   // rows beyond the grid point at a valid row
+    int n, nh;
+    T w0, w1;               // 1 inside the grid, 0 beyond
+    __device__ __forceinline__ Cx<T> load(int i) const
+    {
+        const bool mirror = i >= nh;
+        const int k = mirror ? n - i : i;
+        Cx<T> xe = cscale(x0[k], w0);
+        Cx<T> xo = cscale(x1[k], w1);
+        if (mirror) {
+            xe.y = -xe.y;
+            xo.y = -xo.y;
+        }
+        if (i == 0 || 2 * i == n) {
+            xe.y = T(0);
+            xo.y = T(0);
+        }
+        return Cx<T>{xe.x - xo.y, -(xe.y + xo.x)};
+    }
+};
+
+// P5 output: the conjugate of the last stage's value is x + i y for the
+// two real rows
+template <typename T>
+struct RealPairOut {
+    static constexpr bool kLds = false;
+    T *o0, *o1;
+    bool v0, v1;
+    __device__ __forceinline__ void store(int i, Cx<T> v) const
+    {
+        if (v0) o0[i] = v.x;
+        if (v1) o1[i] = -v.y;
+    }
+};
+
+// pencil-major tile pitch: n rounded so that consecutive pencils start in
+// opposite halves of the LDS banks
+__host__ __device__ inline int row_pitch(int n) { return n + ((16 - n % 32) + 32) % 32; }
+
 // ---------------------------------------------------------------- P1
-// mode 0: x = rho.  mode 1 (backward): x = grad_v + grad_e * dV * rho.
-template <typename T, int R0, int R1, int R2, int R3>
-__global__ __launch_bounds__(256) void k_r2c(PassArgs a)
+// MODE 0: x = rho.  MODE 1 (backward): x = grad_v + grad_e * dV * rho.
+// MODE 2: x = grad_e * dV * rho.
+template <typename T, int MODE, int R0, int R1, int R2, int R3>
+__global__ __launch_bounds__(256) void k_r2c_mode(PassArgs a)
 {
     constexpr int NT = kPassThreads;
-    const int P = 1 << a.p_log2, TPP = NT >> a.p_log2, PP = P + 1;
+    const int P = 1 << a.p_log2, TPP = NT >> a.p_log2;
     extern __shared__ __align__(16) unsigned char smem[];
     int prob, tile;
     find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
     const ProbDesc &d = a.desc[prob];
     const int n = d.dims[2], nh = d.dims[3];
+    const int ldp = row_pitch(n);
     const int64_t nrows = int64_t(d.dims[0]) * d.dims[1];
     const int64_t row0 = int64_t(tile) * 2 * P;
     const int rows = int((nrows - row0) < 2 * P ? (nrows - row0) : 2 * P);
     Cx<T> *buf = reinterpret_cast<Cx<T> *>(smem);
-    Cx<T> *tw = buf + n * PP;
+    Cx<T> *tw = buf + P * ldp;
     const int tid = threadIdx.x;
     load_twiddles(tw, reinterpret_cast<const Cx<T> *>(a.tw) + d.ax[2].tw_off, n, tid, NT);
+    __syncthreads();
 
-    // rows 2q and 2q+1 become the real and imaginary parts of pencil q
-    const int64_t g0 = d.grid_off + row0 * n;
-    const T *src = reinterpret_cast<const T *>(a.in) + g0;
-    const T *rho = reinterpret_cast<const T *>(a.in2) + g0;
-    const int mode = a.mode;
-    T scale = T(0);
-    if (mode == 1 && a.grad_e != nullptr) scale = T(a.grad_e[prob] * d.dv);
-    const int total = rows * n;
-    T *bufr = reinterpret_cast<T *>(buf);
-    for (int e = tid; e < 2 * P * n; e += NT) {
-        const int row = int(fdiv(uint32_t(e), d.div_nc));
-        const int k = e - row * n;
-        T v = T(0);
-        if (e < total) {
-            if (mode == 0) {
-                v = src[e];
-            } else {
-                if (a.in != nullptr) v = src[e];
-                if (a.grad_e != nullptr) v += scale * rho[e];
-            }
-        }
-        bufr[2 * (k * PP + (row >> 1)) + (row & 1)] = v;
+    const int q = tid / TPP, tip = tid - q * TPP;
+    const bool v0 = 2 * q < rows, v1 = 2 * q + 1 < rows;
+    const int64_t g_even = d.grid_off + (row0 + (v0 ? 2 * q : 0)) * n;
+    const int64_t g_odd = d.grid_off + (row0 + (v1 ? 2 * q + 1 : 0)) * n;
+    RealPairIn<T, MODE> in;
+    in.r0 = reinterpret_cast<const T *>(a.in) + g_even;
+    in.r1 = reinterpret_cast<const T *>(a.in) + g_odd;
+    in.h0 = reinterpret_cast<const T *>(a.in2) + g_even;
+    in.h1 = reinterpret_cast<const T *>(a.in2) + g_odd;
+    in.w0 = v0 ? T(1) : T(0);
+    in.w1 = v1 ? T(1) : T(0);
+    const T scale = MODE == 0 ? T(0) : T(a.grad_e[prob] * d.dv);
+    in.s0 = scale * in.w0;
+    in.s1 = scale * in.w1;
+    const LdsRow<T> lr{buf, ldp, q, false};
+    if (d.ax[2].nstages > 0) {
+        LdsRow<T> out = lr;
+        fft_any<T, R0, R1, R2, R3>(in, out, lr, tw, d.ax[2], tip, TPP);
+    } else if (tip == 0) {
+        lr.store(0, in.load(0));
     }
     __syncthreads();
-    const int p = tid & (P - 1), tip = tid >> a.p_log2;
-    const LdsPencil<T> lp{buf, PP, p, false};
-    if (d.ax[2].nstages > 0) {
-        LdsPencil<T> out = lp;
-        fft_any<T, R0, R1, R2, R3>(lp, out, lp, tw, d.ax[2], tip, TPP);
-        __syncthreads();
-    }
 
     // X[k] = (Z[k] + conj Z[n-k]) / 2,  Y[k] = (Z[k] - conj Z[n-k]) / (2i)
     Cx<T> *dst = reinterpret_cast<Cx<T> *>(a.spec) + d.spec_off + row0 * nh;
@@ -100,9 +180,9 @@ __global__ __launch_bounds__(256) void k_r2c(PassArgs a)
     for (int e = tid; e < totalh; e += NT) {
         const int row = int(fdiv(uint32_t(e), d.div_nh));
         const int k = e - row * nh;
-        const int q = row >> 1;
-        const Cx<T> A = buf[k * PP + q];
-        const Cx<T> B = buf[(k == 0 ? 0 : n - k) * PP + q];
+        const Cx<T> *z = buf + (row >> 1) * ldp;
+        const Cx<T> A = z[k];
+        const Cx<T> B = z[k == 0 ? 0 : n - k];
         Cx<T> X;
         if ((row & 1) == 0)
             X = {T(0.5) * (A.x + B.x), T(0.5) * (A.y - B.y)};
@@ -117,58 +197,42 @@ template <typename T, int R0, int R1, int R2, int R3>
 __global__ __launch_bounds__(256) void k_c2r(PassArgs a)
 {
     constexpr int NT = kPassThreads;
-    const int P = 1 << a.p_log2, TPP = NT >> a.p_log2, PP = P + 1;
+    const int P = 1 << a.p_log2, TPP = NT >> a.p_log2;
     extern __shared__ __align__(16) unsigned char smem[];
     int prob, tile;
     find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
     const ProbDesc &d = a.desc[prob];
     const int n = d.dims[2], nh = d.dims[3];
+    const int ldp = row_pitch(n);
     const int64_t nrows = int64_t(d.dims[0]) * d.dims[1];
     const int64_t row0 = int64_t(tile) * 2 * P;
     const int rows = int((nrows - row0) < 2 * P ? (nrows - row0) : 2 * P);
     Cx<T> *buf = reinterpret_cast<Cx<T> *>(smem);
-    Cx<T> *tw = buf + n * PP;
+    Cx<T> *tw = buf + P * ldp;
     const int tid = threadIdx.x;
     load_twiddles(tw, reinterpret_cast<const Cx<T> *>(a.tw) + d.ax[2].tw_off, n, tid, NT);
-
-    // Z[k] = X[k] + i Y[k] over the full length, with X[n-k] = conj X[k]; the
-    // imaginary parts of the k = 0 and Nyquist bins are dropped (they vanish
-    // in exact arithmetic: the inverse of a Hermitian spectrum is real)
-    const Cx<T> *src = reinterpret_cast<const Cx<T> *>(a.spec) + d.spec_off + row0 * nh;
-    for (int e = tid; e < P * n; e += NT) {
-        const int q = int(fdiv(uint32_t(e), d.div_nc));
-        const int k = e - q * n;
-        const bool ve = 2 * q < rows, vo = 2 * q + 1 < rows;
-        const bool mirror = k >= nh;
-        const int kk = mirror ? n - k : k;
-        Cx<T> xe = ve ? src[(2 * q) * nh + kk] : Cx<T>{T(0), T(0)};
-        Cx<T> xo = vo ? src[(2 * q + 1) * nh + kk] : Cx<T>{T(0), T(0)};
-        if (mirror) {
-            xe.y = -xe.y;
-            xo.y = -xo.y;
-        }
-        if (k == 0 || 2 * k == n) {
-            xe.y = T(0);
-            xo.y = T(0);
-        }
-        buf[k * PP + q] = Cx<T>{xe.x - xo.y, xe.y + xo.x};
-    }
     __syncthreads();
-    const int p = tid & (P - 1), tip = tid >> a.p_log2;
-    const LdsPencil<T> lp{buf, PP, p, true};
-    if (d.ax[2].nstages > 0) {
-        LdsPencil<T> out = lp;
-        fft_any<T, R0, R1, R2, R3>(lp, out, lp, tw, d.ax[2], tip, TPP);
-        __syncthreads();
-    }
 
-    T *dst = reinterpret_cast<T *>(a.out) + d.grid_off + row0 * n;
-    const T *bufr = reinterpret_cast<const T *>(buf);
-    const int total = rows * n;
-    for (int e = tid; e < total; e += NT) {
-        const int row = int(fdiv(uint32_t(e), d.div_nc));
-        const int k = e - row * n;
-        dst[e] = bufr[2 * (k * PP + (row >> 1)) + (row & 1)];
+    const int q = tid / TPP, tip = tid - q * TPP;
+    const bool v0 = 2 * q < rows, v1 = 2 * q + 1 < rows;
+    const Cx<T> *spec = reinterpret_cast<const Cx<T> *>(a.spec) + d.spec_off + row0 * nh;
+    HermitianPairIn<T> in;
+    in.x0 = spec + (v0 ? 2 * q : 0) * nh;
+    in.x1 = spec + (v1 ? 2 * q + 1 : 0) * nh;
+    in.n = n;
+    in.nh = nh;
+    in.w0 = v0 ? T(1) : T(0);
+    in.w1 = v1 ? T(1) : T(0);
+    RealPairOut<T> out;
+    out.o0 = reinterpret_cast<T *>(a.out) + d.grid_off + (row0 + 2 * q) * n;
+    out.o1 = out.o0 + n;
+    out.v0 = v0;
+    out.v1 = v1;
+    const LdsRow<T> lr{buf, ldp, q, false};
+    if (d.ax[2].nstages > 0) {
+        fft_any<T, R0, R1, R2, R3>(in, out, lr, tw, d.ax[2], tip, TPP);
+    } else if (tip == 0) {
+        out.store(0, in.load(0));
     }
 }
 
@@ -249,9 +313,14 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 // Destination of the last forward stage along a: element m_a of the thread's
 // column is multiplied by K(G)/N on its way into the LDS tile, and (energy)
-// w(m_c) K |X|^2 is accumulated in double.
+// w(m_c) K |X|^2 is accumulated in double.  The column's share of G,
+// m_b b_b + m_c b_c, is formed once per thread; cells where the Nyquist
+// average applies take the general path of kernel_value.
 template <typename T>
 struct KernelMultiply {
     static constexpr bool kLds = true;
@@ -263,9 +332,34 @@ struct KernelMultiply {
     T invn;
     double wgt;
     double acc;
+    int na;
+    bool general;     // a Nyquist b or c index of a non-orthorhombic cell
+    T ba[3], gbc[3];  // b_a and m_b b_b + m_c b_c
+    __device__ __forceinline__ void init()
+    {
+        const T *B = nullptr;
+        if constexpr (sizeof(T) == 4) B = reinterpret_cast<const T *>(d->Bf);
+        else B = reinterpret_cast<const T *>(d->B);
+        const int Nb = d->dims[1], Nc = d->dims[2];
+        na = d->dims[0];
+        general = !d->ortho && (2 * mb == Nb || 2 * mc == Nc);
+        const T sb = T((2 * mb < Nb) ? mb : mb - Nb), sc = T(mc);
+        for (int x = 0; x < 3; ++x) {
+            ba[x] = B[x];
+            gbc[x] = sb * B[3 + x] + sc * B[6 + x];
+        }
+    }
     __device__ __forceinline__ void store(int i, Cx<T> v)
     {
-        const T K = kernel_value<T>(*d, i, mb, mc);
+        T K;
+        if (general || (!d->ortho && 2 * i == na)) {
+            K = kernel_value<T>(*d, i, mb, mc);
+        } else {
+            const T sa = T((2 * i < na) ? i : i - na);
+            const T gx = sa * ba[0] + gbc[0], gy = sa * ba[1] + gbc[1], gz = sa * ba[2] + gbc[2];
+            const T g2 = gx * gx + gy * gy + gz * gz;
+            K = (g2 > T(0)) ? T(12.566370614359172953850573533118) * recip(g2) : T(0);
+        }
         if (energy) acc += wgt * double(K * (v.x * v.x + v.y * v.y));
         buf[i * pp + p] = cscale(v, K * invn);
     }
@@ -304,6 +398,7 @@ __global__ __launch_bounds__(256) void k_fft_a(PassArgs a)
     const LdsPencil<T> lp{buf, PP, p, false};
     KernelMultiply<T> km{buf, PP, p, &d, mb, mc, energy && p < valid, T(d.inv_n),
                          (mc == 0 || 2 * mc == Nc) ? 1.0 : 2.0, 0.0};
+    km.init();
     if (d.ax[0].nstages == 0) {
         // length-1 axis: the multiply alone
         if (tip == 0) km.store(0, gp.load(0));
@@ -355,7 +450,10 @@ typedef hipError_t (*PassLaunchFn)(int grid, size_t lds, hipStream_t s, const Pa
 template <typename T>
 inline size_t pass_lds_bytes(const PassArgs &a, int maxn)
 {
-    return sizeof(Cx<T>) * (size_t((1 << a.p_log2) + 1) * maxn + maxn);
+    // strided tiles n (P + 1); pencil-major tiles P row_pitch(n) <= P (n + 31)
+    const size_t P = size_t(1) << a.p_log2;
+    const size_t tile_elems = (P + 1) * maxn > P * (maxn + 31) ? (P + 1) * maxn : P * (maxn + 31);
+    return sizeof(Cx<T>) * (tile_elems + maxn);
 }
 
 }  // namespace hartree

@@ -8,7 +8,11 @@ namespace {
 template <int R0, int R1, int R2, int R3>
 hipError_t launch_one(int grid, size_t lds, hipStream_t s, const PassArgs &a)
 {
-    return launch_pass(k_r2c<double, R0, R1, R2, R3>, grid, lds, s, a);
+    // forward: rho.  Backward (mode 1): grad_v + s rho, grad_v alone (no
+    // grad_e), or s rho alone (no grad_v); the host never passes neither.
+    if (a.mode == 0 || a.grad_e == nullptr) return launch_pass(k_r2c_mode<double, 0, R0, R1, R2, R3>, grid, lds, s, a);
+    if (a.in != nullptr) return launch_pass(k_r2c_mode<double, 1, R0, R1, R2, R3>, grid, lds, s, a);
+    return launch_pass(k_r2c_mode<double, 2, R0, R1, R2, R3>, grid, lds, s, a);
 }
 #define HARTREE_ENTRY(R0, R1, R2, R3) &launch_one<R0, R1, R2, R3>,
 const PassLaunchFn kTable[] = {HARTREE_PLANS(HARTREE_ENTRY)};

@@ -39,11 +39,12 @@ struct PassArgs {
     TileList tl;
 };
 
-int pass_p_log2(int fp64, int n, const int *radix, int nstages);
+int pass_p_log2(int fp64, int n, const int *radix, int nstages, int max_p);
 int find_plan(const int *radix, int nstages);
 hipError_t run_pass(int fp64, PassKind kind, int plan, int p_log2, int maxn, int grid, hipStream_t s,
                     const PassArgs &a);
 hipError_t run_finalize(const ProbDesc *desc, const double *partials, double *e_h, int nprob, hipStream_t s);
+hipError_t run_zero(void *p, size_t bytes, hipStream_t s);
 
 // ---------------------------------------------------------------- splat
 
@@ -76,6 +77,8 @@ struct SplatArgs {
     const void *grad_rho;   // adjoint input grid
     double *grad_pos;       // adjoint output
     double *qsum;           // nprob: total charge per problem
+    void *tab;              // per-atom 1-D factor tables: max_atoms x 3 x wcap pairs (g, gd) of the precision
+    int32_t wcap;           // table row length
 };
 
 hipError_t run_bin(const SplatArgs &a, hipStream_t s);

@@ -77,6 +77,46 @@ __global__ void k_atom_prep(SplatArgs a)
     a.info[atom] = in;
 }
 
+// Per-atom 1-D factor tables (see splat_common.hpp): one thread per
+// (atom, axis, entry).  The displacement is formed in double and the
+// exponential evaluated in the working precision.
+template <typename T>
+__global__ __launch_bounds__(256) void k_atom_tables(SplatArgs a)
+{
+    const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int64_t rowlen = a.wcap;
+    if (e >= int64_t(a.natoms) * 3 * rowlen) return;
+    const int t = int(e % rowlen);
+    const int x = int((e / rowlen) % 3);
+    const int atom = int(e / (3 * rowlen));
+    const AtomInfo in = a.info[atom];
+    const ProbDesc &d = a.desc[in.prob];
+    const int n = d.dims[x];
+    const int lo = in.lo[x], hi = in.hi[x];
+    if (hi < lo) return;
+    const int wl = hi - lo + 1;
+    const double h = d.L[x] / n;
+    T g = T(0), gd = T(0);
+    if (wl < n) {
+        if (t >= wl) return;
+        const double dd = double(lo + t) * h - in.X[x];
+        const T dt = T(dd);
+        g = expT<T>(-dt * dt * T(in.inv2s2));
+        gd = g * dt;
+    } else {
+        if (t >= n) return;
+        // every unwrapped index congruent to t inside the window
+        for (int ip = lo + wrapi(t - lo, n); ip <= hi; ip += n) {
+            const double dd = double(ip) * h - in.X[x];
+            const T dt = T(dd);
+            const T ev = expT<T>(-dt * dt * T(in.inv2s2));
+            g += ev;
+            gd += ev * dt;
+        }
+    }
+    reinterpret_cast<Cx<T> *>(a.tab)[e] = Cx<T>{g, gd};
+}
+
 __global__ __launch_bounds__(256) void k_charge(SplatArgs a, double *qsum)
 {
     __shared__ double red[256];
@@ -218,24 +258,37 @@ __global__ __launch_bounds__(256) void k_scan_blocks(SplatArgs a)
 
 // one wavefront per brick: order the list by atom index (indices are
 // distinct, so an entry's rank is the count of smaller ones), and record
-// each entry's final slot under (atom, brick) for the adjoint's reduction
+// each entry's final slot under (atom, brick) for the adjoint's reduction.
+// Lists of up to kSortLds entries are ranked from LDS.
+constexpr int kSortLds = 256;
+
 __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a)
 {
-    const int64_t b = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (b >= a.nbricks_total) return;
-    const int64_t off = a.offsets[b];
-    const int cnt = int(a.offsets[b + 1] - off);
-    const int prob = [&] {
-        int p = 0;
-        while (p + 1 < a.nprob && b >= a.desc[p + 1].brick_off) ++p;
-        return p;
-    }();
+    __shared__ int lst[4][kSortLds];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t b = int64_t(blockIdx.x) * 4 + w;
+    int64_t off = 0;
+    int cnt = 0;
+    if (b < a.nbricks_total) {
+        off = a.offsets[b];
+        cnt = int(a.offsets[b + 1] - off);
+    }
+    const bool in_lds = cnt <= kSortLds;
+    if (in_lds)
+        for (int e = lane; e < cnt; e += 64) lst[w][e] = a.list[off + e];
+    __syncthreads();
+    if (cnt == 0) return;
+    int prob = 0;
+    while (prob + 1 < a.nprob && b >= a.desc[prob + 1].brick_off) ++prob;
     const ProbDesc &d = a.desc[prob];
     for (int e = lane; e < cnt; e += 64) {
-        const int v = a.list[off + e];
+        const int v = in_lds ? lst[w][e] : a.list[off + e];
         int rank = 0;
-        for (int j = 0; j < cnt; ++j) rank += (a.list[off + j] < v) ? 1 : 0;
+        if (in_lds) {
+            for (int j = 0; j < cnt; ++j) rank += (lst[w][j] < v) ? 1 : 0;
+        } else {
+            for (int j = 0; j < cnt; ++j) rank += (a.list[off + j] < v) ? 1 : 0;
+        }
         a.list_sorted[off + rank] = v;
         const Touch t = atom_touch(a.info[v], d);
         a.slot_of[int64_t(v) * a.cap_pa + touch_index(t, d, b - d.brick_off)] = int32_t(off + rank);
@@ -251,16 +304,16 @@ __global__ __launch_bounds__(kBrickThreads) void k_splat_gather(SplatArgs a, con
     const int64_t b = blockIdx.x;
     const int prob = brick_prob(a, b);
     const ProbDesc &d = a.desc[prob];
-    const int64_t lb = b - d.brick_off;
-    const int bk = int(lb % d.nbricks[2]);
-    const int bj = int((lb / d.nbricks[2]) % d.nbricks[1]);
-    const int bi = int(lb / (int64_t(d.nbricks[2]) * d.nbricks[1]));
+    const int lb = int(b - d.brick_off);  // bricks of one problem fit 32 bits
+    const int bk = lb % d.nbricks[2];
+    const int bij = lb / d.nbricks[2];
+    const int bj = bij % d.nbricks[1];
+    const int bi = bij / d.nbricks[1];
     const int t = threadIdx.x;
     const int ci = (t & 63) >> 3, cj = t & 7, strip = t >> 6;
     const int i = bi * kBI + ci, j = bj * kBJ + cj, k0 = bk * kBK + strip * kStrip;
     const int64_t off = a.offsets[b];
     const int cnt = int(a.offsets[b + 1] - off);
-    const double h[3] = {d.L[0] / d.dims[0], d.L[1] / d.dims[1], d.L[2] / d.dims[2]};
 
     T acc[kStrip];
 #pragma unroll
@@ -274,18 +327,14 @@ __global__ __launch_bounds__(kBrickThreads) void k_splat_gather(SplatArgs a, con
         for (int e = t; e < nc * (kBI + kBJ + kBK); e += kBrickThreads) {
             const int s = e / (kBI + kBJ + kBK), q = e % (kBI + kBJ + kBK);
             const StagedAtom &in = atoms[s];
-            T g, gd;
             if (q < kBI) {
-                staged_factor<T, false>(bi * kBI + q, d.dims[0], h[0], in, 0, g, gd);
-                gx[s][q] = g * T(in.w);
+                gx[s][q] = table_factor<T>(a, bi * kBI + q, d.dims[0], in, 0).x * T(in.w);
             } else if (q < kBI + kBJ) {
                 const int qq = q - kBI;
-                staged_factor<T, false>(bj * kBJ + qq, d.dims[1], h[1], in, 1, g, gd);
-                gy[s][qq] = g;
+                gy[s][qq] = table_factor<T>(a, bj * kBJ + qq, d.dims[1], in, 1).x;
             } else {
                 const int qq = q - kBI - kBJ;
-                staged_factor<T, false>(bk * kBK + qq, d.dims[2], h[2], in, 2, g, gd);
-                gz[s][qq] = g;
+                gz[s][qq] = table_factor<T>(a, bk * kBK + qq, d.dims[2], in, 2).x;
             }
         }
         __syncthreads();
@@ -323,17 +372,17 @@ __global__ __launch_bounds__(kBrickThreads) void k_splat_adjoint(SplatArgs a)
     const int64_t b = blockIdx.x;
     const int prob = brick_prob(a, b);
     const ProbDesc &d = a.desc[prob];
-    const int64_t lb = b - d.brick_off;
-    const int bk = int(lb % d.nbricks[2]);
-    const int bj = int((lb / d.nbricks[2]) % d.nbricks[1]);
-    const int bi = int(lb / (int64_t(d.nbricks[2]) * d.nbricks[1]));
+    const int lb = int(b - d.brick_off);  // bricks of one problem fit 32 bits
+    const int bk = lb % d.nbricks[2];
+    const int bij = lb / d.nbricks[2];
+    const int bj = bij % d.nbricks[1];
+    const int bi = bij / d.nbricks[1];
     const int t = threadIdx.x;
     const int ci = (t & 63) >> 3, cj = t & 7, strip = t >> 6;
     const int i = bi * kBI + ci, j = bj * kBJ + cj, k0 = bk * kBK + strip * kStrip;
     const int64_t off = a.offsets[b];
     const int cnt = int(a.offsets[b + 1] - off);
     if (cnt == 0) return;
-    const double h[3] = {d.L[0] / d.dims[0], d.L[1] / d.dims[1], d.L[2] / d.dims[2]};
 
     T gr[kStrip];
     {
@@ -351,21 +400,20 @@ __global__ __launch_bounds__(kBrickThreads) void k_splat_adjoint(SplatArgs a)
         for (int e = t; e < nc * (kBI + kBJ + kBK); e += kBrickThreads) {
             const int s = e / (kBI + kBJ + kBK), q = e % (kBI + kBJ + kBK);
             const StagedAtom &in = atoms[s];
-            T g, gd;
             if (q < kBI) {
-                staged_factor<T, true>(bi * kBI + q, d.dims[0], h[0], in, 0, g, gd);
-                gx[s][q] = g;
-                gdx[s][q] = gd;
+                const Cx<T> v = table_factor<T>(a, bi * kBI + q, d.dims[0], in, 0);
+                gx[s][q] = v.x;
+                gdx[s][q] = v.y;
             } else if (q < kBI + kBJ) {
                 const int qq = q - kBI;
-                staged_factor<T, true>(bj * kBJ + qq, d.dims[1], h[1], in, 1, g, gd);
-                gy[s][qq] = g;
-                gdy[s][qq] = gd;
+                const Cx<T> v = table_factor<T>(a, bj * kBJ + qq, d.dims[1], in, 1);
+                gy[s][qq] = v.x;
+                gdy[s][qq] = v.y;
             } else {
                 const int qq = q - kBI - kBJ;
-                staged_factor<T, true>(bk * kBK + qq, d.dims[2], h[2], in, 2, g, gd);
-                gz[s][qq] = g;
-                gdz[s][qq] = gd;
+                const Cx<T> v = table_factor<T>(a, bk * kBK + qq, d.dims[2], in, 2);
+                gz[s][qq] = v.x;
+                gdz[s][qq] = v.y;
             }
         }
         __syncthreads();
@@ -444,6 +492,11 @@ hipError_t run_bin(const SplatArgs &a, hipStream_t s)
     const int nsb = int((nbt + kScanBlock - 1) / kScanBlock);
     if (a.natoms > 0) {
         hipLaunchKernelGGL(k_atom_prep, dim3(nb), dim3(256), 0, s, a);
+        const int nt = int((int64_t(a.natoms) * 3 * a.wcap + 255) / 256);
+        if (a.fp64)
+            hipLaunchKernelGGL(k_atom_tables<double>, dim3(nt), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL(k_atom_tables<float>, dim3(nt), dim3(256), 0, s, a);
         hipLaunchKernelGGL(k_brick_visit<0>, dim3(nw), dim3(256), 0, s, a);
     }
     hipLaunchKernelGGL(k_scan_sums, dim3(nsb), dim3(256), 0, s, a);

@@ -76,15 +76,19 @@ __device__ __forceinline__ void axis_factor_t(int ig, int n, double h, double X,
     }
 }
 
-// One atom of a chunk staged in LDS for the table computations: the window
-// start is also kept reduced into [0, n) so that a table entry needs no
-// integer division.
+// Per-atom 1-D factor tables, built once per call by k_atom_tables: for atom
+// a and axis x, entry t of row (a, x) holds (g, gd), the 1-D Gaussian factor
+// and its displacement-weighted sum,
+//   window narrower than the axis (wl < n): the single image at unwrapped
+//       index ip = lo + t, t < wl = hi - lo + 1;
+//   window as wide as the axis: every image at wrapped index t < n.
+// A brick reads the entries of its own index range from these rows.
+
+// One atom of a group staged in LDS: its table row and window.
 struct StagedAtom {
-    double X[3];
-    double inv2s2;
-    double w;
-    int lo[3], low[3], hi[3];
-    int pad;
+    int idx;                 // atom index (table row)
+    int lo[3], low[3], wl[3];  // window start, start mod n, width (0: none)
+    double w;                // Z (2 pi s^2)^(-3/2)
 };
 
 // threads t < nc stage atoms list[c0 + t]
@@ -92,39 +96,35 @@ __device__ __forceinline__ void stage_atoms(StagedAtom *dst, const SplatArgs &a,
                                             int c0, int nc, int t)
 {
     if (t < nc) {
-        const AtomInfo in = a.info[a.list_sorted[off + c0 + t]];
+        const int atom = a.list_sorted[off + c0 + t];
+        const AtomInfo in = a.info[atom];
         StagedAtom s;
+        s.idx = atom;
         for (int x = 0; x < 3; ++x) {
-            s.X[x] = in.X[x];
             s.lo[x] = in.lo[x];
-            s.hi[x] = in.hi[x];
             s.low[x] = wrapi(in.lo[x], d.dims[x]);
+            s.wl[x] = in.hi[x] >= in.lo[x] ? in.hi[x] - in.lo[x] + 1 : 0;
         }
-        s.inv2s2 = in.inv2s2;
         s.w = in.w;
-        s.pad = 0;
         dst[t] = s;
     }
 }
 
-// axis_factor_t for a staged atom: the first unwrapped index congruent to ig
-// is lo + ((ig - low) mod n), with ig and low both in [0, n)
-template <typename T, bool WITH_D>
-__device__ __forceinline__ void staged_factor(int ig, int n, double h, const StagedAtom &at, int x, T &g, T &gd)
+// (g, gd) of a staged atom at wrapped grid index ig along axis x
+template <typename T>
+__device__ __forceinline__ Cx<T> table_factor(const SplatArgs &a, int ig, int n, const StagedAtom &at, int x)
 {
-    g = T(0);
-    gd = T(0);
-    const int lo = at.lo[x], hi = at.hi[x];
-    if (hi < lo || ig >= n) return;
-    int delta = ig - at.low[x];
-    if (delta < 0) delta += n;
-    for (int ip = lo + delta; ip <= hi; ip += n) {
-        const double dd = double(ip) * h - at.X[x];
-        const T dt = T(dd);
-        const T e = expT<T>(-dt * dt * T(at.inv2s2));
-        g += e;
-        if (WITH_D) gd += e * dt;
+    const int wl = at.wl[x];
+    if (wl <= 0 || ig >= n) return Cx<T>{T(0), T(0)};
+    int t = ig;
+    if (wl < n) {
+        t = ig - at.low[x];
+        if (t < 0) t += n;
+        if (t >= wl) return Cx<T>{T(0), T(0)};
     }
+    if (t >= a.wcap) return Cx<T>{T(0), T(0)};  // never for sigma <= max_sigma
+    const Cx<T> *tab = reinterpret_cast<const Cx<T> *>(a.tab);
+    return tab[(int64_t(at.idx) * 3 + x) * a.wcap + t];
 }
 
 }  // namespace hartree

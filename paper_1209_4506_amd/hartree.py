@@ -63,6 +63,9 @@ def _load():
         "hartree_splat": [vp, i32, vp, vp, vp, P(i32), vp, i32, vp],
         "hartree_splat_adjoint": [vp, i32, vp, vp, vp, P(i32), vp, vp, vp],
         "hartree_device_status": [vp, P(ctypes.c_uint32), vp],
+        "hartree_atoms_bind": [vp, i32, vp, vp, vp, P(i32), P(ctypes.c_uint64), vp],
+        "hartree_splat_bound": [vp, ctypes.c_uint64, vp, i32, vp],
+        "hartree_splat_adjoint_bound": [vp, ctypes.c_uint64, vp, vp, vp],
         "hartree_profile_begin": [vp],
         "hartree_profile_end": [vp, P(d), P(i64)],
     }
@@ -83,7 +86,8 @@ LIB = _load()
 EXPORTED = ["hartree_plan_create", "hartree_plan_create_batched", "hartree_plan_destroy", "hartree_plan_nprob",
             "hartree_plan_grid_offset", "hartree_workspace_size", "hartree_bind_workspace", "hartree_solve",
             "hartree_energy", "hartree_backward", "hartree_splat", "hartree_splat_adjoint",
-            "hartree_device_status", "hartree_profile_begin", "hartree_profile_end", "hartree_last_error"]
+            "hartree_device_status", "hartree_atoms_bind", "hartree_splat_bound", "hartree_splat_adjoint_bound",
+            "hartree_profile_begin", "hartree_profile_end", "hartree_last_error"]
 
 # hartree_kernel_id order
 KERNELS = ["r2c", "r2c_bwd", "fft_b", "fft_a", "fft_a_bwd", "fft_a_eonly", "fft_b_inv", "c2r", "finalize",
@@ -243,6 +247,30 @@ class Plan:
             offs = (ctypes.c_int32 * len(c))(*c.tolist())
         return pos, Z, sigma, n, offs
 
+    def bind_atoms(self, pos, Z, sigma, atom_counts=None, stream=None):
+        """Bin the atoms once for a splat and its adjoint; returns a token.
+        The tensors passed here must stay alive and unchanged while it is used."""
+        pos, Z, sigma, n, offs = self._atoms(pos, Z, sigma, atom_counts)
+        token = ctypes.c_uint64()
+        _check(LIB.hartree_atoms_bind(self._h, n, _ptr(pos), _ptr(Z), _ptr(sigma), offs, ctypes.byref(token),
+                                      stream or _stream(self.device)))
+        self._bound = (pos, Z, sigma, n)  # keep the converted arrays alive
+        return int(token.value)
+
+    def splat_bound(self, token, out=None, subtract_background=True, stream=None):
+        out = self.empty_grid() if out is None else self._grid(out, "out")
+        _check(LIB.hartree_splat_bound(self._h, ctypes.c_uint64(token), _ptr(out), 1 if subtract_background else 0,
+                                       stream or _stream(self.device)))
+        return out
+
+    def splat_adjoint_bound(self, token, grad_rho, out=None, stream=None):
+        self._grid(grad_rho, "grad_rho")
+        n = self._bound[3]
+        out = torch.empty((n, 3), dtype=torch.float64, device=self.device) if out is None else out
+        _check(LIB.hartree_splat_adjoint_bound(self._h, ctypes.c_uint64(token), _ptr(grad_rho), _ptr(out),
+                                               stream or _stream(self.device)))
+        return out
+
     def splat(self, pos, Z, sigma, out=None, subtract_background=True, atom_counts=None, stream=None):
         pos, Z, sigma, n, offs = self._atoms(pos, Z, sigma, atom_counts)
         out = self.empty_grid() if out is None else self._grid(out, "out")
@@ -287,10 +315,12 @@ class HartreeFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, pos, Z, sigma, plan, atom_counts=None):
-        rho = plan.splat(pos.detach(), Z, sigma, atom_counts=atom_counts)
+        token = plan.bind_atoms(pos.detach(), Z, sigma, atom_counts=atom_counts)
+        rho = plan.splat_bound(token)
         V, E = plan.solve(rho)
         ctx.plan = plan
         ctx.atom_counts = atom_counts
+        ctx.token = token
         ctx.save_for_backward(pos, Z, sigma, rho)
         return V, E
 
@@ -300,7 +330,10 @@ class HartreeFn(torch.autograd.Function):
         plan = ctx.plan
         gV = None if gV is None else gV.to(plan.dtype).contiguous()
         grho = plan.backward(grad_v=gV, grad_e=gE, rho=rho if gE is not None else None)
-        gpos = plan.splat_adjoint(pos.detach(), Z, sigma, grho, atom_counts=ctx.atom_counts)
+        try:  # the forward's binding, unless the plan has been rebound since
+            gpos = plan.splat_adjoint_bound(ctx.token, grho)
+        except HartreeError:
+            gpos = plan.splat_adjoint(pos.detach(), Z, sigma, grho, atom_counts=ctx.atom_counts)
         return gpos.to(pos.dtype), None, None, None, None
 
 

@@ -212,3 +212,24 @@ def test_rejects_arguments(H):
     plan.splat(pos, one, one * 2.0)
     assert plan.device_status() & H.DEV_SIGMA_RANGE
     assert plan.device_status() == 0
+
+
+def test_bound_atoms_reuse(H):
+    """A binding shared by splat and adjoint gives the unbound results bit for
+    bit; a rebinding invalidates older tokens."""
+    say("case bound atoms")
+    p = inputs.small_problem((30, 36, 40), 20, seed=3, L=(8.0, 8.5, 9.0))
+    plan = H.Plan(p.cell, p.dims, precision="fp32", max_atoms=p.natoms)
+    pos, Z, sig = _atoms(p)
+    rho_u = plan.splat(pos, Z, sig)
+    g = torch.randn(p.dims, device="cuda", dtype=torch.float32)
+    f_u = plan.splat_adjoint(pos, Z, sig, g)
+    tok = plan.bind_atoms(pos, Z, sig)
+    rho_b = plan.splat_bound(tok)
+    f_b = plan.splat_adjoint_bound(tok, g)
+    torch.cuda.synchronize()
+    assert torch.equal(rho_u, rho_b) and torch.equal(f_u, f_b)
+    tok2 = plan.bind_atoms(pos + 0.1, Z, sig)
+    assert tok2 != tok
+    with pytest.raises(H.HartreeError):
+        plan.splat_bound(tok)
