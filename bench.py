@@ -35,6 +35,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default pass shapes (skip hartree_plan_tune)")
+    ap.add_argument("--graph", action="store_true",
+                    help="also time the step replayed as one captured HIP graph")
     ap.add_argument("--cpu-atoms", type=int, default=512, help="atoms in the CPU-oracle sample")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -68,11 +71,12 @@ def source_hash():
 class Step:
     """Preallocated buffers and the four C-ABI calls of one fwd+bwd solve."""
 
-    def __init__(self, prob, precision, torch, H, inputs):
+    def __init__(self, prob, precision, torch, H, inputs, tune=True):
         self.torch = torch
         dev = torch.device("cuda:0")
         self.plan = H.Plan(prob.cell, prob.dims, precision=precision, device=dev, max_atoms=prob.natoms)
         p = self.plan
+        self.config = p.tune(reps=5) if tune else p.get_config()
         self.pos = torch.tensor(prob.pos, device=dev)
         self.Z = torch.tensor(prob.Z, device=dev)
         self.sig = torch.tensor(prob.sigma, device=dev)
@@ -108,6 +112,19 @@ class Step:
         t1 = time.perf_counter()
         prof = self.plan.profile_end() if profile else None
         return (t1 - t0), prof
+
+    def timed_graph(self, steps, warmup):
+        """The same step captured once as a HIP graph and replayed."""
+        torch = self.torch
+        self.plan.capture(self)
+        for _ in range(warmup):
+            self.plan.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.plan.replay()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
 
 
 def kernel_bytes(name, prob, s):
@@ -190,10 +207,14 @@ def main():
     from paper_1209_4506_amd import inputs
 
     prob = inputs.diamond360()
-    step = Step(prob, "fp32", torch, H, inputs)
+    step = Step(prob, "fp32", torch, H, inputs, tune=not args.no_tune)
     assert step.plan.device_status() == 0
     dt, prof = step.timed(args.steps, args.warmup, profile=True)
     assert step.plan.device_status() == 0, "device status bits set"
+    graph = None
+    if args.graph:
+        dtg = step.timed_graph(args.steps, args.warmup)
+        graph = {"value": args.steps / dtg, "unit": "solves/s", "ms_per_step": 1000.0 * dtg / args.steps}
     ms = 1000.0 * dt / args.steps
     s = 4
     n = prob.npoints
@@ -229,12 +250,15 @@ def main():
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_for(dom, "fp32"),
                      "bytes_per_launch": dom_bytes, "avg_launch_us": 1000.0 * dom_ms},
         "kernels": per_kernel,
+        "pass_config": step.config.reshape(-1).tolist(),
         "source_hash": source_hash(),
     }
+    if graph is not None:
+        out["graph_replay"] = graph
     if not args.no_fp64:
         del step
         torch.cuda.empty_cache()
-        step64 = Step(prob, "fp64", torch, H, inputs)
+        step64 = Step(prob, "fp64", torch, H, inputs, tune=not args.no_tune)
         k64 = max(3, args.steps // 4)
         dt64, prof64 = step64.timed(k64, 2, profile=True)
         out["fp64_plain"] = {"value": k64 / dt64, "unit": "solves/s", "ms_per_step": 1000.0 * dt64 / k64,

@@ -109,7 +109,8 @@ hartree_status hartree_plan_grid_offset(hartree_plan plan, int32_t p, int64_t *o
 
 /* Workspace: bytes needed (host out), then bind a device allocation of at
  * least that many bytes, 256-byte aligned.  Binding uploads the FP64-generated
- * twiddle tables with a synchronous copy; it is the only call that
+ * twiddle tables with a synchronous copy; apart from hartree_device_status,
+ * hartree_plan_set_config and hartree_plan_tune it is the only call that
  * synchronizes.  Rebinding replaces the previous workspace. */
 hartree_status hartree_workspace_size(hartree_plan plan, size_t *bytes);
 hartree_status hartree_bind_workspace(hartree_plan plan, void *workspace, size_t bytes);
@@ -209,8 +210,56 @@ hartree_status hartree_splat_bound(hartree_plan plan, uint64_t token, void *rho_
 hartree_status hartree_splat_adjoint_bound(hartree_plan plan, uint64_t token, const void *grad_rho, double *grad_pos,
                                            void *stream);
 
-/* Read (synchronously) and clear the device status word (HARTREE_DEV_* bits). */
+/* Read (synchronously) and clear the device status word (HARTREE_DEV_* bits).
+ * Refused (HARTREE_ERR_ARG) while a graph capture is open on the plan. */
 hartree_status hartree_device_status(hartree_plan plan, uint32_t *bits, void *stream);
+
+/* One-launch replay of a whole step (not from the paper: it replaces per-call
+ * launches by one HIP graph launch, e.g. for the batched workload of many
+ * small problems).
+ *   hartree_graph_begin  starts capturing `stream` (a created stream, not the
+ *                        default one) in thread-local mode;
+ *   then the caller enqueues any sequence of this plan's compute calls on that
+ *   stream (for instance hartree_splat_bound, hartree_solve,
+ *   hartree_backward, hartree_splat_adjoint_bound): they are recorded, not run;
+ *   hartree_graph_end    ends the capture and instantiates the graph, which the
+ *                        plan keeps (replacing an earlier one);
+ *   hartree_graph_launch replays it on any stream.
+ * A replay reads and writes the same device addresses as the captured calls
+ * (current contents of the inputs, including atom positions of the binding
+ * that was current at capture; the binding itself is recomputed only if
+ * hartree_atoms_bind was among the captured calls).  Run the sequence once
+ * without capture first: that first run makes the one-time attribute calls
+ * that capture does not allow.  No profiling events are recorded while
+ * capturing; hartree_bind_workspace and hartree_device_status are refused.
+ * A HIP error inside the capture makes hartree_graph_end return
+ * HARTREE_ERR_HIP and keep the previous graph. */
+hartree_status hartree_graph_begin(hartree_plan plan, void *stream);
+hartree_status hartree_graph_end(hartree_plan plan, void *stream);
+hartree_status hartree_graph_launch(hartree_plan plan, void *stream);
+
+/* Pass shapes: for every problem q and axis x (0 = a, 1 = b, 2 = c) a plan
+ * uses a radix sequence (an entry of the library's compiled plan table, or -1
+ * for the default factorization on the run-time radix kernel) and a tile of
+ * 2^p_log2 pencils per workgroup.  cfg is a host array of nprob x 3 x 2 int32:
+ * cfg[2 (3 q + x)] = plan entry, cfg[2 (3 q + x) + 1] = p_log2.  The choice
+ * changes only the schedule and the rounding order of the FP32/FP64 sums, not
+ * what is computed.
+ *   hartree_plan_get_config  writes the current choice;
+ *   hartree_plan_set_config  validates and applies one (HARTREE_ERR_ARG if an
+ *                            entry does not factor the length, needs more
+ *                            threads than a workgroup has, or more LDS than
+ *                            the device allows); with a workspace bound it
+ *                            re-uploads the problem descriptors (synchronous);
+ *   hartree_plan_tune        times every valid choice per (axis, length), the
+ *                            forward and inverse passes of that axis, `reps`
+ *                            times each on `stream`, keeps the fastest and
+ *                            applies it.  scratch: a device grid of the plan's
+ *                            precision and total grid size, overwritten.
+ *                            Synchronous; needs a bound workspace. */
+hartree_status hartree_plan_get_config(hartree_plan plan, int32_t *cfg);
+hartree_status hartree_plan_set_config(hartree_plan plan, const int32_t *cfg);
+hartree_status hartree_plan_tune(hartree_plan plan, void *scratch, int32_t reps, void *stream);
 
 /* Description of the last error on the calling thread ("" if none). */
 const char *hartree_last_error(void);

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <string>
 #include <vector>
@@ -137,6 +138,14 @@ struct hartree_plan_s {
     int64_t nbricks = 0;
     int64_t capacity = 0;
     std::vector<Launch> lr2c, lb, la;  // P1/P5 (axis c), P2/P4 (axis b), P3 (axis a)
+    // per problem and axis (a, b, c): compiled radix plan (-1: run-time
+    // radix kernel) and log2 of the pencils per workgroup
+    struct AxisCfg {
+        int plan;
+        int p_log2;
+    };
+    std::vector<AxisCfg> cfg;
+    int64_t max_parts = 0;  // E_H partial slots at one pencil per workgroup
     // workspace layout
     size_t o_status = 0, o_desc = 0, o_tw = 0, o_spec = 0, o_parts = 0, o_qsum = 0, o_info = 0, o_counts = 0,
            o_offsets = 0, o_cursor = 0, o_list = 0, o_lists = 0, o_bpart = 0, o_slot = 0, o_bsum = 0, o_tab = 0,
@@ -159,8 +168,21 @@ struct hartree_plan_s {
     int32_t bound_natoms = 0;
     const double *bound_pos = nullptr, *bound_Z = nullptr, *bound_sigma = nullptr;
     std::vector<int32_t> bound_offsets;
+    // stream capture into a graph (hartree_graph_begin / end / launch)
+    bool capturing = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    void drop_graph()
+    {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        graph_exec = nullptr;
+        graph = nullptr;
+    }
     ~hartree_plan_s()
     {
+        drop_graph();
         for (hipEvent_t e : pool) (void)hipEventDestroy(e);
     }
 };
@@ -198,6 +220,31 @@ void add_launch(std::vector<Launch> &v, int plan, int p_log2, int n, int prob, i
     l.tl.start[1] = tiles;
     l.tl.total = tiles;
     v.push_back(l);
+}
+
+// launch groups of the three pass kinds and the E_H partial slots from the
+// per-axis choices in p->cfg
+void rebuild_launches(hartree_plan p)
+{
+    p->lr2c.clear();
+    p->lb.clear();
+    p->la.clear();
+    p->nparts = 0;
+    for (int q = 0; q < p->nprob; ++q) {
+        ProbDesc &d = p->desc[q];
+        const auto *c = &p->cfg[3 * q];
+        const int pa = 1 << c[0].p_log2, pb = 1 << c[1].p_log2, pc = 1 << c[2].p_log2;
+        const int64_t rows = int64_t(d.dims[0]) * d.dims[1];
+        const int64_t t1 = (rows + 2 * pc - 1) / (2 * pc);
+        const int64_t t2 = int64_t(d.dims[0]) * ((d.dims[3] + pb - 1) / pb);
+        const int64_t t3 = (int64_t(d.dims[1]) * d.dims[3] + pa - 1) / pa;
+        add_launch(p->lr2c, c[2].plan, c[2].p_log2, d.dims[2], q, int(t1));
+        add_launch(p->lb, c[1].plan, c[1].p_log2, d.dims[1], q, int(t2));
+        add_launch(p->la, c[0].plan, c[0].p_log2, d.dims[0], q, int(t3));
+        d.part_off = p->nparts;
+        d.nparts = int(t3);
+        p->nparts += int(t3);
+    }
 }
 
 hartree_status create(hartree_plan *out, int nprob, const double *cells, const int32_t *dims, int32_t precision,
@@ -326,39 +373,31 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
         d.L[1] = A[4];
         d.L[2] = A[8];
         if (!ortho || A[0] <= 0.0 || A[4] <= 0.0 || A[8] <= 0.0) p->splat_ok = false;
-        // pass tiles
-        int lp[3];
+        // pass tiles: default radix plan and pencils per workgroup per axis
         for (int x = 0; x < 3; ++x) {
             // strided axes (a, b): up to 64 pencils side by side; the c axis:
             // at most 16 pencils, so at least 16 threads run along each one
-            lp[x] = pass_p_log2(p->fp64, N[x], d.ax[x].radix, d.ax[x].nstages, x == 2 ? 16 : 64);
-            if (lp[x] < 0) {
+            const int lp = pass_p_log2(p->fp64, N[x], d.ax[x].radix, d.ax[x].nstages, x == 2 ? 16 : 64);
+            if (lp < 0) {
                 delete p;
                 return fail(HARTREE_ERR_DIMS, "problem %d: length %d needs more threads per pencil than a workgroup has",
                             q, N[x]);
             }
+            p->cfg.push_back({find_plan(d.ax[x].radix, d.ax[x].nstages), lp});
         }
-        const int pa = 1 << lp[0], pb = 1 << lp[1], pc = 1 << lp[2];
+        // tile counts at one pencil per workgroup bound every choice
         const int64_t rows = int64_t(N[0]) * N[1];
-        const int64_t t1 = (rows + 2 * pc - 1) / (2 * pc);
-        const int64_t t2 = int64_t(N[0]) * ((d.dims[3] + pb - 1) / pb);
-        const int64_t t3 = (int64_t(N[1]) * d.dims[3] + pa - 1) / pa;
-        if (t1 > (1 << 30) || t2 > (1 << 30) || t3 > (1 << 30)) {
+        if ((rows + 1) / 2 > (1 << 30) || int64_t(N[0]) * d.dims[3] > (1 << 30) ||
+            int64_t(N[1]) * d.dims[3] > (1 << 30)) {
             delete p;
             return fail(HARTREE_ERR_DIMS, "problem %d: grid too large", q);
         }
-        int pl[3];
-        for (int x = 0; x < 3; ++x) pl[x] = find_plan(d.ax[x].radix, d.ax[x].nstages);
-        add_launch(p->lr2c, pl[2], lp[2], N[2], q, int(t1));
-        add_launch(p->lb, pl[1], lp[1], N[1], q, int(t2));
-        add_launch(p->la, pl[0], lp[0], N[0], q, int(t3));
-        d.part_off = p->nparts;
-        d.nparts = int(t3);
-        p->nparts += int(t3);
+        p->max_parts += int64_t(N[1]) * d.dims[3];
         // splat bricks
-        const int bsz[3] = {kBI, kBJ, kBK};
+        const int bsz[3] = {p->fp64 ? kBI : kMI, p->fp64 ? kBJ : kMJ, p->fp64 ? kBK : kMK};
         int64_t per_atom = 1;
         for (int x = 0; x < 3; ++x) {
+            d.bsz[x] = bsz[x];
             d.nbricks[x] = (N[x] + bsz[x] - 1) / bsz[x];
             const double h = std::fabs(A[4 * x]) / N[x];
             const double w = std::floor(2.0 * p->cutoff * p->max_sigma / (h > 0 ? h : 1.0)) + 1.0;
@@ -379,6 +418,7 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
     p->grid_offsets.push_back(grid);
     p->grid_total = grid;
     p->spec_count = spec;
+    rebuild_launches(p);
     p->nbricks = p->splat_ok ? bricks : 0;
     p->capacity = p->splat_ok ? int64_t(p->max_atoms) * cap_per_atom : 0;
     p->cap_pa = int32_t(cap_per_atom);
@@ -401,7 +441,7 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
     p->o_desc = take(sizeof(ProbDesc) * nprob);
     p->o_tw = take(cx * (p->twiddles.size() / 2));
     p->o_spec = take(cx * size_t(p->spec_count));
-    p->o_parts = take(8 * size_t(p->nparts + 1));
+    p->o_parts = take(8 * size_t(p->max_parts + 1));
     p->o_qsum = take(8 * size_t(nprob));
     if (p->splat_ok) {
         p->o_info = take(sizeof(AtomInfo) * size_t(p->max_atoms));
@@ -443,7 +483,7 @@ hipEvent_t next_event(hartree_plan p)
 template <typename F>
 hipError_t timed(hartree_plan p, int id, hipStream_t s, F f)
 {
-    if (!p->prof || p->recs.size() >= kMaxProfRecs) return f();
+    if (!p->prof || p->capturing || p->recs.size() >= kMaxProfRecs) return f();
     hipEvent_t a = next_event(p), b = next_event(p);
     if (!a || !b) return f();
     hipError_t e = hipEventRecord(a, s);
@@ -597,6 +637,7 @@ hartree_status hartree_workspace_size(hartree_plan plan, size_t *bytes)
 hartree_status hartree_bind_workspace(hartree_plan plan, void *workspace, size_t bytes)
 {
     if (!plan || !workspace) return fail(HARTREE_ERR_ARG, "NULL argument");
+    if (plan->capturing) return fail(HARTREE_ERR_ARG, "cannot bind a workspace during graph capture");
     if (bytes < plan->ws_size)
         return fail(HARTREE_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu needed", bytes,
                     plan->ws_size);
@@ -787,6 +828,7 @@ hartree_status hartree_device_status(hartree_plan plan, uint32_t *bits, void *st
 {
     hartree_status st = check_ws(plan);
     if (st != HARTREE_OK) return st;
+    if (plan->capturing) return fail(HARTREE_ERR_ARG, "the status word cannot be read during graph capture");
     if (!bits) return fail(HARTREE_ERR_ARG, "bits is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
     uint32_t v = 0;
@@ -831,6 +873,254 @@ hartree_status hartree_profile_end(hartree_plan plan, double *total_ms, int64_t 
     plan->recs.clear();
     plan->pool_used = 0;
     return ok();
+}
+
+hartree_status hartree_graph_begin(hartree_plan plan, void *stream)
+{
+    hartree_status st = check_ws(plan);
+    if (st != HARTREE_OK) return st;
+    if (plan->capturing) return fail(HARTREE_ERR_ARG, "a capture is already open on this plan");
+    if (!stream) return fail(HARTREE_ERR_ARG, "capture needs a created stream, not the default stream");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "beginning stream capture");
+    plan->capturing = true;
+    plan->cap_stream = s;
+    return ok();
+}
+
+hartree_status hartree_graph_end(hartree_plan plan, void *stream)
+{
+    if (!plan) return fail(HARTREE_ERR_ARG, "plan is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!plan->capturing || s != plan->cap_stream)
+        return fail(HARTREE_ERR_ARG, "no capture open on this plan and stream");
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    plan->capturing = false;
+    plan->cap_stream = nullptr;
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(e, "ending stream capture");
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e, "instantiating the captured graph");
+    }
+    plan->drop_graph();
+    plan->graph = g;
+    plan->graph_exec = x;
+    return ok();
+}
+
+hartree_status hartree_graph_launch(hartree_plan plan, void *stream)
+{
+    if (!plan) return fail(HARTREE_ERR_ARG, "plan is NULL");
+    if (!plan->graph_exec) return fail(HARTREE_ERR_ARG, "no graph captured on this plan");
+    if (plan->capturing) return fail(HARTREE_ERR_ARG, "a capture is open on this plan");
+    hipError_t e = hipGraphLaunch(plan->graph_exec, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "launching the captured graph");
+    return ok();
+}
+
+namespace {
+
+// largest dynamic LDS a workgroup may opt in to on the current device
+size_t lds_cap()
+{
+    static size_t cap = 0;
+    if (cap == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) == hipSuccess && v > 0)
+            cap = size_t(v);
+        else
+            cap = 65536;
+    }
+    return cap;
+}
+
+// radices of an axis choice for length n (plan < 0: the default
+// factorization on the run-time radix kernel); false if it does not apply
+bool choice_radices(hartree_plan p, int n, int plan, int p_log2, std::vector<int> &r)
+{
+    r.clear();
+    if (plan >= 0) {
+        if (plan >= plan_table_size()) return false;
+        int rad[4];
+        const int ns = plan_table_row(plan, rad);
+        long prod = 1;
+        for (int s = 0; s < ns; ++s) {
+            r.push_back(rad[s]);
+            prod *= rad[s];
+        }
+        if (prod != n) return false;
+    } else if (!factorize(n, p->fp64, r)) {
+        return false;
+    }
+    if (p_log2 < 0 || p_log2 > 8) return false;
+    const int tpp = pass_min_tpp(p->fp64, n, r.data(), int(r.size()));
+    if ((256 >> p_log2) < tpp) return false;  // 256 threads per pass workgroup
+    return pass_tile_lds(p->fp64, n, p_log2) <= lds_cap();
+}
+
+void set_axis(ProbDesc &d, int x, const std::vector<int> &r)
+{
+    AxisPlan &ap = d.ax[x];
+    const int n = ap.n;
+    ap.nstages = int(r.size());
+    int ns = 1;
+    for (int s = 0; s < kMaxStages; ++s) {
+        ap.radix[s] = s < ap.nstages ? r[s] : 0;
+        ap.twstride[s] = 0;
+        ap.ns[s] = make_fastdiv(1u);
+    }
+    for (int s = 0; s < ap.nstages; ++s) {
+        ap.ns[s] = make_fastdiv(uint32_t(ns));
+        ap.twstride[s] = n / (ns * r[s]);
+        ns *= r[s];
+    }
+}
+
+hartree_status upload_desc(hartree_plan p)
+{
+    if (!p->ws) return HARTREE_OK;
+    hipError_t e = hipMemcpy(p->ws + p->o_desc, p->desc.data(), sizeof(ProbDesc) * p->nprob, hipMemcpyHostToDevice);
+    return e == hipSuccess ? HARTREE_OK : hip_fail(e, "uploading problem descriptors");
+}
+
+// apply per-(problem, axis) choices (plan, p_log2) after validating all
+hartree_status apply_config(hartree_plan p, const int32_t *cfg)
+{
+    std::vector<std::vector<int>> rad(3 * p->nprob);
+    for (int q = 0; q < p->nprob; ++q)
+        for (int x = 0; x < 3; ++x) {
+            const int plan = cfg[2 * (3 * q + x)], lp = cfg[2 * (3 * q + x) + 1];
+            if (!choice_radices(p, p->desc[q].dims[x], plan, lp, rad[3 * q + x]))
+                return fail(HARTREE_ERR_ARG, "problem %d axis %d: plan %d with 2^%d pencils does not apply to length %d",
+                            q, x, plan, lp, p->desc[q].dims[x]);
+        }
+    for (int q = 0; q < p->nprob; ++q)
+        for (int x = 0; x < 3; ++x) {
+            set_axis(p->desc[q], x, rad[3 * q + x]);
+            p->cfg[3 * q + x] = {cfg[2 * (3 * q + x)], cfg[2 * (3 * q + x) + 1]};
+        }
+    rebuild_launches(p);
+    return upload_desc(p);
+}
+
+void get_config(hartree_plan p, std::vector<int32_t> &cfg)
+{
+    cfg.resize(6 * size_t(p->nprob));
+    for (size_t i = 0; i < p->cfg.size(); ++i) {
+        cfg[2 * i] = p->cfg[i].plan;
+        cfg[2 * i + 1] = p->cfg[i].p_log2;
+    }
+}
+
+// enqueue the passes along axis x (both directions) once
+hipError_t run_axis(hartree_plan p, int x, void *scratch, hipStream_t s)
+{
+    PassArgs a = base_args(p);
+    a.in = scratch;
+    a.out = scratch;
+    hipError_t e;
+    if (x == 2) {
+        if ((e = run_group(p, p->lr2c, PASS_R2C_FWD, a, s)) != hipSuccess) return e;
+        return run_group(p, p->lr2c, PASS_C2R, a, s);
+    }
+    if (x == 1) {
+        if ((e = run_group(p, p->lb, PASS_B_FWD, a, s)) != hipSuccess) return e;
+        return run_group(p, p->lb, PASS_B_INV, a, s);
+    }
+    return run_group(p, p->la, PASS_A_FULL, a, s);
+}
+
+}  // namespace
+
+hartree_status hartree_plan_get_config(hartree_plan plan, int32_t *cfg)
+{
+    if (!plan || !cfg) return fail(HARTREE_ERR_ARG, "NULL argument");
+    std::vector<int32_t> c;
+    get_config(plan, c);
+    std::copy(c.begin(), c.end(), cfg);
+    return ok();
+}
+
+hartree_status hartree_plan_set_config(hartree_plan plan, const int32_t *cfg)
+{
+    if (!plan || !cfg) return fail(HARTREE_ERR_ARG, "NULL argument");
+    if (plan->capturing) return fail(HARTREE_ERR_ARG, "cannot change the plan during graph capture");
+    hartree_status st = apply_config(plan, cfg);
+    return st == HARTREE_OK ? ok() : st;
+}
+
+hartree_status hartree_plan_tune(hartree_plan plan, void *scratch, int32_t reps, void *stream)
+{
+    hartree_status st = check_ws(plan);
+    if (st != HARTREE_OK) return st;
+    if (!scratch) return fail(HARTREE_ERR_ARG, "scratch is NULL");
+    if (reps < 1 || reps > 1000) return fail(HARTREE_ERR_ARG, "reps must be in [1, 1000]");
+    if (plan->capturing || plan->prof) return fail(HARTREE_ERR_ARG, "cannot tune during capture or profiling");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) {
+        if (ev[0]) (void)hipEventDestroy(ev[0]);
+        return fail(HARTREE_ERR_HIP, "creating timing events");
+    }
+    std::vector<int32_t> cfg;
+    get_config(plan, cfg);
+    hartree_status result = HARTREE_OK;
+    // one key per (axis, length): every problem with that length takes the choice
+    for (int x = 2; x >= 0 && result == HARTREE_OK; --x) {
+        std::vector<int> lengths;
+        for (int q = 0; q < plan->nprob; ++q)
+            if (std::find(lengths.begin(), lengths.end(), plan->desc[q].dims[x]) == lengths.end())
+                lengths.push_back(plan->desc[q].dims[x]);
+        for (int n : lengths) {
+            std::vector<std::pair<int, int>> cand;
+            std::vector<int> r;
+            for (int id = -1; id < plan_table_size(); ++id)
+                for (int lp = 0; lp <= 6; ++lp)
+                    if (choice_radices(plan, n, id, lp, r) && (id >= 0 || find_plan(r.data(), int(r.size())) < 0))
+                        cand.push_back({id, lp});
+            float best = 0.0f;
+            std::vector<int32_t> best_cfg = cfg;
+            for (const auto &c : cand) {
+                std::vector<int32_t> trial = cfg;
+                for (int q = 0; q < plan->nprob; ++q)
+                    if (plan->desc[q].dims[x] == n) {
+                        trial[2 * (3 * q + x)] = c.first;
+                        trial[2 * (3 * q + x) + 1] = c.second;
+                    }
+                if (apply_config(plan, trial.data()) != HARTREE_OK) continue;
+                hipError_t e = run_axis(plan, x, scratch, s);  // warm-up (and attribute opt-in)
+                if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+                for (int i = 0; i < reps && e == hipSuccess; ++i) e = run_axis(plan, x, scratch, s);
+                if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+                if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+                if (e != hipSuccess) {
+                    result = hip_fail(e, "timing a pass candidate");
+                    break;
+                }
+                if (best == 0.0f || ms < best) {
+                    best = ms;
+                    best_cfg = trial;
+                }
+            }
+            if (result != HARTREE_OK) break;
+            cfg = best_cfg;
+        }
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    hartree_status st2 = apply_config(plan, cfg.data());
+    if (result != HARTREE_OK) return result;
+    return st2 == HARTREE_OK ? ok() : st2;
 }
 
 const char *hartree_last_error(void) { return g_last_error.c_str(); }

@@ -71,10 +71,14 @@ struct ProbDesc {
     int64_t brick_off;  // first brick of this problem (splat bins)
     int32_t nbricks[3]; // bricks per axis
     int32_t pad2;
+    int32_t bsz[3];     // brick edge in grid points per axis
+    int32_t pad3;
 };
 
-// Splat bricks: BI x BJ x BK grid points, one workgroup each.
+// Splat bricks, one workgroup each: BI x BJ x BK grid points for the FP64
+// (vector-unit) kernels, MI x MJ x MK for the FP32 (matrix-core) kernels.
 constexpr int kBI = 8, kBJ = 8, kBK = 32;
+constexpr int kMI = 16, kMJ = 16, kMK = 32;
 constexpr int kBrickThreads = 256;   // 64 columns x 4 k-strips
 constexpr int kStrip = kBK / 4;      // points per thread along k
 

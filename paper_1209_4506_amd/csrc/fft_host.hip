@@ -33,7 +33,7 @@ __global__ __launch_bounds__(256) void k_finalize(const ProbDesc *desc, const do
 // length does not fit): enough threads per pencil that every stage's
 // butterflies fit the registers, at most 64 pencils, and a tile that leaves
 // room for two workgroups per CU.
-int pass_p_log2(int fp64, int n, const int *radix, int nstages, int max_p)
+int pass_min_tpp(int fp64, int n, const int *radix, int nstages)
 {
     int tpp = 1;
     for (int s = 0; s < nstages; ++s) {
@@ -42,6 +42,19 @@ int pass_p_log2(int fp64, int n, const int *radix, int nstages, int max_p)
         const int need = (nb + mb - 1) / mb;
         while (tpp < need) tpp <<= 1;
     }
+    return tpp;
+}
+
+size_t pass_tile_lds(int fp64, int n, int p_log2)
+{
+    const size_t P = size_t(1) << p_log2, cx = fp64 ? 16 : 8;
+    const size_t tile = (P + 1) * n > P * (n + 31) ? (P + 1) * n : P * (n + 31);
+    return cx * (tile + n);
+}
+
+int pass_p_log2(int fp64, int n, const int *radix, int nstages, int max_p)
+{
+    const int tpp = pass_min_tpp(fp64, n, radix, nstages);
     if (tpp > kPassThreads) return -1;
     int P = kPassThreads / tpp;
     if (P > max_p) P = max_p;
@@ -52,13 +65,27 @@ int pass_p_log2(int fp64, int n, const int *radix, int nstages, int max_p)
     return l;
 }
 
+#define HARTREE_ROW(R0, R1, R2, R3) {R0, R1, R2, R3},
+static const int kPlanTable[][4] = {HARTREE_PLANS(HARTREE_ROW)};
+#undef HARTREE_ROW
+
+int plan_table_size() { return int(sizeof(kPlanTable) / sizeof(kPlanTable[0])); }
+
+int plan_table_row(int id, int *radix)
+{
+    int ns = 0;
+    for (int s = 0; s < 4; ++s) {
+        radix[s] = kPlanTable[id][s];
+        if (radix[s] > 0) ns = s + 1;
+    }
+    return ns;
+}
+
 // index of a radix sequence in HARTREE_PLANS, or -1
 int find_plan(const int *radix, int nstages)
 {
-#define HARTREE_ROW(R0, R1, R2, R3) {R0, R1, R2, R3},
-    static const int plans[][4] = {HARTREE_PLANS(HARTREE_ROW)};
-#undef HARTREE_ROW
-    const int np = int(sizeof(plans) / sizeof(plans[0]));
+    const auto &plans = kPlanTable;
+    const int np = plan_table_size();
     for (int i = 0; i < np; ++i) {
         bool same = true;
         for (int s = 0; s < 4; ++s) same = same && plans[i][s] == (s < nstages ? radix[s] : 0);

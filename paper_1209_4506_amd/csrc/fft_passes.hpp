@@ -18,6 +18,9 @@
 // Nyquist planes, 2 elsewhere (the half spectrum stands for both halves).
 #pragma once
 
+#include <map>
+#include <mutex>
+
 #include "fft_core.hpp"
 #include "kernels.hpp"
 
@@ -429,13 +432,27 @@ __global__ __launch_bounds__(256) void k_fft_a(PassArgs a)
 
 // ------------------------------------------------------------- launchers
 
+// A kernel that needs more than 64 KiB of dynamic LDS is opted in once per
+// kernel (to the largest size asked so far), so that repeated launches, for
+// instance under stream capture, make no attribute calls.
+inline hipError_t lds_opt_in(const void *kern, size_t lds)
+{
+    static std::mutex mu;
+    static std::map<const void *, size_t> granted;
+    std::lock_guard<std::mutex> lock(mu);
+    size_t &g = granted[kern];
+    if (g >= lds) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e == hipSuccess) g = lds;
+    return e;
+}
+
 template <typename F>
 static hipError_t launch_pass(F kern, int grid, size_t lds, hipStream_t s, const PassArgs &a)
 {
     if (grid <= 0) return hipSuccess;
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        hipError_t e = lds_opt_in(reinterpret_cast<const void *>(kern), lds);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, s, a);

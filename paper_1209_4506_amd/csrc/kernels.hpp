@@ -40,7 +40,11 @@ struct PassArgs {
 };
 
 int pass_p_log2(int fp64, int n, const int *radix, int nstages, int max_p);
+int pass_min_tpp(int fp64, int n, const int *radix, int nstages);
+size_t pass_tile_lds(int fp64, int n, int p_log2);
 int find_plan(const int *radix, int nstages);
+int plan_table_size();
+int plan_table_row(int id, int *radix);  // fills radix[4], returns the stage count
 hipError_t run_pass(int fp64, PassKind kind, int plan, int p_log2, int maxn, int grid, hipStream_t s,
                     const PassArgs &a);
 hipError_t run_finalize(const ProbDesc *desc, const double *partials, double *e_h, int nprob, hipStream_t s);

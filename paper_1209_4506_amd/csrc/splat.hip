@@ -2,7 +2,8 @@
 //
 // The density of each atom is a product of three 1-D periodic Gaussians in
 // an orthorhombic cell, so every contribution factorizes into per-axis
-// tables.  The grid is cut into bricks of 8 x 8 x 32 points (the analogue of
+// tables.  The grid is cut into bricks of 8 x 8 x 32 points in FP64 and
+// 16 x 16 x 32 in FP32 (the analogue of
 // the paper's structure A / structure C idea, Sec. 3.2.2: the points touched
 // by one atom's sphere, and a box around a group of atoms); each brick is one
 // workgroup that gathers the atoms whose truncation window overlaps it.
@@ -142,8 +143,7 @@ struct Touch {
 __device__ __forceinline__ Touch atom_touch(const AtomInfo &in, const ProbDesc &d)
 {
     Touch t;
-    const int bsz[3] = {kBI, kBJ, kBK};
-    for (int x = 0; x < 3; ++x) axis_bricks(in.lo[x], in.hi[x], d.dims[x], bsz[x], d.nbricks[x], t.st[x], t.ct[x]);
+    for (int x = 0; x < 3; ++x) axis_bricks(in.lo[x], in.hi[x], d.dims[x], d.bsz[x], d.nbricks[x], t.st[x], t.ct[x]);
     return t;
 }
 

@@ -1,6 +1,6 @@
 // FP32 splat and splat adjoint on the matrix cores (v_mfma_f32_32x32x2f32).
 //
-// Inside one brick (8 x 8 columns (i, j) by 32 points along c) both
+// A brick is 16 x 16 columns (i, j) by 32 points along c.  Inside it both
 // operations are dense contractions over the brick's atom list:
 //
 //   splat    rho[c][k]  = sum_a  W_a gx_a(i_c) gy_a(j_c)  *  gz_a(k)
@@ -9,14 +9,19 @@
 //            (columns x k) . (k x atom functions), then per atom
 //            F_a = sum_c [gdx gy S0, gx gdy S0, gx gy S1]
 //
-// with the per-axis factors gx, gdx, ... of the VALU kernels (1-D periodic
-// Gaussians and their displacement-weighted sums).  Each wavefront owns one
-// 32-column half of the brick (and, for the adjoint, one column tile).
+// with the per-axis factors gx, gdx, ... (1-D periodic Gaussians and their
+// displacement-weighted sums) read from the per-atom tables.  The 256
+// columns (c = 16 i + j) form 8 row tiles of 32; wavefront w owns tiles 2w
+// and 2w + 1, i.e. local i = 4w, 4w + 1 and 4w + 2, 4w + 3.
 //
 // Operand layout of v_mfma_f32_32x32x2f32 (C = A B + C, A 32x2, B 2x32):
 // lane l supplies A[l % 32][l / 32] and B[l / 32][l % 32]; after the call
 // lane l holds C[i][l % 32] for i = 8 (r / 4) + 4 (l / 32) + r % 4 in its
-// accumulator element r = 0 .. 15.
+// accumulator element r = 0 .. 15.  Which reduction index sits in which of
+// the two K slots is free as long as A and B agree: the splat puts atom
+// 2 m + l / 32 in slot l / 32 of step m, the adjoint puts point
+// k = 16 (l / 32) + m there, so that each lane's grad_rho values are 16
+// consecutive points of one column, loaded once into registers.
 #include "splat_common.hpp"
 
 namespace hartree {
@@ -29,199 +34,230 @@ __device__ __forceinline__ int mfma_row(int r, int lane) { return 8 * (r >> 2) +
 // edges along c) kept on one XCD
 __device__ __forceinline__ int64_t brick_of_block() { return xcd_remap(blockIdx.x, gridDim.x); }
 
-// Atoms are staged in groups of up to kGroup (global loads and table
-// evaluation once per group, then the group's matrix work).  Four
-// wavefronts per brick; table rows are padded to an odd number of words.
-constexpr int kBrickWaves = 4;
-constexpr int kSplatThreads = 64 * kBrickWaves;
-constexpr int kGroup = 32;
+constexpr int kMThreads = 256;   // four wavefronts per brick
+constexpr int kSplatChunk = 64;  // atoms staged per pass (splat)
+constexpr int kAdjChunk = 32;    // atoms staged per pass (adjoint)
+constexpr int kAdjGroup = 16;    // atoms per MFMA column tile: 16 atoms x (g, gd)
+constexpr int kAdjGroups = kAdjChunk / kAdjGroup;
+constexpr int kRow = kMI + kMJ + kMK;  // table entries one atom needs in one brick
 
-// splat: wave w computes brick columns 32 (w & 1) .. +31 over the atom pairs
-// with (pair index & 1) == (w >> 1); the two halves are summed at the end
-__global__ __launch_bounds__(kSplatThreads) void k_splat_mfma(SplatArgs a)
+struct BrickPos {
+    int bi, bj, bk;
+};
+
+__device__ __forceinline__ BrickPos brick_pos(const ProbDesc &d, int64_t b)
 {
-    __shared__ StagedAtom atoms[kGroup];
-    __shared__ float gxw[kGroup][kBI + 1], gy[kGroup][kBJ + 1];
-    __shared__ float gz[kGroup][kBK];
-    __shared__ float part[2][64][17];  // accumulators of the odd-pair waves
+    const int lb = int(b - d.brick_off);  // bricks of one problem fit 32 bits
+    BrickPos p;
+    p.bk = lb % d.nbricks[2];
+    const int bij = lb / d.nbricks[2];
+    p.bj = bij % d.nbricks[1];
+    p.bi = bij / d.nbricks[1];
+    return p;
+}
+
+__global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
+{
+    __shared__ StagedAtom atoms[kSplatChunk];
+    __shared__ float gxw[kSplatChunk][kMI + 1], gy[kSplatChunk][kMJ + 1], gz[kSplatChunk][kMK + 1];
     const int64_t b = brick_of_block();
     const int prob = brick_prob(a, b);
     const ProbDesc &d = a.desc[prob];
-    const int lb = int(b - d.brick_off);  // bricks of one problem fit 32 bits
-    const int bk = lb % d.nbricks[2];
-    const int bij = lb / d.nbricks[2];
-    const int bj = bij % d.nbricks[1];
-    const int bi = bij / d.nbricks[1];
+    const BrickPos p = brick_pos(d, b);
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
-    const int mt = wave & 1, kh = wave >> 1;
     const int64_t off = a.offsets[b];
     const int cnt = int(a.offsets[b + 1] - off);
-    // this lane's A row: brick column c = 32 mt + lane % 32
-    const int ca = 32 * mt + (lane & 31);
-    const int ci = ca >> 3, cj = ca & 7;
-    const int kk = lane >> 5;
+    const int kk = lane >> 5, col = lane & 31;
+    // this lane's A rows: column 32 (2 wave + u) + col, i.e. local
+    // i = 4 wave + 2 u + col / 16 and j = col % 16, for u = 0, 1
+    const int i0 = 4 * wave + (col >> 4), jj = col & 15;
 
-    floatx16 acc;
+    floatx16 acc0, acc1;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    for (int r = 0; r < 16; ++r) {
+        acc0[r] = 0.0f;
+        acc1[r] = 0.0f;
+    }
 
-    for (int c0 = 0; c0 < cnt; c0 += kGroup) {
-        const int ns = (cnt - c0) < kGroup ? (cnt - c0) : kGroup;
+    for (int c0 = 0; c0 < cnt; c0 += kSplatChunk) {
+        const int ns = (cnt - c0) < kSplatChunk ? (cnt - c0) : kSplatChunk;
+        const int npair = (ns + 1) >> 1;
         stage_atoms(atoms, a, d, off, c0, ns, t);
         __syncthreads();
-        for (int e = t; e < ns * (kBI + kBJ + kBK); e += kSplatThreads) {
-            const int s = e / (kBI + kBJ + kBK), q = e % (kBI + kBJ + kBK);
-            const StagedAtom &in = atoms[s];
-            if (q < kBI) {
-                gxw[s][q] = table_factor<float>(a, bi * kBI + q, d.dims[0], in, 0).x * float(in.w);
-            } else if (q < kBI + kBJ) {
-                const int qq = q - kBI;
-                gy[s][qq] = table_factor<float>(a, bj * kBJ + qq, d.dims[1], in, 1).x;
+        for (int e = t; e < 2 * npair * kRow; e += kMThreads) {
+            const int s = e / kRow, q = e - s * kRow;
+            float v = 0.0f;
+            if (q < kMI) {
+                if (s < ns) v = table_factor<float>(a, p.bi * kMI + q, d.dims[0], atoms[s], 0).x * float(atoms[s].w);
+                gxw[s][q] = v;
+            } else if (q < kMI + kMJ) {
+                if (s < ns) v = table_factor<float>(a, p.bj * kMJ + (q - kMI), d.dims[1], atoms[s], 1).x;
+                gy[s][q - kMI] = v;
             } else {
-                const int qq = q - kBI - kBJ;
-                gz[s][qq] = table_factor<float>(a, bk * kBK + qq, d.dims[2], in, 2).x;
+                if (s < ns) v = table_factor<float>(a, p.bk * kMK + (q - kMI - kMJ), d.dims[2], atoms[s], 2).x;
+                gz[s][q - kMI - kMJ] = v;
             }
         }
         __syncthreads();
-        for (int s0 = 2 * kh; s0 < ns; s0 += 4) {
-            const int s = s0 + kk;
-            const float av = (s < ns) ? gxw[s][ci] * gy[s][cj] : 0.0f;
-            const float bv = (s < ns) ? gz[s][lane & 31] : 0.0f;
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+        for (int m = 0; m < npair; ++m) {
+            const int s = 2 * m + kk;
+            const float y = gy[s][jj];
+            const float bv = gz[s][col];
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(gxw[s][i0] * y, bv, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(gxw[s][i0 + 2] * y, bv, acc1, 0, 0, 0);
         }
         __syncthreads();
     }
-    if (kh == 1) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) part[mt][lane][r] = acc[r];
-    }
-    __syncthreads();
-    if (kh == 1) return;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] += part[mt][lane][r];
     const float bg = a.subtract_background ? float(a.qsum[prob] / (d.L[0] * d.L[1] * d.L[2])) : 0.0f;
-    const int k = bk * kBK + (lane & 31);
+    const int k = p.bk * kMK + col;
     if (k >= d.dims[2]) return;
     float *out = reinterpret_cast<float *>(a.rho) + d.grid_off;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        const int c = 32 * mt + mfma_row(r, lane);
-        const int i = bi * kBI + (c >> 3), j = bj * kBJ + (c & 7);
-        if (i < d.dims[0] && j < d.dims[1]) out[(int64_t(i) * d.dims[1] + j) * d.dims[2] + k] = acc[r] - bg;
+        const int c = mfma_row(r, lane);  // row within the tile: local i offset c / 16, j = c % 16
+        const int j = p.bj * kMJ + (c & 15);
+        const int ia = p.bi * kMI + 4 * wave + (c >> 4);
+        if (j < d.dims[1]) {
+            if (ia < d.dims[0]) out[(int64_t(ia) * d.dims[1] + j) * d.dims[2] + k] = acc0[r] - bg;
+            if (ia + 2 < d.dims[0]) out[(int64_t(ia + 2) * d.dims[1] + j) * d.dims[2] + k] = acc1[r] - bg;
+        }
     }
 }
 
-constexpr int kAdjTile = 16;                   // atoms per MFMA column tile: 16 atoms x (gz, gdz)
-constexpr int kAdjTiles = kGroup / kAdjTile;   // column tiles per group (2)
-
-// adjoint: wave w computes the 32x32 tile (columns 32 (w & 1) .., column
-// tile w >> 1) of S[c][n], n = (f, atom) = 16 f + atom
-__global__ __launch_bounds__(kSplatThreads) void k_adjoint_mfma(SplatArgs a)
+// adjoint: wave w holds grad_rho of its two row tiles in registers; per
+// group of 16 staged atoms it forms S for both tiles (32 columns n = 16 f +
+// atom) and folds the transverse factors in.
+__global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_adjoint_mfma(SplatArgs a)
 {
-    __shared__ StagedAtom atoms[kGroup];
-    __shared__ float gr[kBI * kBJ][kBK + 1];                 // brick of grad_rho, padded rows
-    __shared__ float gzt[kAdjTiles][2 * kAdjTile][kBK + 1];  // per tile: gz (f = 0) and gdz (f = 1) rows
-    __shared__ float gx[kGroup][kBI + 1], gdx[kGroup][kBI + 1], gy[kGroup][kBJ + 1], gdy[kGroup][kBJ + 1];
-    __shared__ float red[kAdjTiles][2][2][kAdjTile][3];      // [tile][column half][lane half][atom][x]
+    __shared__ StagedAtom atoms[kAdjChunk];
+    __shared__ float gx[kAdjChunk][kMI + 1], gdx[kAdjChunk][kMI + 1];
+    __shared__ float gy[kAdjChunk][kMJ + 1], gdy[kAdjChunk][kMJ + 1];
+    __shared__ float gzt[kAdjGroups][2 * kAdjGroup][kMK + 1];  // per group: gz rows, then gdz rows
+    __shared__ float red[4][2][2 * kAdjGroup][kAdjGroups][2];  // [wave][lane half][n][group][component]
     const int64_t b = brick_of_block();
     const int prob = brick_prob(a, b);
     const ProbDesc &d = a.desc[prob];
-    const int lb = int(b - d.brick_off);  // bricks of one problem fit 32 bits
-    const int bk = lb % d.nbricks[2];
-    const int bij = lb / d.nbricks[2];
-    const int bj = bij % d.nbricks[1];
-    const int bi = bij / d.nbricks[1];
+    const BrickPos p = brick_pos(d, b);
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
-    const int mt = wave & 1, tile = wave >> 1;
     const int64_t off = a.offsets[b];
     const int cnt = int(a.offsets[b + 1] - off);
     if (cnt == 0) return;
+    const int half = lane >> 5, col = lane & 31;
 
-    // grad_rho brick: 64 rows of 32 consecutive points
+    // grad_rho of this lane's two A rows (local i = 4 wave + col / 16 and
+    // + 2, j = col % 16) at points k = 32 bk + 16 half + m, m = 0 .. 15
+    float g0[16], g1[16];
     {
         const float *src = reinterpret_cast<const float *>(a.grad_rho) + d.grid_off;
-        for (int e = t; e < kBI * kBJ * kBK; e += kSplatThreads) {
-            const int c = e >> 5, k = e & 31;
-            const int i = bi * kBI + (c >> 3), j = bj * kBJ + (c & 7), kg = bk * kBK + k;
-            float v = 0.0f;
-            if (i < d.dims[0] && j < d.dims[1] && kg < d.dims[2])
-                v = src[(int64_t(i) * d.dims[1] + j) * d.dims[2] + kg];
-            gr[c][k] = v;
+        const int j = p.bj * kMJ + (col & 15);
+        const int ia = p.bi * kMI + 4 * wave + (col >> 4);
+        const int k0 = p.bk * kMK + 16 * half;
+        const bool jin = j < d.dims[1];
+        const bool in0 = jin && ia < d.dims[0], in1 = jin && ia + 2 < d.dims[0];
+        const int64_t r0 = (int64_t(ia) * d.dims[1] + j) * d.dims[2] + k0;
+        const int64_t r1 = (int64_t(ia + 2) * d.dims[1] + j) * d.dims[2] + k0;
+        const bool vec = ((d.dims[2] & 3) == 0) && ((reinterpret_cast<uintptr_t>(src) & 15) == 0) &&
+                         (k0 + 16 <= d.dims[2]);
+        if (vec) {
+            const float4 z4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 v0 = in0 ? reinterpret_cast<const float4 *>(src + r0)[q] : z4;
+                const float4 v1 = in1 ? reinterpret_cast<const float4 *>(src + r1)[q] : z4;
+                g0[4 * q] = v0.x;
+                g0[4 * q + 1] = v0.y;
+                g0[4 * q + 2] = v0.z;
+                g0[4 * q + 3] = v0.w;
+                g1[4 * q] = v1.x;
+                g1[4 * q + 1] = v1.y;
+                g1[4 * q + 2] = v1.z;
+                g1[4 * q + 3] = v1.w;
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const bool kin = k0 + m < d.dims[2];
+                g0[m] = (in0 && kin) ? src[r0 + m] : 0.0f;
+                g1[m] = (in1 && kin) ? src[r1 + m] : 0.0f;
+            }
         }
     }
-    const int n = lane & 31;              // this lane's C column: f = n / 16, atom n % 16
-    const int ca = 32 * mt + (lane & 31); // this lane's A row (brick column)
-    const int kk = lane >> 5;
-    const int f = n >> 4, sl = n & 15, half = lane >> 5;
+    const int n = col;  // this lane's C column: function f = n / 16 of atom n % 16
+    const int f = n >> 4, sl = n & 15;
 
-    for (int c0 = 0; c0 < cnt; c0 += kGroup) {
-        const int ns = (cnt - c0) < kGroup ? (cnt - c0) : kGroup;
-        const int ntile = (ns + kAdjTile - 1) / kAdjTile;
+    for (int c0 = 0; c0 < cnt; c0 += kAdjChunk) {
+        const int ns = (cnt - c0) < kAdjChunk ? (cnt - c0) : kAdjChunk;
+        const int ngroup = (ns + kAdjGroup - 1) / kAdjGroup;
         stage_atoms(atoms, a, d, off, c0, ns, t);
         __syncthreads();
-        for (int e = t; e < ntile * kAdjTile * (kBI + kBJ + kBK); e += kSplatThreads) {
-            const int s = e / (kBI + kBJ + kBK), q = e % (kBI + kBJ + kBK);
-            const int tl = s / kAdjTile, st = s % kAdjTile;
+        for (int e = t; e < ngroup * kAdjGroup * kRow; e += kMThreads) {
+            const int s = e / kRow, q = e - s * kRow;
             Cx<float> v{0.0f, 0.0f};
-            if (q < kBI) {
-                if (s < ns) v = table_factor<float>(a, bi * kBI + q, d.dims[0], atoms[s], 0);
+            if (q < kMI) {
+                if (s < ns) v = table_factor<float>(a, p.bi * kMI + q, d.dims[0], atoms[s], 0);
                 gx[s][q] = v.x;
                 gdx[s][q] = v.y;
-            } else if (q < kBI + kBJ) {
-                const int qq = q - kBI;
-                if (s < ns) v = table_factor<float>(a, bj * kBJ + qq, d.dims[1], atoms[s], 1);
+            } else if (q < kMI + kMJ) {
+                const int qq = q - kMI;
+                if (s < ns) v = table_factor<float>(a, p.bj * kMJ + qq, d.dims[1], atoms[s], 1);
                 gy[s][qq] = v.x;
                 gdy[s][qq] = v.y;
             } else {
                 // padded atom slots give zero columns
-                const int qq = q - kBI - kBJ;
-                if (s < ns) v = table_factor<float>(a, bk * kBK + qq, d.dims[2], atoms[s], 2);
-                gzt[tl][st][qq] = v.x;
-                gzt[tl][kAdjTile + st][qq] = v.y;
+                const int qq = q - kMI - kMJ;
+                if (s < ns) v = table_factor<float>(a, p.bk * kMK + qq, d.dims[2], atoms[s], 2);
+                const int g = s / kAdjGroup, st = s - g * kAdjGroup;
+                gzt[g][st][qq] = v.x;
+                gzt[g][kAdjGroup + st][qq] = v.y;
             }
         }
         __syncthreads();
-        if (tile < ntile) {
-            floatx16 acc;
+        for (int g = 0; g < ngroup; ++g) {
+            // lane holds S[row][n] for 16 rows of each of its two tiles;
+            // rows r = 8 h .. 8 h + 7 of tile u share local i = 4 wave + 2 u + h
+            const int s = g * kAdjGroup + sl;
+            float ax = 0.0f, ay = 0.0f;  // f = 0: (x, y) components; f = 1: z in ax
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+            for (int u = 0; u < 2; ++u) {
+                floatx16 acc;
 #pragma unroll
-            for (int k0 = 0; k0 < kBK; k0 += 2) {
-                const float av = gr[ca][k0 + kk];
-                const float bv = gzt[tile][n][k0 + kk];
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
-            }
-            // lane holds S[c][n] for 16 columns c; fold in the transverse factors
-            const int s = tile * kAdjTile + sl;
-            float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+                for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int c = 32 * mt + mfma_row(r, lane);
-                const int ci = c >> 3, cj = c & 7;
-                const float v = acc[r];
-                if (f == 0) {
-                    fx += gdx[s][ci] * gy[s][cj] * v;
-                    fy += gx[s][ci] * gdy[s][cj] * v;
-                } else {
-                    fz += gx[s][ci] * gy[s][cj] * v;
+                for (int m = 0; m < 16; ++m)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(u == 0 ? g0[m] : g1[m], gzt[g][n][16 * half + m], acc,
+                                                               0, 0, 0);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int i = 4 * wave + 2 * u + h;
+                    float sy = 0.0f, sdy = 0.0f;
+#pragma unroll
+                    for (int r = 8 * h; r < 8 * h + 8; ++r) {
+                        const int j = mfma_row(r, lane) & 15;
+                        sy += gy[s][j] * acc[r];
+                        sdy += gdy[s][j] * acc[r];
+                    }
+                    if (f == 0) {
+                        ax += gdx[s][i] * sy;
+                        ay += gx[s][i] * sdy;
+                    } else {
+                        ax += gx[s][i] * sy;
+                    }
                 }
             }
-            // lanes n and n + 16 (f = 0, 1) of each half carry the same atom
-            if (f == 0) {
-                red[tile][mt][half][sl][0] = fx;
-                red[tile][mt][half][sl][1] = fy;
-            } else {
-                red[tile][mt][half][sl][2] = fz;
-            }
+            red[wave][half][n][g][0] = ax;
+            red[wave][half][n][g][1] = ay;
         }
         __syncthreads();
-        for (int e = t; e < ns * 3; e += kSplatThreads) {
-            const int s2 = e / 3, x = e % 3;
-            const int tl = s2 / kAdjTile, st = s2 % kAdjTile;
-            const double v = (double(red[tl][0][0][st][x]) + double(red[tl][0][1][st][x])) +
-                             (double(red[tl][1][0][st][x]) + double(red[tl][1][1][st][x]));
+        // fixed-order sum over the 4 waves and 2 lane halves, in double
+        for (int e = t; e < ns * 3; e += kMThreads) {
+            const int s2 = e / 3, x = e - s2 * 3;
+            const int g = s2 / kAdjGroup, st = s2 - g * kAdjGroup;
+            const int nn = x == 2 ? kAdjGroup + st : st;
+            const int comp = x == 1 ? 1 : 0;
+            double v = 0.0;
+            for (int w = 0; w < 4; ++w) v += double(red[w][0][nn][g][comp]) + double(red[w][1][nn][g][comp]);
             const int64_t slot = off + c0 + s2;
             if (slot < a.capacity) a.bpart[slot * 3 + x] = v;
         }
@@ -231,13 +267,13 @@ __global__ __launch_bounds__(kSplatThreads) void k_adjoint_mfma(SplatArgs a)
 
 hipError_t run_gather_mfma(const SplatArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_splat_mfma, dim3(int(a.nbricks_total)), dim3(kSplatThreads), 0, s, a);
+    hipLaunchKernelGGL(k_splat_mfma, dim3(int(a.nbricks_total)), dim3(kMThreads), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t run_adjoint_mfma(const SplatArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_adjoint_mfma, dim3(int(a.nbricks_total)), dim3(kSplatThreads), 0, s, a);
+    hipLaunchKernelGGL(k_adjoint_mfma, dim3(int(a.nbricks_total)), dim3(kMThreads), 0, s, a);
     return hipGetLastError();
 }
 

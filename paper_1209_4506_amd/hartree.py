@@ -68,6 +68,12 @@ def _load():
         "hartree_splat_adjoint_bound": [vp, ctypes.c_uint64, vp, vp, vp],
         "hartree_profile_begin": [vp],
         "hartree_profile_end": [vp, P(d), P(i64)],
+        "hartree_graph_begin": [vp, vp],
+        "hartree_graph_end": [vp, vp],
+        "hartree_graph_launch": [vp, vp],
+        "hartree_plan_get_config": [vp, P(i32)],
+        "hartree_plan_set_config": [vp, P(i32)],
+        "hartree_plan_tune": [vp, vp, i32, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -87,7 +93,9 @@ EXPORTED = ["hartree_plan_create", "hartree_plan_create_batched", "hartree_plan_
             "hartree_plan_grid_offset", "hartree_workspace_size", "hartree_bind_workspace", "hartree_solve",
             "hartree_energy", "hartree_backward", "hartree_splat", "hartree_splat_adjoint",
             "hartree_device_status", "hartree_atoms_bind", "hartree_splat_bound", "hartree_splat_adjoint_bound",
-            "hartree_profile_begin", "hartree_profile_end", "hartree_last_error"]
+            "hartree_profile_begin", "hartree_profile_end", "hartree_graph_begin", "hartree_graph_end",
+            "hartree_graph_launch", "hartree_plan_get_config", "hartree_plan_set_config", "hartree_plan_tune",
+            "hartree_last_error"]
 
 # hartree_kernel_id order
 KERNELS = ["r2c", "r2c_bwd", "fft_b", "fft_a", "fft_a_bwd", "fft_a_eonly", "fft_b_inv", "c2r", "finalize",
@@ -303,6 +311,74 @@ class Plan:
 
     def dv(self):
         return [float(self.volumes[p] / (self.offsets[p + 1] - self.offsets[p])) for p in range(self.nprob)]
+
+    # ------------------------------------------------------------ pass shapes
+    def get_config(self):
+        """(nprob, 3, 2) int array: per problem and axis (a, b, c) the compiled
+        radix plan entry (-1: run-time radix kernel) and log2 pencils per tile."""
+        buf = (ctypes.c_int32 * (6 * self.nprob))()
+        _check(LIB.hartree_plan_get_config(self._h, buf))
+        return np.array(buf[:], dtype=np.int32).reshape(self.nprob, 3, 2)
+
+    def set_config(self, cfg):
+        cfg = np.ascontiguousarray(cfg, dtype=np.int32).reshape(-1)
+        if cfg.size != 6 * self.nprob:
+            raise ValueError("config needs %d entries" % (6 * self.nprob))
+        _check(LIB.hartree_plan_set_config(self._h, cfg.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+
+    def cache_key(self):
+        return "%s:%s" % (self.precision, ";".join("x".join(str(int(v)) for v in d) for d in self.dims))
+
+    def tune(self, reps=5, cache=None):
+        """Pick the fastest pass shapes on this device (see hartree_plan_tune).
+
+        ``cache``: path of a JSON file keyed by precision and grid sizes; a hit
+        applies the stored choice without timing, a miss tunes and stores it.
+        Returns the applied config."""
+        import json
+
+        key = self.cache_key()
+        table = {}
+        if cache is not None and os.path.exists(cache):
+            with open(cache) as fh:
+                table = json.load(fh)
+            if key in table:
+                self.set_config(table[key])
+                return self.get_config()
+        scratch = self.empty_grid()
+        _check(LIB.hartree_plan_tune(self._h, _ptr(scratch), int(reps), _stream(self.device)))
+        del scratch
+        cfg = self.get_config()
+        if cache is not None:
+            table[key] = cfg.reshape(-1).tolist()
+            with open(cache, "w") as fh:
+                json.dump(table, fh, indent=1, sort_keys=True)
+        return cfg
+
+    def capture(self, fn, stream=None):
+        """Run ``fn()`` once eagerly, then record it into the plan's HIP graph.
+
+        ``fn`` enqueues this plan's calls on the current stream and must write
+        only into preallocated tensors (``out=`` arguments): nothing may be
+        allocated while the stream is captured.  Capture runs on ``stream`` (a
+        new side stream by default); replay with :meth:`replay`.
+        """
+        fn()
+        s = stream or torch.cuda.Stream(self.device)
+        s.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(s):
+            h = ctypes.c_void_p(s.cuda_stream)
+            _check(LIB.hartree_graph_begin(self._h, h))
+            try:
+                fn()
+            finally:
+                code = LIB.hartree_graph_end(self._h, h)
+        _check(code)
+        torch.cuda.current_stream(self.device).wait_stream(s)
+
+    def replay(self, stream=None):
+        """Launch the captured graph on the current stream (or ``stream``)."""
+        _check(LIB.hartree_graph_launch(self._h, stream or _stream(self.device)))
 
 
 class HartreeFn(torch.autograd.Function):

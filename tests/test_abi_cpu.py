@@ -126,3 +126,34 @@ def test_every_smooth_length_gets_a_plan(lib):
             lib.hartree_plan_destroy(h)
     for n in (11, 13, 22, 4097, 4099):
         assert _create(lib, cube, (1, n, 1))[0] == 2
+
+
+def test_pass_config_validation(lib):
+    """Pass shapes: get returns one (plan, p_log2) per problem and axis; set
+    accepts the current choice and rejects ones that do not apply; tuning
+    needs a bound workspace (host-side checks only)."""
+    lib.hartree_last_error.restype = ctypes.c_char_p
+    for fn in ("hartree_plan_get_config", "hartree_plan_set_config", "hartree_plan_tune"):
+        getattr(lib, fn).restype = ctypes.c_int
+    for prec in (0, 1):
+        rc, h = _create(lib, np.diag([9.0, 10.0, 11.0]), (360, 60, 45), prec=prec)
+        assert rc == 0
+        cfg = (ctypes.c_int32 * 6)()
+        assert lib.hartree_plan_get_config(h, cfg) == 0
+        vals = list(cfg)
+        assert all(0 <= vals[2 * x + 1] <= 8 for x in range(3))
+        assert lib.hartree_plan_set_config(h, cfg) == 0          # the current choice round-trips
+        bad = (ctypes.c_int32 * 6)(*vals)
+        bad[1] = 9                                               # 512 pencils per workgroup
+        assert lib.hartree_plan_set_config(h, bad) == 1
+        bad = (ctypes.c_int32 * 6)(*vals)
+        bad[0] = 10_000                                          # no such compiled plan
+        assert lib.hartree_plan_set_config(h, bad) == 1
+        bad = (ctypes.c_int32 * 6)(*vals)
+        bad[4] = vals[0] if vals[0] >= 0 else 0                  # the 360 plan on the length-45 axis
+        assert lib.hartree_plan_set_config(h, bad) == 1
+        assert b"does not apply" in lib.hartree_last_error()
+        assert lib.hartree_plan_get_config(h, cfg) == 0
+        assert list(cfg) == vals                                 # rejected choices change nothing
+        assert lib.hartree_plan_tune(h, ctypes.c_void_p(1), 3, None) == 5   # no workspace bound
+        lib.hartree_plan_destroy(h)

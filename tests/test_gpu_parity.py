@@ -233,3 +233,40 @@ def test_bound_atoms_reuse(H):
     assert tok2 != tok
     with pytest.raises(H.HartreeError):
         plan.splat_bound(tok)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_tuned_plan_parity(H, oracle_mod, prec):
+    """After hartree_plan_tune (and a config round trip) the solve and the
+    backward still match the oracle; a batched plan tunes per length."""
+    cell = CELLS["ortho"]
+    dims = (45, 36, 40)
+    say("case tuned plan", prec, dims)
+    plan = H.Plan(cell, dims, precision=prec, max_atoms=1)
+    before = plan.get_config()
+    after = plan.tune(reps=2)
+    assert after.shape == before.shape
+    plan.set_config(after)
+    assert np.array_equal(plan.get_config(), after)
+    rho = inputs.random_grid(dims, 11).astype(np.float32 if prec == "fp32" else np.float64)
+    V, E = plan.solve(to_dev(rho, plan.dtype))
+    torch.cuda.synchronize()
+    V_o, _, e_recip, _ = oracle_mod.poisson(cell.reshape(9), rho.astype(np.float64))
+    assert rel_l2(V.double().cpu().numpy(), V_o) <= TOL[prec]["v"]
+    assert abs(float(E[0]) - e_recip) <= TOL[prec]["e"] * abs(e_recip)
+
+    say("case tuned batched plan", prec)
+    cells = np.stack([CELLS["ortho"], CELLS["cubic"], CELLS["ortho"]])
+    bdims = np.array([(45, 36, 40), (32, 32, 32), (36, 45, 21)])
+    bplan = H.Plan(cells, bdims, precision=prec, max_atoms=1)
+    bplan.tune(reps=2)
+    grids = [inputs.random_grid(tuple(d), 20 + i).astype(np.float32 if prec == "fp32" else np.float64)
+             for i, d in enumerate(bdims)]
+    Vb, Eb = bplan.solve(to_dev(np.concatenate([g.reshape(-1) for g in grids]), bplan.dtype))
+    torch.cuda.synchronize()
+    Vb = Vb.double().cpu().numpy()
+    for i, g in enumerate(grids):
+        V_o, _, e_recip, _ = oracle_mod.poisson(cells[i].reshape(9), g.astype(np.float64))
+        o0, o1 = bplan.offsets[i], bplan.offsets[i + 1]
+        assert rel_l2(Vb[o0:o1], V_o.reshape(-1)) <= TOL[prec]["v"]
+        assert abs(float(Eb[i]) - e_recip) <= TOL[prec]["e"] * abs(e_recip)
