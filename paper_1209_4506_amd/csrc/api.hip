@@ -401,14 +401,13 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
             d.nbricks[x] = (N[x] + bsz[x] - 1) / bsz[x];
             const double h = std::fabs(A[4 * x]) / N[x];
             const double w = std::floor(2.0 * p->cutoff * p->max_sigma / (h > 0 ? h : 1.0)) + 1.0;
-            // factor table row: the window width, or the whole axis when it wraps
-            const int64_t row = w < N[x] ? int64_t(w) : int64_t(N[x]);
-            if (row > wcap) wcap = row;
-            int64_t nbx = d.nbricks[x];
+            int64_t nbx = d.nbricks[x];  // most bricks one atom's window touches along x
             if (w < N[x]) {
                 const int64_t bnd = int64_t(std::ceil((w - 1.0) / bsz[x])) + 2;
                 if (bnd < nbx) nbx = bnd;
             }
+            // factor table row: one entry per point of the touched bricks
+            if (nbx * bsz[x] > wcap) wcap = nbx * bsz[x];
             per_atom *= nbx;
         }
         d.brick_off = bricks;

@@ -92,22 +92,20 @@ __global__ __launch_bounds__(256) void k_atom_tables(SplatArgs a)
     const int atom = int(e / (3 * rowlen));
     const AtomInfo in = a.info[atom];
     const ProbDesc &d = a.desc[in.prob];
-    const int n = d.dims[x];
+    const int n = d.dims[x], bsz = d.bsz[x];
     const int lo = in.lo[x], hi = in.hi[x];
-    if (hi < lo) return;
-    const int wl = hi - lo + 1;
+    int st, ct;
+    axis_bricks(lo, hi, n, bsz, d.nbricks[x], st, ct);
+    const int u = t / bsz;
+    if (u >= ct) return;  // never read
+    int sb = st + u;
+    if (sb >= d.nbricks[x]) sb -= d.nbricks[x];
+    const int ig = sb * bsz + (t - u * bsz);
     const double h = d.L[x] / n;
     T g = T(0), gd = T(0);
-    if (wl < n) {
-        if (t >= wl) return;
-        const double dd = double(lo + t) * h - in.X[x];
-        const T dt = T(dd);
-        g = expT<T>(-dt * dt * T(in.inv2s2));
-        gd = g * dt;
-    } else {
-        if (t >= n) return;
-        // every unwrapped index congruent to t inside the window
-        for (int ip = lo + wrapi(t - lo, n); ip <= hi; ip += n) {
+    if (ig < n) {
+        // every unwrapped index congruent to ig inside the window
+        for (int ip = lo + wrapi(ig - lo, n); ip <= hi; ip += n) {
             const double dd = double(ip) * h - in.X[x];
             const T dt = T(dd);
             const T ev = expT<T>(-dt * dt * T(in.inv2s2));
@@ -143,7 +141,7 @@ struct Touch {
 __device__ __forceinline__ Touch atom_touch(const AtomInfo &in, const ProbDesc &d)
 {
     Touch t;
-    for (int x = 0; x < 3; ++x) axis_bricks(in.lo[x], in.hi[x], d.dims[x], d.bsz[x], d.nbricks[x], t.st[x], t.ct[x]);
+    atom_bricks(in, d, t.st, t.ct);
     return t;
 }
 
@@ -309,6 +307,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_splat_gather(SplatArgs a, con
     const int bij = lb / d.nbricks[2];
     const int bj = bij % d.nbricks[1];
     const int bi = bij / d.nbricks[1];
+    const int nb0 = d.nbricks[0], nb1 = d.nbricks[1], nb2 = d.nbricks[2];
     const int t = threadIdx.x;
     const int ci = (t & 63) >> 3, cj = t & 7, strip = t >> 6;
     const int i = bi * kBI + ci, j = bj * kBJ + cj, k0 = bk * kBK + strip * kStrip;
@@ -328,13 +327,13 @@ __global__ __launch_bounds__(kBrickThreads) void k_splat_gather(SplatArgs a, con
             const int s = e / (kBI + kBJ + kBK), q = e % (kBI + kBJ + kBK);
             const StagedAtom &in = atoms[s];
             if (q < kBI) {
-                gx[s][q] = table_factor<T>(a, bi * kBI + q, d.dims[0], in, 0).x * T(in.w);
+                gx[s][q] = table_factor<T>(a, nb0, kBI, bi, q, in, 0).x * T(in.w);
             } else if (q < kBI + kBJ) {
                 const int qq = q - kBI;
-                gy[s][qq] = table_factor<T>(a, bj * kBJ + qq, d.dims[1], in, 1).x;
+                gy[s][qq] = table_factor<T>(a, nb1, kBJ, bj, qq, in, 1).x;
             } else {
                 const int qq = q - kBI - kBJ;
-                gz[s][qq] = table_factor<T>(a, bk * kBK + qq, d.dims[2], in, 2).x;
+                gz[s][qq] = table_factor<T>(a, nb2, kBK, bk, qq, in, 2).x;
             }
         }
         __syncthreads();
@@ -377,6 +376,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_splat_adjoint(SplatArgs a)
     const int bij = lb / d.nbricks[2];
     const int bj = bij % d.nbricks[1];
     const int bi = bij / d.nbricks[1];
+    const int nb0 = d.nbricks[0], nb1 = d.nbricks[1], nb2 = d.nbricks[2];
     const int t = threadIdx.x;
     const int ci = (t & 63) >> 3, cj = t & 7, strip = t >> 6;
     const int i = bi * kBI + ci, j = bj * kBJ + cj, k0 = bk * kBK + strip * kStrip;
@@ -401,17 +401,17 @@ __global__ __launch_bounds__(kBrickThreads) void k_splat_adjoint(SplatArgs a)
             const int s = e / (kBI + kBJ + kBK), q = e % (kBI + kBJ + kBK);
             const StagedAtom &in = atoms[s];
             if (q < kBI) {
-                const Cx<T> v = table_factor<T>(a, bi * kBI + q, d.dims[0], in, 0);
+                const Cx<T> v = table_factor<T>(a, nb0, kBI, bi, q, in, 0);
                 gx[s][q] = v.x;
                 gdx[s][q] = v.y;
             } else if (q < kBI + kBJ) {
                 const int qq = q - kBI;
-                const Cx<T> v = table_factor<T>(a, bj * kBJ + qq, d.dims[1], in, 1);
+                const Cx<T> v = table_factor<T>(a, nb1, kBJ, bj, qq, in, 1);
                 gy[s][qq] = v.x;
                 gdy[s][qq] = v.y;
             } else {
                 const int qq = q - kBI - kBJ;
-                const Cx<T> v = table_factor<T>(a, bk * kBK + qq, d.dims[2], in, 2);
+                const Cx<T> v = table_factor<T>(a, nb2, kBK, bk, qq, in, 2);
                 gz[s][qq] = v.x;
                 gdz[s][qq] = v.y;
             }

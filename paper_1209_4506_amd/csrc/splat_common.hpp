@@ -57,39 +57,25 @@ __device__ __forceinline__ float expT<float>(float x) { return expf(x); }
 template <>
 __device__ __forceinline__ double expT<double>(double x) { return exp(x); }
 
-// 1-D periodic Gaussian factor along one axis at wrapped index ig:
-// g = sum over unwrapped i' = ig (mod n) in [lo, hi] of exp(-(i' h - X)^2 / (2 s^2)),
-// gd = the same sum weighted by the displacement (i' h - X).  The exponent is
-// formed in double (positions near L lose digits in float) and evaluated in T.
-template <typename T, bool WITH_D>
-__device__ __forceinline__ void axis_factor_t(int ig, int n, double h, double X, int lo, int hi, double inv2s2, T &g,
-                                              T &gd)
-{
-    g = T(0);
-    gd = T(0);
-    if (hi < lo || ig >= n) return;
-    for (int ip = lo + wrapi(ig - lo, n); ip <= hi; ip += n) {
-        const double dd = double(ip) * h - X;
-        const T e = expT<T>(T(-dd * dd * inv2s2));
-        g += e;
-        if (WITH_D) gd += e * T(dd);
-    }
-}
+// Per-atom 1-D factor tables, built once per binding by k_atom_tables: for
+// atom a and axis x, row (a, x) holds (g, gd), the 1-D Gaussian factor and
+// its displacement-weighted sum, at every grid index of the bricks the atom's
+// window touches along x, brick by brick in touch order: entry
+// u * bsz + q belongs to brick (st + u) mod nbricks, point q of it (zero past
+// the end of the axis or outside the window).  A brick reads its bsz
+// consecutive entries without index arithmetic per point.
 
-// Per-atom 1-D factor tables, built once per call by k_atom_tables: for atom
-// a and axis x, entry t of row (a, x) holds (g, gd), the 1-D Gaussian factor
-// and its displacement-weighted sum,
-//   window narrower than the axis (wl < n): the single image at unwrapped
-//       index ip = lo + t, t < wl = hi - lo + 1;
-//   window as wide as the axis: every image at wrapped index t < n.
-// A brick reads the entries of its own index range from these rows.
-
-// One atom of a group staged in LDS: its table row and window.
+// One atom of a group staged in LDS: its table row and touched brick ranges.
 struct StagedAtom {
-    int idx;                 // atom index (table row)
-    int lo[3], low[3], wl[3];  // window start, start mod n, width (0: none)
-    double w;                // Z (2 pi s^2)^(-3/2)
+    int idx;           // atom index (table row)
+    int st[3], ct[3];  // first touched brick and number of touched bricks per axis
+    double w;          // Z (2 pi s^2)^(-3/2)
 };
+
+__device__ __forceinline__ void atom_bricks(const AtomInfo &in, const ProbDesc &d, int *st, int *ct)
+{
+    for (int x = 0; x < 3; ++x) axis_bricks(in.lo[x], in.hi[x], d.dims[x], d.bsz[x], d.nbricks[x], st[x], ct[x]);
+}
 
 // threads t < nc stage atoms list[c0 + t]
 __device__ __forceinline__ void stage_atoms(StagedAtom *dst, const SplatArgs &a, const ProbDesc &d, int64_t off,
@@ -100,31 +86,33 @@ __device__ __forceinline__ void stage_atoms(StagedAtom *dst, const SplatArgs &a,
         const AtomInfo in = a.info[atom];
         StagedAtom s;
         s.idx = atom;
-        for (int x = 0; x < 3; ++x) {
-            s.lo[x] = in.lo[x];
-            s.low[x] = wrapi(in.lo[x], d.dims[x]);
-            s.wl[x] = in.hi[x] >= in.lo[x] ? in.hi[x] - in.lo[x] + 1 : 0;
-        }
+        atom_bricks(in, d, s.st, s.ct);
         s.w = in.w;
         dst[t] = s;
     }
 }
 
-// (g, gd) of a staged atom at wrapped grid index ig along axis x
+// (g, gd) of a staged atom at point q of brick bidx along axis x, for an axis
+// of nbx bricks of bsz points (passed by value: kernels keep them in
+// registers rather than re-reading the problem descriptor).  The load is
+// unconditional (from the row start when the entry lies outside the window)
+// so that a thread's successive lookups need not wait for each other.
 template <typename T>
-__device__ __forceinline__ Cx<T> table_factor(const SplatArgs &a, int ig, int n, const StagedAtom &at, int x)
+__device__ __forceinline__ Cx<T> table_factor(const SplatArgs &a, int nbx, int bsz, int bidx, int q,
+                                              const StagedAtom &at, int x, bool use = true)
 {
-    const int wl = at.wl[x];
-    if (wl <= 0 || ig >= n) return Cx<T>{T(0), T(0)};
-    int t = ig;
-    if (wl < n) {
-        t = ig - at.low[x];
-        if (t < 0) t += n;
-        if (t >= wl) return Cx<T>{T(0), T(0)};
-    }
-    if (t >= a.wcap) return Cx<T>{T(0), T(0)};  // never for sigma <= max_sigma
+    // select by value: indexing st[] / ct[] with a run-time axis would
+    // put a copy of the struct in scratch memory
+    const int m0 = -int(x == 0), m1 = -int(x == 1), m2 = -int(x == 2);
+    const int st = (at.st[0] & m0) | (at.st[1] & m1) | (at.st[2] & m2);
+    const int ct = (at.ct[0] & m0) | (at.ct[1] & m1) | (at.ct[2] & m2);
+    int u = bidx - st;
+    if (u < 0) u += nbx;
+    const int e = u * bsz + q;
+    const bool ok = use && u < ct && e < a.wcap;
     const Cx<T> *tab = reinterpret_cast<const Cx<T> *>(a.tab);
-    return tab[(int64_t(at.idx) * 3 + x) * a.wcap + t];
+    const Cx<T> v = tab[(int64_t(at.idx) * 3 + x) * a.wcap + (ok ? e : 0)];
+    return ok ? v : Cx<T>{T(0), T(0)};
 }
 
 }  // namespace hartree

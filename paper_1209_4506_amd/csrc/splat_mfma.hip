@@ -41,19 +41,50 @@ constexpr int kAdjGroup = 16;    // atoms per MFMA column tile: 16 atoms x (g, g
 constexpr int kAdjGroups = kAdjChunk / kAdjGroup;
 constexpr int kRow = kMI + kMJ + kMK;  // table entries one atom needs in one brick
 
+// A brick's position and its problem's brick counts, kept in registers as
+// separate scalars (fields of a local struct selected by a run-time axis end
+// up in scratch memory).
 struct BrickPos {
-    int bi, bj, bk;
+    int b0, b1, b2;     // brick index along a, b, c
+    int nb0, nb1, nb2;  // bricks along a, b, c
+    // brick index and brick count along axis x, selected arithmetically
+    __device__ __forceinline__ void axis(int x, int &bidx, int &nbx) const
+    {
+        const int m0 = -int(x == 0), m1 = -int(x == 1), m2 = -int(x == 2);
+        bidx = (b0 & m0) | (b1 & m1) | (b2 & m2);
+        nbx = (nb0 & m0) | (nb1 & m1) | (nb2 & m2);
+    }
 };
 
 __device__ __forceinline__ BrickPos brick_pos(const ProbDesc &d, int64_t b)
 {
     const int lb = int(b - d.brick_off);  // bricks of one problem fit 32 bits
     BrickPos p;
-    p.bk = lb % d.nbricks[2];
-    const int bij = lb / d.nbricks[2];
-    p.bj = bij % d.nbricks[1];
-    p.bi = bij / d.nbricks[1];
+    p.nb0 = d.nbricks[0];
+    p.nb1 = d.nbricks[1];
+    p.nb2 = d.nbricks[2];
+    p.b2 = lb % p.nb2;
+    const int bij = lb / p.nb2;
+    p.b1 = bij % p.nb1;
+    p.b0 = bij / p.nb1;
     return p;
+}
+
+// Entry q (0 .. 63) of one atom's factor rows over this brick: q < 16 along
+// a, q < 32 along b, the rest along c.  A wavefront fills one atom per round,
+// lane = entry, and issues all its rounds' loads before storing any.
+static_assert(kRow == 64, "one table entry per lane");
+static_assert(kMI == kMJ, "a and b share one brick edge");
+
+__device__ __forceinline__ Cx<float> brick_entry(const SplatArgs &a, const BrickPos &p, const StagedAtom &at, int q,
+                                                 bool use)
+{
+    const int x = q < kMI ? 0 : (q < kMI + kMJ ? 1 : 2);
+    int bidx, nbx;
+    p.axis(x, bidx, nbx);
+    const int bsz = x == 2 ? kMK : kMI;
+    const int qq = q - (x == 0 ? 0 : (x == 1 ? kMI : kMI + kMJ));
+    return table_factor<float>(a, nbx, bsz, bidx, qq, at, x, use);
 }
 
 __global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
@@ -85,18 +116,28 @@ __global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
         const int npair = (ns + 1) >> 1;
         stage_atoms(atoms, a, d, off, c0, ns, t);
         __syncthreads();
-        for (int e = t; e < 2 * npair * kRow; e += kMThreads) {
-            const int s = e / kRow, q = e - s * kRow;
-            float v = 0.0f;
-            if (q < kMI) {
-                if (s < ns) v = table_factor<float>(a, p.bi * kMI + q, d.dims[0], atoms[s], 0).x * float(atoms[s].w);
-                gxw[s][q] = v;
-            } else if (q < kMI + kMJ) {
-                if (s < ns) v = table_factor<float>(a, p.bj * kMJ + (q - kMI), d.dims[1], atoms[s], 1).x;
-                gy[s][q - kMI] = v;
-            } else {
-                if (s < ns) v = table_factor<float>(a, p.bk * kMK + (q - kMI - kMJ), d.dims[2], atoms[s], 2).x;
-                gz[s][q - kMI - kMJ] = v;
+        {
+            constexpr int R = kSplatChunk / 4;  // rounds: atoms per wavefront
+            float v[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int s = wave + 4 * r;
+                const StagedAtom &at = atoms[s < ns ? s : 0];
+                float x = brick_entry(a, p, at, lane, s < ns).x;
+                if (lane < kMI) x *= float(at.w);
+                v[r] = x;
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int s = wave + 4 * r;
+                if (s < 2 * npair) {  // a padding atom gets zero rows
+                    if (lane < kMI)
+                        gxw[s][lane] = v[r];
+                    else if (lane < kMI + kMJ)
+                        gy[s][lane - kMI] = v[r];
+                    else
+                        gz[s][lane - kMI - kMJ] = v[r];
+                }
             }
         }
         __syncthreads();
@@ -110,14 +151,14 @@ __global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
         __syncthreads();
     }
     const float bg = a.subtract_background ? float(a.qsum[prob] / (d.L[0] * d.L[1] * d.L[2])) : 0.0f;
-    const int k = p.bk * kMK + col;
+    const int k = p.b2 * kMK + col;
     if (k >= d.dims[2]) return;
     float *out = reinterpret_cast<float *>(a.rho) + d.grid_off;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int c = mfma_row(r, lane);  // row within the tile: local i offset c / 16, j = c % 16
-        const int j = p.bj * kMJ + (c & 15);
-        const int ia = p.bi * kMI + 4 * wave + (c >> 4);
+        const int j = p.b1 * kMJ + (c & 15);
+        const int ia = p.b0 * kMI + 4 * wave + (c >> 4);
         if (j < d.dims[1]) {
             if (ia < d.dims[0]) out[(int64_t(ia) * d.dims[1] + j) * d.dims[2] + k] = acc0[r] - bg;
             if (ia + 2 < d.dims[0]) out[(int64_t(ia + 2) * d.dims[1] + j) * d.dims[2] + k] = acc1[r] - bg;
@@ -128,7 +169,7 @@ __global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
 // adjoint: wave w holds grad_rho of its two row tiles in registers; per
 // group of 16 staged atoms it forms S for both tiles (32 columns n = 16 f +
 // atom) and folds the transverse factors in.
-__global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_adjoint_mfma(SplatArgs a)
+__global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
 {
     __shared__ StagedAtom atoms[kAdjChunk];
     __shared__ float gx[kAdjChunk][kMI + 1], gdx[kAdjChunk][kMI + 1];
@@ -151,9 +192,9 @@ __global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     float g0[16], g1[16];
     {
         const float *src = reinterpret_cast<const float *>(a.grad_rho) + d.grid_off;
-        const int j = p.bj * kMJ + (col & 15);
-        const int ia = p.bi * kMI + 4 * wave + (col >> 4);
-        const int k0 = p.bk * kMK + 16 * half;
+        const int j = p.b1 * kMJ + (col & 15);
+        const int ia = p.b0 * kMI + 4 * wave + (col >> 4);
+        const int k0 = p.b2 * kMK + 16 * half;
         const bool jin = j < d.dims[1];
         const bool in0 = jin && ia < d.dims[0], in1 = jin && ia + 2 < d.dims[0];
         const int64_t r0 = (int64_t(ia) * d.dims[1] + j) * d.dims[2] + k0;
@@ -192,32 +233,46 @@ __global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         const int ngroup = (ns + kAdjGroup - 1) / kAdjGroup;
         stage_atoms(atoms, a, d, off, c0, ns, t);
         __syncthreads();
-        for (int e = t; e < ngroup * kAdjGroup * kRow; e += kMThreads) {
-            const int s = e / kRow, q = e - s * kRow;
-            Cx<float> v{0.0f, 0.0f};
-            if (q < kMI) {
-                if (s < ns) v = table_factor<float>(a, p.bi * kMI + q, d.dims[0], atoms[s], 0);
-                gx[s][q] = v.x;
-                gdx[s][q] = v.y;
-            } else if (q < kMI + kMJ) {
-                const int qq = q - kMI;
-                if (s < ns) v = table_factor<float>(a, p.bj * kMJ + qq, d.dims[1], atoms[s], 1);
-                gy[s][qq] = v.x;
-                gdy[s][qq] = v.y;
-            } else {
-                // padded atom slots give zero columns
-                const int qq = q - kMI - kMJ;
-                if (s < ns) v = table_factor<float>(a, p.bk * kMK + qq, d.dims[2], atoms[s], 2);
-                const int g = s / kAdjGroup, st = s - g * kAdjGroup;
-                gzt[g][st][qq] = v.x;
-                gzt[g][kAdjGroup + st][qq] = v.y;
+        {
+            constexpr int R = kAdjChunk / 4;  // rounds: atoms per wavefront
+            Cx<float> v[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int s = wave + 4 * r;
+                v[r] = brick_entry(a, p, atoms[s < ns ? s : 0], lane, s < ns);
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int s = wave + 4 * r;
+                if (s < ngroup * kAdjGroup) {  // padding atoms give zero columns
+                    if (lane < kMI) {
+                        gx[s][lane] = v[r].x;
+                        gdx[s][lane] = v[r].y;
+                    } else if (lane < kMI + kMJ) {
+                        gy[s][lane - kMI] = v[r].x;
+                        gdy[s][lane - kMI] = v[r].y;
+                    } else {
+                        const int g = s / kAdjGroup, st = s - g * kAdjGroup;
+                        gzt[g][st][lane - kMI - kMJ] = v[r].x;
+                        gzt[g][kAdjGroup + st][lane - kMI - kMJ] = v[r].y;
+                    }
+                }
             }
         }
         __syncthreads();
         for (int g = 0; g < ngroup; ++g) {
-            // lane holds S[row][n] for 16 rows of each of its two tiles;
-            // rows r = 8 h .. 8 h + 7 of tile u share local i = 4 wave + 2 u + h
+            // lane holds S[row][n] for 16 rows of each of its two tiles: row
+            // r of tile u is local i = 4 wave + 2 u + r / 8 and
+            // j = 8 ((r / 4) % 2) + 4 half + r % 4, so the eight j values (and
+            // their gy, gdy) are the same for both tiles and both halves r / 8
             const int s = g * kAdjGroup + sl;
+            float yv[8], dyv[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int j = mfma_row(r, lane) & 15;
+                yv[r] = gy[s][j];
+                dyv[r] = gdy[s][j];
+            }
             float ax = 0.0f, ay = 0.0f;  // f = 0: (x, y) components; f = 1: z in ax
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
@@ -233,10 +288,9 @@ __global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(4))) 
                     const int i = 4 * wave + 2 * u + h;
                     float sy = 0.0f, sdy = 0.0f;
 #pragma unroll
-                    for (int r = 8 * h; r < 8 * h + 8; ++r) {
-                        const int j = mfma_row(r, lane) & 15;
-                        sy += gy[s][j] * acc[r];
-                        sdy += gdy[s][j] * acc[r];
+                    for (int r = 0; r < 8; ++r) {
+                        sy += yv[r] * acc[8 * h + r];
+                        sdy += dyv[r] * acc[8 * h + r];
                     }
                     if (f == 0) {
                         ax += gdx[s][i] * sy;
