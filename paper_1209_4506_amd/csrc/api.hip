@@ -451,7 +451,7 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
         p->o_lists = take(4 * size_t(p->capacity));
         p->o_bpart = take(24 * size_t(p->capacity));
         p->o_slot = take(4 * size_t(p->capacity));
-        p->o_tab = take(2 * (p->fp64 ? 8 : 4) * size_t(p->max_atoms) * 3 * size_t(p->wcap));
+        if (p->fp64) p->o_tab = take(16 * size_t(p->max_atoms) * 3 * size_t(p->wcap));
         p->o_bsum = take(8 * size_t(p->nbricks / 4096 + 2));
     }
     p->ws_size = o;

@@ -492,11 +492,10 @@ hipError_t run_bin(const SplatArgs &a, hipStream_t s)
     const int nsb = int((nbt + kScanBlock - 1) / kScanBlock);
     if (a.natoms > 0) {
         hipLaunchKernelGGL(k_atom_prep, dim3(nb), dim3(256), 0, s, a);
+        // FP64 kernels read per-atom factor tables; the FP32 matrix-core
+        // kernels evaluate the factors themselves
         const int nt = int((int64_t(a.natoms) * 3 * a.wcap + 255) / 256);
-        if (a.fp64)
-            hipLaunchKernelGGL(k_atom_tables<double>, dim3(nt), dim3(256), 0, s, a);
-        else
-            hipLaunchKernelGGL(k_atom_tables<float>, dim3(nt), dim3(256), 0, s, a);
+        if (a.fp64) hipLaunchKernelGGL(k_atom_tables<double>, dim3(nt), dim3(256), 0, s, a);
         hipLaunchKernelGGL(k_brick_visit<0>, dim3(nw), dim3(256), 0, s, a);
     }
     hipLaunchKernelGGL(k_scan_sums, dim3(nsb), dim3(256), 0, s, a);

@@ -41,60 +41,118 @@ constexpr int kAdjGroup = 16;    // atoms per MFMA column tile: 16 atoms x (g, g
 constexpr int kAdjGroups = kAdjChunk / kAdjGroup;
 constexpr int kRow = kMI + kMJ + kMK;  // table entries one atom needs in one brick
 
-// A brick's position and its problem's brick counts, kept in registers as
-// separate scalars (fields of a local struct selected by a run-time axis end
-// up in scratch memory).
+// A brick's position (brick index per axis), kept in registers
 struct BrickPos {
-    int b0, b1, b2;     // brick index along a, b, c
-    int nb0, nb1, nb2;  // bricks along a, b, c
-    // brick index and brick count along axis x, selected arithmetically
-    __device__ __forceinline__ void axis(int x, int &bidx, int &nbx) const
-    {
-        const int m0 = -int(x == 0), m1 = -int(x == 1), m2 = -int(x == 2);
-        bidx = (b0 & m0) | (b1 & m1) | (b2 & m2);
-        nbx = (nb0 & m0) | (nb1 & m1) | (nb2 & m2);
-    }
+    int b0, b1, b2;
 };
 
 __device__ __forceinline__ BrickPos brick_pos(const ProbDesc &d, int64_t b)
 {
     const int lb = int(b - d.brick_off);  // bricks of one problem fit 32 bits
     BrickPos p;
-    p.nb0 = d.nbricks[0];
-    p.nb1 = d.nbricks[1];
-    p.nb2 = d.nbricks[2];
-    p.b2 = lb % p.nb2;
-    const int bij = lb / p.nb2;
-    p.b1 = bij % p.nb1;
-    p.b0 = bij / p.nb1;
+    p.b2 = lb % d.nbricks[2];
+    const int bij = lb / d.nbricks[2];
+    p.b1 = bij % d.nbricks[1];
+    p.b0 = bij / d.nbricks[1];
     return p;
 }
 
-// Entry q (0 .. 63) of one atom's factor rows over this brick: q < 16 along
-// a, q < 32 along b, the rest along c.  A wavefront fills one atom per round,
-// lane = entry, and issues all its rounds' loads before storing any.
-static_assert(kRow == 64, "one table entry per lane");
+// One atom staged for one brick.  The brick's 1-D factors are evaluated on
+// the fly: along axis x, brick point q has grid index g = b_x bsz_x + q and
+// lies at offset r = (r0 + q) mod n_x from the window start lo_x; its
+// unwrapped images are r, r + n_x, ... while inside the window width wl_x,
+// each with displacement d = r h_x - xb_x, xb_x = X_x - lo_x h_x (formed in
+// double, small), factor exp(-d^2 / (2 sigma^2)).
+struct StagedG {
+    float xb[3];
+    int r0[3];
+    int wl[3];  // 0 for an atom that touches nothing
+    float inv2s2;
+    float w;    // Z (2 pi s^2)^(-3/2)
+};
+
+// the problem's per-axis grid data, kept in registers
+struct AxisGrid {
+    int n0, n1, n2;
+    float h0, h1, h2;
+};
+
+__device__ __forceinline__ AxisGrid axis_grid(const ProbDesc &d)
+{
+    return {d.dims[0], d.dims[1], d.dims[2], float(d.L[0] / d.dims[0]), float(d.L[1] / d.dims[1]),
+            float(d.L[2] / d.dims[2])};
+}
+
+// threads t < nc stage atoms list[c0 + t] for brick p
+__device__ __forceinline__ void stage_g(StagedG *dst, const SplatArgs &a, const ProbDesc &d, const BrickPos &p,
+                                        int64_t off, int c0, int nc, int t)
+{
+    if (t < nc) {
+        const int atom = a.list_sorted[off + c0 + t];
+        const AtomInfo in = a.info[atom];
+        StagedG s;
+        const int bidx[3] = {p.b0, p.b1, p.b2};
+        const int bsz[3] = {kMI, kMJ, kMK};
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+            const int n = d.dims[x];
+            const double h = d.L[x] / n;
+            s.xb[x] = float(in.X[x] - in.lo[x] * h);
+            s.r0[x] = wrapi(bidx[x] * bsz[x] - in.lo[x], n);
+            s.wl[x] = in.hi[x] >= in.lo[x] ? in.hi[x] - in.lo[x] + 1 : 0;
+        }
+        s.inv2s2 = float(in.inv2s2);
+        s.w = float(in.w);
+        dst[t] = s;
+    }
+}
+
+// Entry q (0 .. 63) of one staged atom's factors over this brick: q < 16
+// along a, q < 32 along b, the rest along c; returns (g, gd) with gd the
+// displacement-weighted factor.  A wavefront fills one atom per round, lane =
+// entry.
+static_assert(kRow == 64, "one factor entry per lane");
 static_assert(kMI == kMJ, "a and b share one brick edge");
 
-__device__ __forceinline__ Cx<float> brick_entry(const SplatArgs &a, const BrickPos &p, const StagedAtom &at, int q,
+__device__ __forceinline__ Cx<float> brick_entry(const AxisGrid &ag, const BrickPos &p, const StagedG &at, int q,
                                                  bool use)
 {
     const int x = q < kMI ? 0 : (q < kMI + kMJ ? 1 : 2);
-    int bidx, nbx;
-    p.axis(x, bidx, nbx);
-    const int bsz = x == 2 ? kMK : kMI;
     const int qq = q - (x == 0 ? 0 : (x == 1 ? kMI : kMI + kMJ));
-    return table_factor<float>(a, nbx, bsz, bidx, qq, at, x, use);
+    // per-axis values selected with bit masks: a select chain over struct
+    // fields is turned into an indexed local array, i.e. scratch memory
+    const int m0 = -int(x == 0), m1 = -int(x == 1), m2 = -int(x == 2);
+    const int n = (ag.n0 & m0) | (ag.n1 & m1) | (ag.n2 & m2);
+    const float h = __int_as_float((__float_as_int(ag.h0) & m0) | (__float_as_int(ag.h1) & m1) |
+                                   (__float_as_int(ag.h2) & m2));
+    const int g = ((p.b0 * kMI) & m0) + ((p.b1 * kMJ) & m1) + ((p.b2 * kMK) & m2) + qq;
+    const float xb = __int_as_float((__float_as_int(at.xb[0]) & m0) | (__float_as_int(at.xb[1]) & m1) |
+                                    (__float_as_int(at.xb[2]) & m2));
+    const int r0 = (at.r0[0] & m0) | (at.r0[1] & m1) | (at.r0[2] & m2);
+    const int wl = (at.wl[0] & m0) | (at.wl[1] & m1) | (at.wl[2] & m2);
+    float gs = 0.0f, gds = 0.0f;
+    if (use && g < n) {
+        int r = r0 + qq;
+        if (r >= n) r -= n;
+        for (; r < wl; r += n) {
+            const float dd = float(r) * h - xb;
+            const float e = expf(-dd * dd * at.inv2s2);
+            gs += e;
+            gds += e * dd;
+        }
+    }
+    return Cx<float>{gs, gds};
 }
 
 __global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
 {
-    __shared__ StagedAtom atoms[kSplatChunk];
+    __shared__ StagedG atoms[kSplatChunk];
     __shared__ float gxw[kSplatChunk][kMI + 1], gy[kSplatChunk][kMJ + 1], gz[kSplatChunk][kMK + 1];
     const int64_t b = brick_of_block();
     const int prob = brick_prob(a, b);
     const ProbDesc &d = a.desc[prob];
     const BrickPos p = brick_pos(d, b);
+    const AxisGrid ag = axis_grid(d);
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
     const int64_t off = a.offsets[b];
@@ -114,7 +172,7 @@ __global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
     for (int c0 = 0; c0 < cnt; c0 += kSplatChunk) {
         const int ns = (cnt - c0) < kSplatChunk ? (cnt - c0) : kSplatChunk;
         const int npair = (ns + 1) >> 1;
-        stage_atoms(atoms, a, d, off, c0, ns, t);
+        stage_g(atoms, a, d, p, off, c0, ns, t);
         __syncthreads();
         {
             constexpr int R = kSplatChunk / 4;  // rounds: atoms per wavefront
@@ -122,9 +180,9 @@ __global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int s = wave + 4 * r;
-                const StagedAtom &at = atoms[s < ns ? s : 0];
-                float x = brick_entry(a, p, at, lane, s < ns).x;
-                if (lane < kMI) x *= float(at.w);
+                const StagedG &at = atoms[s < ns ? s : 0];
+                float x = brick_entry(ag, p, at, lane, s < ns).x;
+                if (lane < kMI) x *= at.w;
                 v[r] = x;
             }
 #pragma unroll
@@ -171,7 +229,7 @@ __global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
 // atom) and folds the transverse factors in.
 __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
 {
-    __shared__ StagedAtom atoms[kAdjChunk];
+    __shared__ StagedG atoms[kAdjChunk];
     __shared__ float gx[kAdjChunk][kMI + 1], gdx[kAdjChunk][kMI + 1];
     __shared__ float gy[kAdjChunk][kMJ + 1], gdy[kAdjChunk][kMJ + 1];
     __shared__ float gzt[kAdjGroups][2 * kAdjGroup][kMK + 1];  // per group: gz rows, then gdz rows
@@ -180,6 +238,7 @@ __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
     const int prob = brick_prob(a, b);
     const ProbDesc &d = a.desc[prob];
     const BrickPos p = brick_pos(d, b);
+    const AxisGrid ag = axis_grid(d);
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
     const int64_t off = a.offsets[b];
@@ -231,7 +290,7 @@ __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
     for (int c0 = 0; c0 < cnt; c0 += kAdjChunk) {
         const int ns = (cnt - c0) < kAdjChunk ? (cnt - c0) : kAdjChunk;
         const int ngroup = (ns + kAdjGroup - 1) / kAdjGroup;
-        stage_atoms(atoms, a, d, off, c0, ns, t);
+        stage_g(atoms, a, d, p, off, c0, ns, t);
         __syncthreads();
         {
             constexpr int R = kAdjChunk / 4;  // rounds: atoms per wavefront
@@ -239,7 +298,7 @@ __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int s = wave + 4 * r;
-                v[r] = brick_entry(a, p, atoms[s < ns ? s : 0], lane, s < ns);
+                v[r] = brick_entry(ag, p, atoms[s < ns ? s : 0], lane, s < ns);
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
