@@ -240,11 +240,12 @@ hartree_status hartree_graph_launch(hartree_plan plan, void *stream);
 
 /* Pass shapes: for every problem q and axis x (0 = a, 1 = b, 2 = c) a plan
  * uses a radix sequence (an entry of the library's compiled plan table, or -1
- * for the default factorization on the run-time radix kernel) and a tile of
- * 2^p_log2 pencils per workgroup.  cfg is a host array of nprob x 3 x 2 int32:
- * cfg[2 (3 q + x)] = plan entry, cfg[2 (3 q + x) + 1] = p_log2.  The choice
- * changes only the schedule and the rounding order of the FP32/FP64 sums, not
- * what is computed.
+ * for the default factorization on the run-time radix kernel), a tile of
+ * 2^p_log2 pencils per workgroup and, on the strided axes a and b, an LDS
+ * pitch of 2^p_log2 + pad complex values (pad 0 .. 3; 0 on axis c).  cfg is a
+ * host array of nprob x 3 x 3 int32: cfg[3 (3 q + x) + 0, 1, 2] = plan
+ * entry, p_log2, pad.  The choice changes only the schedule and the rounding
+ * order of the FP32/FP64 sums, not what is computed.
  *   hartree_plan_get_config  writes the current choice;
  *   hartree_plan_set_config  validates and applies one (HARTREE_ERR_ARG if an
  *                            entry does not factor the length, needs more

@@ -116,6 +116,7 @@ void unit_root(long t, long n, double &c, double &s)
 struct Launch {
     int plan;    // compiled radix plan (index in HARTREE_PLANS) or -1
     int p_log2;  // pencils per workgroup, log2
+    int pad;     // LDS pitch pad of strided tiles
     int maxn;    // longest pencil in the launch (sizes the LDS tile)
     TileList tl;
 };
@@ -139,10 +140,11 @@ struct hartree_plan_s {
     int64_t capacity = 0;
     std::vector<Launch> lr2c, lb, la;  // P1/P5 (axis c), P2/P4 (axis b), P3 (axis a)
     // per problem and axis (a, b, c): compiled radix plan (-1: run-time
-    // radix kernel) and log2 of the pencils per workgroup
+    // radix kernel), log2 of the pencils per workgroup, LDS pitch pad
     struct AxisCfg {
         int plan;
         int p_log2;
+        int pad;
     };
     std::vector<AxisCfg> cfg;
     int64_t max_parts = 0;  // E_H partial slots at one pencil per workgroup
@@ -197,10 +199,10 @@ bool is_smooth(int n)
     return n == 1;
 }
 
-void add_launch(std::vector<Launch> &v, int plan, int p_log2, int n, int prob, int tiles)
+void add_launch(std::vector<Launch> &v, int plan, int p_log2, int pad, int n, int prob, int tiles)
 {
     for (auto &l : v) {
-        if (l.plan == plan && l.p_log2 == p_log2 && l.tl.count < kMaxProb) {
+        if (l.plan == plan && l.p_log2 == p_log2 && l.pad == pad && l.tl.count < kMaxProb) {
             l.tl.prob[l.tl.count] = prob;
             l.tl.start[l.tl.count + 1] = l.tl.start[l.tl.count] + tiles;
             l.tl.count++;
@@ -213,6 +215,7 @@ void add_launch(std::vector<Launch> &v, int plan, int p_log2, int n, int prob, i
     std::memset(&l, 0, sizeof(l));
     l.plan = plan;
     l.p_log2 = p_log2;
+    l.pad = pad;
     l.maxn = n;
     l.tl.count = 1;
     l.tl.prob[0] = prob;
@@ -238,9 +241,9 @@ void rebuild_launches(hartree_plan p)
         const int64_t t1 = (rows + 2 * pc - 1) / (2 * pc);
         const int64_t t2 = int64_t(d.dims[0]) * ((d.dims[3] + pb - 1) / pb);
         const int64_t t3 = (int64_t(d.dims[1]) * d.dims[3] + pa - 1) / pa;
-        add_launch(p->lr2c, c[2].plan, c[2].p_log2, d.dims[2], q, int(t1));
-        add_launch(p->lb, c[1].plan, c[1].p_log2, d.dims[1], q, int(t2));
-        add_launch(p->la, c[0].plan, c[0].p_log2, d.dims[0], q, int(t3));
+        add_launch(p->lr2c, c[2].plan, c[2].p_log2, c[2].pad, d.dims[2], q, int(t1));
+        add_launch(p->lb, c[1].plan, c[1].p_log2, c[1].pad, d.dims[1], q, int(t2));
+        add_launch(p->la, c[0].plan, c[0].p_log2, c[0].pad, d.dims[0], q, int(t3));
         d.part_off = p->nparts;
         d.nparts = int(t3);
         p->nparts += int(t3);
@@ -383,12 +386,20 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
                 return fail(HARTREE_ERR_DIMS, "problem %d: length %d needs more threads per pencil than a workgroup has",
                             q, N[x]);
             }
-            p->cfg.push_back({find_plan(d.ax[x].radix, d.ax[x].nstages), lp});
+            // strided axes: the LDS pitch pad with the fewest modelled bank
+            // conflicts, among those no larger in LDS than a pad of one
+            int pad = 0;
+            if (x < 2) {
+                pad = pass_default_pad(p->fp64, N[x], d.ax[x].radix, d.ax[x].nstages, lp);
+                if (pass_tile_lds(p->fp64, N[x], lp, pad) > pass_tile_lds(p->fp64, N[x], lp, 1)) pad = 1;
+            }
+            p->cfg.push_back({find_plan(d.ax[x].radix, d.ax[x].nstages), lp, pad});
         }
         // tile counts at one pencil per workgroup bound every choice
         const int64_t rows = int64_t(N[0]) * N[1];
+        // (pass kernels also index one problem's half spectrum with 32-bit offsets)
         if ((rows + 1) / 2 > (1 << 30) || int64_t(N[0]) * d.dims[3] > (1 << 30) ||
-            int64_t(N[1]) * d.dims[3] > (1 << 30)) {
+            int64_t(N[1]) * d.dims[3] > (1 << 30) || rows * d.dims[3] >= (int64_t(1) << 31)) {
             delete p;
             return fail(HARTREE_ERR_DIMS, "problem %d: grid too large", q);
         }
@@ -525,7 +536,7 @@ hipError_t run_group(hartree_plan p, const std::vector<Launch> &groups, PassKind
     return timed(p, kernel_id(kind), s, [&]() {
         for (const Launch &l : groups) {
             a.tl = l.tl;
-            hipError_t e = run_pass(p->fp64, kind, l.plan, l.p_log2, l.maxn, l.tl.total, s, a);
+            hipError_t e = run_pass(p->fp64, kind, l.plan, l.p_log2, l.pad, l.maxn, l.tl.total, s, a);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -941,9 +952,10 @@ size_t lds_cap()
     return cap;
 }
 
-// radices of an axis choice for length n (plan < 0: the default
-// factorization on the run-time radix kernel); false if it does not apply
-bool choice_radices(hartree_plan p, int n, int plan, int p_log2, std::vector<int> &r)
+// radices of an axis choice for length n along axis x (plan < 0: the
+// default factorization on the run-time radix kernel); false if it does not
+// apply.  The pad applies to the strided axes a and b only.
+bool choice_radices(hartree_plan p, int x, int n, int plan, int p_log2, int pad, std::vector<int> &r)
 {
     r.clear();
     if (plan >= 0) {
@@ -960,9 +972,10 @@ bool choice_radices(hartree_plan p, int n, int plan, int p_log2, std::vector<int
         return false;
     }
     if (p_log2 < 0 || p_log2 > 8) return false;
+    if (pad < 0 || pad > 3 || (x == 2 && pad != 0)) return false;
     const int tpp = pass_min_tpp(p->fp64, n, r.data(), int(r.size()));
     if ((256 >> p_log2) < tpp) return false;  // 256 threads per pass workgroup
-    return pass_tile_lds(p->fp64, n, p_log2) <= lds_cap();
+    return pass_tile_lds(p->fp64, n, p_log2, pad) <= lds_cap();
 }
 
 void set_axis(ProbDesc &d, int x, const std::vector<int> &r)
@@ -990,21 +1003,23 @@ hartree_status upload_desc(hartree_plan p)
     return e == hipSuccess ? HARTREE_OK : hip_fail(e, "uploading problem descriptors");
 }
 
-// apply per-(problem, axis) choices (plan, p_log2) after validating all
+// apply per-(problem, axis) choices (plan, p_log2, pad) after validating all
 hartree_status apply_config(hartree_plan p, const int32_t *cfg)
 {
     std::vector<std::vector<int>> rad(3 * p->nprob);
     for (int q = 0; q < p->nprob; ++q)
         for (int x = 0; x < 3; ++x) {
-            const int plan = cfg[2 * (3 * q + x)], lp = cfg[2 * (3 * q + x) + 1];
-            if (!choice_radices(p, p->desc[q].dims[x], plan, lp, rad[3 * q + x]))
-                return fail(HARTREE_ERR_ARG, "problem %d axis %d: plan %d with 2^%d pencils does not apply to length %d",
-                            q, x, plan, lp, p->desc[q].dims[x]);
+            const int32_t *c = cfg + 3 * (3 * q + x);
+            if (!choice_radices(p, x, p->desc[q].dims[x], c[0], c[1], c[2], rad[3 * q + x]))
+                return fail(HARTREE_ERR_ARG,
+                            "problem %d axis %d: plan %d with 2^%d pencils and pad %d does not apply to length %d", q,
+                            x, c[0], c[1], c[2], p->desc[q].dims[x]);
         }
     for (int q = 0; q < p->nprob; ++q)
         for (int x = 0; x < 3; ++x) {
+            const int32_t *c = cfg + 3 * (3 * q + x);
             set_axis(p->desc[q], x, rad[3 * q + x]);
-            p->cfg[3 * q + x] = {cfg[2 * (3 * q + x)], cfg[2 * (3 * q + x) + 1]};
+            p->cfg[3 * q + x] = {c[0], c[1], c[2]};
         }
     rebuild_launches(p);
     return upload_desc(p);
@@ -1012,10 +1027,11 @@ hartree_status apply_config(hartree_plan p, const int32_t *cfg)
 
 void get_config(hartree_plan p, std::vector<int32_t> &cfg)
 {
-    cfg.resize(6 * size_t(p->nprob));
+    cfg.resize(9 * size_t(p->nprob));
     for (size_t i = 0; i < p->cfg.size(); ++i) {
-        cfg[2 * i] = p->cfg[i].plan;
-        cfg[2 * i + 1] = p->cfg[i].p_log2;
+        cfg[3 * i] = p->cfg[i].plan;
+        cfg[3 * i + 1] = p->cfg[i].p_log2;
+        cfg[3 * i + 2] = p->cfg[i].pad;
     }
 }
 
@@ -1079,20 +1095,26 @@ hartree_status hartree_plan_tune(hartree_plan plan, void *scratch, int32_t reps,
             if (std::find(lengths.begin(), lengths.end(), plan->desc[q].dims[x]) == lengths.end())
                 lengths.push_back(plan->desc[q].dims[x]);
         for (int n : lengths) {
-            std::vector<std::pair<int, int>> cand;
+            struct Cand {
+                int id, lp, pad;
+            };
+            std::vector<Cand> cand;
             std::vector<int> r;
             for (int id = -1; id < plan_table_size(); ++id)
                 for (int lp = 0; lp <= 6; ++lp)
-                    if (choice_radices(plan, n, id, lp, r) && (id >= 0 || find_plan(r.data(), int(r.size())) < 0))
-                        cand.push_back({id, lp});
+                    for (int pad = 0; pad <= (x == 2 ? 0 : 2); ++pad)
+                        if (choice_radices(plan, x, n, id, lp, pad, r) &&
+                            (id >= 0 || find_plan(r.data(), int(r.size())) < 0))
+                            cand.push_back({id, lp, pad});
             float best = 0.0f;
             std::vector<int32_t> best_cfg = cfg;
             for (const auto &c : cand) {
                 std::vector<int32_t> trial = cfg;
                 for (int q = 0; q < plan->nprob; ++q)
                     if (plan->desc[q].dims[x] == n) {
-                        trial[2 * (3 * q + x)] = c.first;
-                        trial[2 * (3 * q + x) + 1] = c.second;
+                        trial[3 * (3 * q + x)] = c.id;
+                        trial[3 * (3 * q + x) + 1] = c.lp;
+                        trial[3 * (3 * q + x) + 2] = c.pad;
                     }
                 if (apply_config(plan, trial.data()) != HARTREE_OK) continue;
                 hipError_t e = run_axis(plan, x, scratch, s);  // warm-up (and attribute opt-in)

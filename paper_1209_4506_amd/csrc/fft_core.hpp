@@ -237,24 +237,27 @@ struct LdsRow {
     }
 };
 
-// element i of a strided pencil in global memory (zero beyond the tile edge)
+// element i of a strided pencil in global memory.  A pencil beyond the tile
+// edge (valid false) points at a valid pencil of the tile: it loads real
+// data, is transformed like the others, and stores nothing.  Offsets within
+// one problem's spectrum fit 32 bits (the host limits its size).
 template <typename T>
 struct GlobalPencil {
     static constexpr bool kLds = false;
     Cx<T> *ptr;
-    int64_t stride;
+    int stride;
     bool valid;
     bool cj;
     __device__ __forceinline__ Cx<T> load(int i) const
     {
-        Cx<T> v = valid ? ptr[int64_t(i) * stride] : Cx<T>{T(0), T(0)};
+        Cx<T> v = ptr[i * stride];
         if (cj) v.y = -v.y;
         return v;
     }
     __device__ __forceinline__ void store(int i, Cx<T> v) const
     {
         if (cj) v.y = -v.y;
-        if (valid) ptr[int64_t(i) * stride] = v;
+        if (valid) ptr[i * stride] = v;
     }
 };
 
@@ -303,6 +306,42 @@ __device__ __forceinline__ void stage(const Src &src, Dst &dst, const Cx<T> *tw,
             const int base = jd * ns * R + k;
 #pragma unroll
             for (int q = 0; q < R; ++q) dst.store(base + q * ns, v[m][q]);
+        }
+    }
+}
+
+// The same stage with the length, the stride of its outputs (ns, the
+// product of the earlier radices) and its twiddle stride known at compile
+// time (the compiled radix plans): index arithmetic folds into constants.
+template <typename T, int R, int MAXB, bool FIRST, bool SYNC, int NB, int NS, int TWS, typename Src, typename Dst>
+__device__ __forceinline__ void stage_ct(const Src &src, Dst &dst, const Cx<T> *tw, int tip, int tpp)
+{
+    Cx<T> v[MAXB][R];
+#pragma unroll
+    for (int m = 0; m < MAXB; ++m) {
+        const int j = tip + m * tpp;
+        if (j < NB) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) v[m][q] = src.load(j + q * NB);
+        }
+    }
+    if (SYNC) __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MAXB; ++m) {
+        const int j = tip + m * tpp;
+        if (j < NB) {
+            // the first stage has NS = 1: k = 0 and no twiddles
+            const int jd = j / NS;
+            const int k = j - jd * NS;
+            if (!FIRST) {
+                const int tstep = k * TWS;
+#pragma unroll
+                for (int q = 1; q < R; ++q) v[m][q] = cmul(v[m][q], tw[q * tstep]);
+            }
+            butterfly<T, R, false>(v[m]);
+            const int base = jd * (NS * R) + k;
+#pragma unroll
+            for (int q = 0; q < R; ++q) dst.store(base + q * NS, v[m][q]);
         }
     }
 }
@@ -369,24 +408,29 @@ __device__ __forceinline__ void fft_static(const Src &src, Dst &dst, const L &ld
                                            const AxisPlan &ap, int tip, int tpp)
 {
     constexpr int S = (R0 > 0) + (R1 > 0) + (R2 > 0) + (R3 > 0);
-    const int n = ap.n;
+    constexpr int N = R0 * (R1 > 0 ? R1 : 1) * (R2 > 0 ? R2 : 1) * (R3 > 0 ? R3 : 1);
+    // stage s: ns = product of the earlier radices, twiddle stride n / (ns R)
+    constexpr int NS1 = R0, NS2 = R0 * (R1 > 0 ? R1 : 1), NS3 = NS2 * (R2 > 0 ? R2 : 1);
+    constexpr int Q1 = R1 > 0 ? R1 : 1, Q2 = R2 > 0 ? R2 : 1, Q3 = R3 > 0 ? R3 : 1;
+    (void)ap;
     L l = lds;
     l.cj = false;
-    stage<T, R0, stage_maxb<T>(R0), true, Src::kLds>(src, l, tw, n, ap.twstride[0], ap.ns[0], tip, tpp);
+    stage_ct<T, R0, stage_maxb<T>(R0), true, Src::kLds, N / R0, 1, 1>(src, l, tw, tip, tpp);
     __syncthreads();
     if constexpr (S == 1) {
-        for (int i = tip; i < n; i += tpp) dst.store(i, l.load(i));
+        for (int i = tip; i < N; i += tpp) dst.store(i, l.load(i));
     } else if constexpr (S == 2) {
-        stage<T, R1, stage_maxb<T>(R1), false, Dst::kLds>(l, dst, tw, n, ap.twstride[1], ap.ns[1], tip, tpp);
+        stage_ct<T, Q1, stage_maxb<T>(Q1), false, Dst::kLds, N / Q1, NS1, N / (NS1 * Q1)>(l, dst, tw, tip, tpp);
     } else {
-        stage<T, R1, stage_maxb<T>(R1), false, true>(l, l, tw, n, ap.twstride[1], ap.ns[1], tip, tpp);
+        stage_ct<T, Q1, stage_maxb<T>(Q1), false, true, N / Q1, NS1, N / (NS1 * Q1)>(l, l, tw, tip, tpp);
         __syncthreads();
         if constexpr (S == 3) {
-            stage<T, R2, stage_maxb<T>(R2), false, Dst::kLds>(l, dst, tw, n, ap.twstride[2], ap.ns[2], tip, tpp);
+            stage_ct<T, Q2, stage_maxb<T>(Q2), false, Dst::kLds, N / Q2, NS2, N / (NS2 * Q2)>(l, dst, tw, tip, tpp);
         } else {
-            stage<T, R2, stage_maxb<T>(R2), false, true>(l, l, tw, n, ap.twstride[2], ap.ns[2], tip, tpp);
+            stage_ct<T, Q2, stage_maxb<T>(Q2), false, true, N / Q2, NS2, N / (NS2 * Q2)>(l, l, tw, tip, tpp);
             __syncthreads();
-            stage<T, R3, stage_maxb<T>(R3), false, Dst::kLds>(l, dst, tw, n, ap.twstride[3], ap.ns[3], tip, tpp);
+            stage_ct<T, Q3, stage_maxb<T>(Q3), false, Dst::kLds, N / Q3, NS3, N / (NS3 * Q3)>(l, dst, tw, tip,
+                                                                                               tpp);
         }
     }
 }

@@ -45,11 +45,62 @@ int pass_min_tpp(int fp64, int n, const int *radix, int nstages)
     return tpp;
 }
 
-size_t pass_tile_lds(int fp64, int n, int p_log2)
+size_t pass_tile_lds(int fp64, int n, int p_log2, int pad)
 {
     const size_t P = size_t(1) << p_log2, cx = fp64 ? 16 : 8;
-    const size_t tile = (P + 1) * n > P * (n + 31) ? (P + 1) * n : P * (n + 31);
-    return cx * (tile + n);
+    const size_t strided = (P + size_t(pad)) * n, rows = P * (n + 31);
+    return cx * ((strided > rows ? strided : rows) + n);
+}
+
+// Bank-conflict model of the strided tiles (element (i, p) at i (P + pad) + p):
+// for every LDS access of every stage, the passes a wavefront needs on 64
+// banks of 4 bytes, relative to the conflict-free count.
+static double strided_lds_cost(int fp64, int n, const int *radix, int nstages, int p_log2, int pad)
+{
+    const int P = 1 << p_log2, tpp = kPassThreads >> p_log2, pitch = P + pad, wpe = fp64 ? 4 : 2;
+    double total = 0.0, ideal = 0.0;
+    int ns = 1;
+    int count[64];
+    for (int st = 0; st < nstages; ++st) {
+        const int R = radix[st], nb = n / R, maxb = (nb + tpp - 1) / tpp;
+        for (int wave = 0; wave < kPassThreads / 64; ++wave)
+            for (int m = 0; m < maxb; ++m)
+                for (int dir = 0; dir < 2; ++dir)
+                    for (int q = 0; q < R; ++q) {
+                        for (int b = 0; b < 64; ++b) count[b] = 0;
+                        int lanes = 0;
+                        for (int l = 0; l < 64; ++l) {
+                            const int tid = wave * 64 + l, p = tid & (P - 1), tip = tid >> p_log2;
+                            const int j = tip + m * tpp;
+                            if (j >= nb) continue;
+                            const int i = dir == 0 ? j + q * nb : (j / ns) * ns * R + j % ns + q * ns;
+                            const long w0 = long(i * pitch + p) * wpe;
+                            for (int k = 0; k < wpe; ++k) count[(w0 + k) & 63] += 1;
+                            ++lanes;
+                        }
+                        if (!lanes) continue;
+                        int mx = 0;
+                        for (int b = 0; b < 64; ++b) mx = count[b] > mx ? count[b] : mx;
+                        total += mx;
+                        ideal += (lanes * wpe + 63) / 64;
+                    }
+        ns *= R;
+    }
+    return ideal > 0.0 ? total / ideal : 1.0;
+}
+
+int pass_default_pad(int fp64, int n, const int *radix, int nstages, int p_log2)
+{
+    int best = 1;
+    double cbest = 0.0;
+    for (int pad = 0; pad <= 3; ++pad) {
+        const double c = strided_lds_cost(fp64, n, radix, nstages, p_log2, pad);
+        if (pad == 0 || c < cbest - 1e-9) {
+            cbest = c;
+            best = pad;
+        }
+    }
+    return best;
 }
 
 int pass_p_log2(int fp64, int n, const int *radix, int nstages, int max_p)
@@ -94,13 +145,14 @@ int find_plan(const int *radix, int nstages)
     return -1;
 }
 
-hipError_t run_pass(int fp64, PassKind kind, int plan, int p_log2, int maxn, int grid, hipStream_t s,
+hipError_t run_pass(int fp64, PassKind kind, int plan, int p_log2, int pad, int maxn, int grid, hipStream_t s,
                     const PassArgs &a0)
 {
     PassArgs a = a0;
     a.mode = 0;
     a.inv = 0;
     a.p_log2 = p_log2;
+    a.pad = pad;
     switch (kind) {
     case PASS_R2C_FWD: return fp64 ? run_r2c_f64(plan, maxn, grid, s, a) : run_r2c_f32(plan, maxn, grid, s, a);
     case PASS_R2C_BWD:

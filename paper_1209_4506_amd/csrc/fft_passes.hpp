@@ -246,7 +246,7 @@ template <typename T, int R0, int R1, int R2, int R3>
 __global__ __launch_bounds__(256) void k_fft_b(PassArgs a)
 {
     constexpr int NT = kPassThreads;
-    const int P = 1 << a.p_log2, TPP = NT >> a.p_log2, PP = P + 1;
+    const int P = 1 << a.p_log2, TPP = NT >> a.p_log2, PP = P + a.pad;
     extern __shared__ __align__(16) unsigned char smem[];
     int prob, tile;
     find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(256) void k_fft_b(PassArgs a)
     load_twiddles(tw, reinterpret_cast<const Cx<T> *>(a.tw) + d.ax[1].tw_off, n, tid, NT);
     __syncthreads();
     const int p = tid & (P - 1), tip = tid >> a.p_log2;
-    Cx<T> *g = reinterpret_cast<Cx<T> *>(a.spec) + d.spec_off + int64_t(outer) * n * nh + h0 + p;
+    Cx<T> *g = reinterpret_cast<Cx<T> *>(a.spec) + d.spec_off + int64_t(outer) * n * nh + h0 + (p < valid ? p : 0);
     GlobalPencil<T> gp{g, nh, p < valid, a.inv != 0};
     const LdsPencil<T> lp{buf, PP, p, false};
     fft_any<T, R0, R1, R2, R3>(gp, gp, lp, tw, d.ax[1], tip, TPP);
@@ -375,7 +375,7 @@ template <typename T, int R0, int R1, int R2, int R3>
 __global__ __launch_bounds__(256) void k_fft_a(PassArgs a)
 {
     constexpr int NT = kPassThreads;
-    const int P = 1 << a.p_log2, TPP = NT >> a.p_log2, PP = P + 1;
+    const int P = 1 << a.p_log2, TPP = NT >> a.p_log2, PP = P + a.pad;
     const int mode = a.mode;
     const bool energy = mode != 1;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -396,7 +396,7 @@ __global__ __launch_bounds__(256) void k_fft_a(PassArgs a)
     const int col = col0 + (p < valid ? p : 0);
     const int mb = int(fdiv(uint32_t(col), d.div_nh));
     const int mc = col - mb * nh;
-    Cx<T> *g = reinterpret_cast<Cx<T> *>(a.spec) + d.spec_off + col0 + p;
+    Cx<T> *g = reinterpret_cast<Cx<T> *>(a.spec) + d.spec_off + col;
     GlobalPencil<T> gp{g, ncol, p < valid, false};
     const LdsPencil<T> lp{buf, PP, p, false};
     KernelMultiply<T> km{buf, PP, p, &d, mb, mc, energy && p < valid, T(d.inv_n),
@@ -461,16 +461,16 @@ static hipError_t launch_pass(F kern, int grid, size_t lds, hipStream_t s, const
 
 // A launcher runs plan < 0 through the run-time radix kernel and otherwise
 // entry `plan` of HARTREE_PLANS.  The LDS holds the tile and its twiddle
-// table: n (P + 1) + n complex values.
+// table: n (P + pad) + n complex values.
 typedef hipError_t (*PassLaunchFn)(int grid, size_t lds, hipStream_t s, const PassArgs &a);
 
 template <typename T>
 inline size_t pass_lds_bytes(const PassArgs &a, int maxn)
 {
-    // strided tiles n (P + 1); pencil-major tiles P row_pitch(n) <= P (n + 31)
+    // strided tiles n (P + pad); pencil-major tiles P row_pitch(n) <= P (n + 31)
     const size_t P = size_t(1) << a.p_log2;
-    const size_t tile_elems = (P + 1) * maxn > P * (maxn + 31) ? (P + 1) * maxn : P * (maxn + 31);
-    return sizeof(Cx<T>) * (tile_elems + maxn);
+    const size_t strided = (P + size_t(a.pad)) * maxn, rows = P * (maxn + 31);
+    return sizeof(Cx<T>) * ((strided > rows ? strided : rows) + maxn);
 }
 
 }  // namespace hartree

@@ -36,16 +36,18 @@ struct PassArgs {
     int32_t mode;          // P1: 0 forward, 1 backward;  P3: 0 energy + potential, 1 potential, 2 energy
     int32_t inv;           // P2/P4: 1 for the inverse transform
     int32_t p_log2;        // pencils per workgroup, log2
+    int32_t pad;           // strided tiles (P2-P4): LDS pitch P + pad complex values per pencil element
     TileList tl;
 };
 
 int pass_p_log2(int fp64, int n, const int *radix, int nstages, int max_p);
 int pass_min_tpp(int fp64, int n, const int *radix, int nstages);
-size_t pass_tile_lds(int fp64, int n, int p_log2);
+size_t pass_tile_lds(int fp64, int n, int p_log2, int pad);
+int pass_default_pad(int fp64, int n, const int *radix, int nstages, int p_log2);
 int find_plan(const int *radix, int nstages);
 int plan_table_size();
 int plan_table_row(int id, int *radix);  // fills radix[4], returns the stage count
-hipError_t run_pass(int fp64, PassKind kind, int plan, int p_log2, int maxn, int grid, hipStream_t s,
+hipError_t run_pass(int fp64, PassKind kind, int plan, int p_log2, int pad, int maxn, int grid, hipStream_t s,
                     const PassArgs &a);
 hipError_t run_finalize(const ProbDesc *desc, const double *partials, double *e_h, int nprob, hipStream_t s);
 hipError_t run_zero(void *p, size_t bytes, hipStream_t s);

@@ -184,6 +184,8 @@ class Plan:
         return self
 
     def __del__(self):
+        if LIB is None:  # interpreter shutdown
+            return
         h = getattr(self, "_h", None)
         if h is not None and h.value:
             LIB.hartree_plan_destroy(h)
@@ -314,16 +316,17 @@ class Plan:
 
     # ------------------------------------------------------------ pass shapes
     def get_config(self):
-        """(nprob, 3, 2) int array: per problem and axis (a, b, c) the compiled
-        radix plan entry (-1: run-time radix kernel) and log2 pencils per tile."""
-        buf = (ctypes.c_int32 * (6 * self.nprob))()
+        """(nprob, 3, 3) int array: per problem and axis (a, b, c) the compiled
+        radix plan entry (-1: run-time radix kernel), log2 pencils per tile and
+        the LDS pitch pad of the strided axes."""
+        buf = (ctypes.c_int32 * (9 * self.nprob))()
         _check(LIB.hartree_plan_get_config(self._h, buf))
-        return np.array(buf[:], dtype=np.int32).reshape(self.nprob, 3, 2)
+        return np.array(buf[:], dtype=np.int32).reshape(self.nprob, 3, 3)
 
     def set_config(self, cfg):
         cfg = np.ascontiguousarray(cfg, dtype=np.int32).reshape(-1)
-        if cfg.size != 6 * self.nprob:
-            raise ValueError("config needs %d entries" % (6 * self.nprob))
+        if cfg.size != 9 * self.nprob:
+            raise ValueError("config needs %d entries" % (9 * self.nprob))
         _check(LIB.hartree_plan_set_config(self._h, cfg.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
 
     def cache_key(self):

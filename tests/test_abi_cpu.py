@@ -138,20 +138,20 @@ def test_pass_config_validation(lib):
     for prec in (0, 1):
         rc, h = _create(lib, np.diag([9.0, 10.0, 11.0]), (360, 60, 45), prec=prec)
         assert rc == 0
-        cfg = (ctypes.c_int32 * 6)()
+        cfg = (ctypes.c_int32 * 9)()
         assert lib.hartree_plan_get_config(h, cfg) == 0
         vals = list(cfg)
-        assert all(0 <= vals[2 * x + 1] <= 8 for x in range(3))
+        assert all(0 <= vals[3 * x + 1] <= 8 for x in range(3))
+        assert all(0 <= vals[3 * x + 2] <= 3 for x in range(2)) and vals[8] == 0
         assert lib.hartree_plan_set_config(h, cfg) == 0          # the current choice round-trips
-        bad = (ctypes.c_int32 * 6)(*vals)
-        bad[1] = 9                                               # 512 pencils per workgroup
-        assert lib.hartree_plan_set_config(h, bad) == 1
-        bad = (ctypes.c_int32 * 6)(*vals)
-        bad[0] = 10_000                                          # no such compiled plan
-        assert lib.hartree_plan_set_config(h, bad) == 1
-        bad = (ctypes.c_int32 * 6)(*vals)
-        bad[4] = vals[0] if vals[0] >= 0 else 0                  # the 360 plan on the length-45 axis
-        assert lib.hartree_plan_set_config(h, bad) == 1
+        for idx, bad_value in ((1, 9),                           # 512 pencils per workgroup
+                               (0, 10_000),                      # no such compiled plan
+                               (6, vals[0] if vals[0] >= 0 else 0),  # the 360 plan on the length-45 axis
+                               (2, 4),                           # pad beyond 3
+                               (8, 1)):                          # a pad on the c axis
+            bad = (ctypes.c_int32 * 9)(*vals)
+            bad[idx] = bad_value
+            assert lib.hartree_plan_set_config(h, bad) == 1, (idx, bad_value)
         assert b"does not apply" in lib.hartree_last_error()
         assert lib.hartree_plan_get_config(h, cfg) == 0
         assert list(cfg) == vals                                 # rejected choices change nothing
