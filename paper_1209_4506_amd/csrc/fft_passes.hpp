@@ -77,11 +77,15 @@ struct RealPairIn {
     const T *h0, *h1;       // the same rows of rho (MODE 1, 2)
     T w0, w1;               // 1 for rows inside the grid, 0 beyond
     T s0, s1;               // scale of rho, times w
+    // the real grids are read once per pass: streaming (non-temporal) loads
+    // leave the caches to the half spectrum that the next passes reuse
+    static __device__ __forceinline__ T ld(const T *p) { return __builtin_nontemporal_load(p); }
     __device__ __forceinline__ Cx<T> load(int i) const
     {
-        if constexpr (MODE == 0) return Cx<T>{w0 * r0[i], w1 * r1[i]};
-        else if constexpr (MODE == 1) return Cx<T>{w0 * r0[i] + s0 * h0[i], w1 * r1[i] + s1 * h1[i]};
-        else return Cx<T>{s0 * h0[i], s1 * h1[i]};
+        if constexpr (MODE == 0) return Cx<T>{w0 * ld(r0 + i), w1 * ld(r1 + i)};
+        else if constexpr (MODE == 1)
+            return Cx<T>{w0 * ld(r0 + i) + s0 * ld(h0 + i), w1 * ld(r1 + i) + s1 * ld(h1 + i)};
+        else return Cx<T>{s0 * ld(h0 + i), s1 * ld(h1 + i)};
     }
 };
 
@@ -122,8 +126,8 @@ struct RealPairOut {
     bool v0, v1;
     __device__ __forceinline__ void store(int i, Cx<T> v) const
     {
-        if (v0) o0[i] = v.x;
-        if (v1) o1[i] = -v.y;
+        if (v0) __builtin_nontemporal_store(v.x, o0 + i);
+        if (v1) __builtin_nontemporal_store(-v.y, o1 + i);
     }
 };
 
