@@ -150,7 +150,7 @@ struct hartree_plan_s {
     int64_t max_parts = 0;  // E_H partial slots at one pencil per workgroup
     // workspace layout
     size_t o_status = 0, o_desc = 0, o_tw = 0, o_spec = 0, o_parts = 0, o_qsum = 0, o_info = 0, o_counts = 0,
-           o_offsets = 0, o_cursor = 0, o_list = 0, o_lists = 0, o_bpart = 0, o_slot = 0, o_bsum = 0, o_tab = 0,
+           o_offsets = 0, o_cursor = 0, o_list = 0, o_lists = 0, o_bpart = 0, o_slot = 0, o_bsum = 0, o_tab = 0, o_rec = 0,
            ws_size = 0;
     int32_t cap_pa = 0;
     int32_t wcap = 0;  // per-atom factor table row length
@@ -379,8 +379,8 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
         // pass tiles: default radix plan and pencils per workgroup per axis
         for (int x = 0; x < 3; ++x) {
             // strided axes (a, b): up to 64 pencils side by side; the c axis:
-            // at most 16 pencils, so at least 16 threads run along each one
-            const int lp = pass_p_log2(p->fp64, N[x], d.ax[x].radix, d.ax[x].nstages, x == 2 ? 16 : 64);
+            // at most 4 pencils, so that a wavefront streams whole rows
+            const int lp = pass_p_log2(p->fp64, N[x], d.ax[x].radix, d.ax[x].nstages, x == 2 ? 4 : 64);
             if (lp < 0) {
                 delete p;
                 return fail(HARTREE_ERR_DIMS, "problem %d: length %d needs more threads per pencil than a workgroup has",
@@ -462,6 +462,7 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
         p->o_lists = take(4 * size_t(p->capacity));
         p->o_bpart = take(24 * size_t(p->capacity));
         p->o_slot = take(4 * size_t(p->capacity));
+        if (!p->fp64) p->o_rec = take(sizeof(SlotAtom) * size_t(p->capacity));
         if (p->fp64) p->o_tab = take(16 * size_t(p->max_atoms) * 3 * size_t(p->wcap));
         p->o_bsum = take(8 * size_t(p->nbricks / 4096 + 2));
     }
@@ -570,6 +571,7 @@ SplatArgs splat_args(hartree_plan p, int32_t natoms, const double *pos, const do
     a.list_sorted = reinterpret_cast<int32_t *>(p->ws + p->o_lists);
     a.bpart = reinterpret_cast<double *>(p->ws + p->o_bpart);
     a.slot_of = reinterpret_cast<int32_t *>(p->ws + p->o_slot);
+    a.rec = p->fp64 ? nullptr : reinterpret_cast<SlotAtom *>(p->ws + p->o_rec);
     a.bsum = reinterpret_cast<int64_t *>(p->ws + p->o_bsum);
     a.cap_pa = p->cap_pa;
     a.tab = p->ws + p->o_tab;

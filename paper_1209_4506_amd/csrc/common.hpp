@@ -93,6 +93,19 @@ struct AtomInfo {
     int32_t pad;
 };
 
+// One atom in one brick's sorted list, as the FP32 splat kernels use it
+// (written by the binning sort): along axis x the brick's first point lies
+// at offset r0[x] (mod n) from the window start lo; an unwrapped offset r
+// inside the window width wl has displacement r h - xb, xb = X - lo h.
+struct SlotAtom {
+    float xb[3];
+    int32_t r0[3];
+    int32_t wl[3];  // 0 for an atom that touches nothing
+    float inv2s2;   // 1 / (2 sigma^2)
+    float w;        // Z (2 pi sigma^2)^(-3/2)
+    int32_t pad;
+};
+
 struct DeviceStatus {
     uint32_t bits;
     uint32_t pad[63];

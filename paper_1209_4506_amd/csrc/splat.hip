@@ -288,8 +288,27 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a)
             for (int j = 0; j < cnt; ++j) rank += (a.list[off + j] < v) ? 1 : 0;
         }
         a.list_sorted[off + rank] = v;
-        const Touch t = atom_touch(a.info[v], d);
+        const AtomInfo in = a.info[v];
+        const Touch t = atom_touch(in, d);
         a.slot_of[int64_t(v) * a.cap_pa + touch_index(t, d, b - d.brick_off)] = int32_t(off + rank);
+        if (a.rec) {
+            // the atom relative to this brick, for the FP32 splat kernels
+            const int64_t lb = b - d.brick_off;
+            const int bc[3] = {int(lb / (int64_t(d.nbricks[2]) * d.nbricks[1])),
+                               int((lb / d.nbricks[2]) % d.nbricks[1]), int(lb % d.nbricks[2])};
+            SlotAtom r;
+            for (int x = 0; x < 3; ++x) {
+                const int n = d.dims[x];
+                const double h = d.L[x] / n;
+                r.xb[x] = float(in.X[x] - in.lo[x] * h);
+                r.r0[x] = wrapi(bc[x] * d.bsz[x] - in.lo[x], n);
+                r.wl[x] = in.hi[x] >= in.lo[x] ? in.hi[x] - in.lo[x] + 1 : 0;
+            }
+            r.inv2s2 = float(in.inv2s2);
+            r.w = float(in.w);
+            r.pad = 0;
+            a.rec[off + rank] = r;
+        }
     }
 }
 

@@ -39,6 +39,8 @@ constexpr int kSplatChunk = 64;  // atoms staged per pass (splat)
 constexpr int kAdjChunk = 32;    // atoms staged per pass (adjoint)
 constexpr int kAdjGroup = 16;    // atoms per MFMA column tile: 16 atoms x (g, gd)
 constexpr int kAdjGroups = kAdjChunk / kAdjGroup;
+constexpr int kStage = 128;      // atom records staged at once (whole lists, almost always)
+static_assert(kStage % kSplatChunk == 0 && kStage % kAdjChunk == 0 && kStage <= kMThreads, "record staging");
 constexpr int kRow = kMI + kMJ + kMK;  // table entries one atom needs in one brick
 
 // A brick's position (brick index per axis), kept in registers
@@ -57,19 +59,13 @@ __device__ __forceinline__ BrickPos brick_pos(const ProbDesc &d, int64_t b)
     return p;
 }
 
-// One atom staged for one brick.  The brick's 1-D factors are evaluated on
-// the fly: along axis x, brick point q has grid index g = b_x bsz_x + q and
-// lies at offset r = (r0 + q) mod n_x from the window start lo_x; its
-// unwrapped images are r, r + n_x, ... while inside the window width wl_x,
-// each with displacement d = r h_x - xb_x, xb_x = X_x - lo_x h_x (formed in
-// double, small), factor exp(-d^2 / (2 sigma^2)).
-struct StagedG {
-    float xb[3];
-    int r0[3];
-    int wl[3];  // 0 for an atom that touches nothing
-    float inv2s2;
-    float w;    // Z (2 pi s^2)^(-3/2)
-};
+// The brick's 1-D factors are evaluated on the fly from the atoms' SlotAtom
+// records (written by the binning sort): along axis x, brick point q has
+// grid index g = b_x bsz_x + q and lies at offset r = (r0 + q) mod n_x from
+// the window start; its unwrapped images are r, r + n_x, ... while inside the
+// window width wl_x, each with displacement d = r h_x - xb_x and factor
+// exp(-d^2 / (2 sigma^2)).
+typedef SlotAtom StagedG;
 
 // the problem's per-axis grid data, kept in registers
 struct AxisGrid {
@@ -83,28 +79,10 @@ __device__ __forceinline__ AxisGrid axis_grid(const ProbDesc &d)
             float(d.L[2] / d.dims[2])};
 }
 
-// threads t < nc stage atoms list[c0 + t] for brick p
-__device__ __forceinline__ void stage_g(StagedG *dst, const SplatArgs &a, const ProbDesc &d, const BrickPos &p,
-                                        int64_t off, int c0, int nc, int t)
+// threads t < nc copy the records of list entries c0 + t to LDS
+__device__ __forceinline__ void stage_g(StagedG *dst, const SplatArgs &a, int64_t off, int c0, int nc, int t)
 {
-    if (t < nc) {
-        const int atom = a.list_sorted[off + c0 + t];
-        const AtomInfo in = a.info[atom];
-        StagedG s;
-        const int bidx[3] = {p.b0, p.b1, p.b2};
-        const int bsz[3] = {kMI, kMJ, kMK};
-#pragma unroll
-        for (int x = 0; x < 3; ++x) {
-            const int n = d.dims[x];
-            const double h = d.L[x] / n;
-            s.xb[x] = float(in.X[x] - in.lo[x] * h);
-            s.r0[x] = wrapi(bidx[x] * bsz[x] - in.lo[x], n);
-            s.wl[x] = in.hi[x] >= in.lo[x] ? in.hi[x] - in.lo[x] + 1 : 0;
-        }
-        s.inv2s2 = float(in.inv2s2);
-        s.w = float(in.w);
-        dst[t] = s;
-    }
+    if (t < nc) dst[t] = a.rec[off + c0 + t];
 }
 
 // Entry q (0 .. 63) of one staged atom's factors over this brick: q < 16
@@ -146,7 +124,7 @@ __device__ __forceinline__ Cx<float> brick_entry(const AxisGrid &ag, const Brick
 
 __global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
 {
-    __shared__ StagedG atoms[kSplatChunk];
+    __shared__ StagedG recs[kStage];
     __shared__ float gxw[kSplatChunk][kMI + 1], gy[kSplatChunk][kMJ + 1], gz[kSplatChunk][kMK + 1];
     const int64_t b = brick_of_block();
     const int prob = brick_prob(a, b);
@@ -172,8 +150,11 @@ __global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
     for (int c0 = 0; c0 < cnt; c0 += kSplatChunk) {
         const int ns = (cnt - c0) < kSplatChunk ? (cnt - c0) : kSplatChunk;
         const int npair = (ns + 1) >> 1;
-        stage_g(atoms, a, d, p, off, c0, ns, t);
-        __syncthreads();
+        if (c0 % kStage == 0) {
+            stage_g(recs, a, off, c0, (cnt - c0) < kStage ? (cnt - c0) : kStage, t);
+            __syncthreads();
+        }
+        const StagedG *atoms = recs + c0 % kStage;
         {
             constexpr int R = kSplatChunk / 4;  // rounds: atoms per wavefront
             float v[R];
@@ -229,7 +210,7 @@ __global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
 // atom) and folds the transverse factors in.
 __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
 {
-    __shared__ StagedG atoms[kAdjChunk];
+    __shared__ StagedG recs[kStage];
     __shared__ float gx[kAdjChunk][kMI + 1], gdx[kAdjChunk][kMI + 1];
     __shared__ float gy[kAdjChunk][kMJ + 1], gdy[kAdjChunk][kMJ + 1];
     __shared__ float gzt[kAdjGroups][2 * kAdjGroup][kMK + 1];  // per group: gz rows, then gdz rows
@@ -290,8 +271,11 @@ __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
     for (int c0 = 0; c0 < cnt; c0 += kAdjChunk) {
         const int ns = (cnt - c0) < kAdjChunk ? (cnt - c0) : kAdjChunk;
         const int ngroup = (ns + kAdjGroup - 1) / kAdjGroup;
-        stage_g(atoms, a, d, p, off, c0, ns, t);
-        __syncthreads();
+        if (c0 % kStage == 0) {
+            stage_g(recs, a, off, c0, (cnt - c0) < kStage ? (cnt - c0) : kStage, t);
+            __syncthreads();
+        }
+        const StagedG *atoms = recs + c0 % kStage;
         {
             constexpr int R = kAdjChunk / 4;  // rounds: atoms per wavefront
             Cx<float> v[R];
