@@ -150,7 +150,7 @@ struct hartree_plan_s {
     int64_t max_parts = 0;  // E_H partial slots at one pencil per workgroup
     // workspace layout
     size_t o_status = 0, o_desc = 0, o_tw = 0, o_spec = 0, o_parts = 0, o_qsum = 0, o_info = 0, o_counts = 0,
-           o_offsets = 0, o_cursor = 0, o_list = 0, o_lists = 0, o_bpart = 0, o_slot = 0, o_bsum = 0, o_tab = 0, o_rec = 0,
+           o_offsets = 0, o_cursor = 0, o_list = 0, o_lists = 0, o_bpart = 0, o_slot = 0, o_tab = 0, o_rec = 0,
            ws_size = 0;
     int32_t cap_pa = 0;
     int32_t wcap = 0;  // per-atom factor table row length
@@ -464,7 +464,6 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
         p->o_slot = take(4 * size_t(p->capacity));
         if (!p->fp64) p->o_rec = take(sizeof(SlotAtom) * size_t(p->capacity));
         if (p->fp64) p->o_tab = take(16 * size_t(p->max_atoms) * 3 * size_t(p->wcap));
-        p->o_bsum = take(8 * size_t(p->nbricks / 4096 + 2));
     }
     p->ws_size = o;
     *out = p;
@@ -572,7 +571,6 @@ SplatArgs splat_args(hartree_plan p, int32_t natoms, const double *pos, const do
     a.bpart = reinterpret_cast<double *>(p->ws + p->o_bpart);
     a.slot_of = reinterpret_cast<int32_t *>(p->ws + p->o_slot);
     a.rec = p->fp64 ? nullptr : reinterpret_cast<SlotAtom *>(p->ws + p->o_rec);
-    a.bsum = reinterpret_cast<int64_t *>(p->ws + p->o_bsum);
     a.cap_pa = p->cap_pa;
     a.tab = p->ws + p->o_tab;
     a.wcap = p->wcap;

@@ -72,7 +72,6 @@ struct SplatArgs {
     int32_t *list_sorted;   // capacity
     int32_t *slot_of;       // max_atoms x cap_pa: sorted-list slot of each (atom, touched brick)
     SlotAtom *rec;          // capacity (FP32 plans): the sorted lists' atoms relative to their brick
-    int64_t *bsum;          // per scan block: count sums
     double *bpart;          // capacity x 3 (adjoint partials)
     int64_t capacity;
     int32_t cap_pa;         // most bricks one atom can touch

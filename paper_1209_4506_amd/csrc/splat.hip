@@ -13,8 +13,9 @@
 // index, and every sum below runs in a fixed order, so results do not depend
 // on scheduling.
 //
-//   prep    per atom: wrapped position, weight, window [lo, hi] per axis
-//   charge  per problem: Q = sum Z (fixed order), for the background Q / Omega
+//   init    zero the brick counters; per atom: wrapped position, weight,
+//           window [lo, hi] per axis; per problem: Q = sum Z (fixed order),
+//           for the background Q / Omega
 //   count   per atom: +1 on each touched brick
 //   scan    exclusive prefix sum of the brick counts
 //   fill    per atom: write its index into each touched brick's list
@@ -26,16 +27,8 @@
 
 namespace hartree {
 
-__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
+__device__ __forceinline__ void atom_prep(const SplatArgs &a, int atom)
 {
-    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-        p[i] = v;
-}
-
-__global__ void k_atom_prep(SplatArgs a)
-{
-    const int atom = blockIdx.x * blockDim.x + threadIdx.x;
-    if (atom >= a.natoms) return;
     const int prob = find_prob_atom(a, atom);
     const ProbDesc &d = a.desc[prob];
     AtomInfo in;
@@ -116,10 +109,20 @@ __global__ __launch_bounds__(256) void k_atom_tables(SplatArgs a)
     reinterpret_cast<Cx<T> *>(a.tab)[e] = Cx<T>{g, gd};
 }
 
-__global__ __launch_bounds__(256) void k_charge(SplatArgs a, double *qsum)
+// Binning set-up in one launch: zero the brick counts and cursors
+// (grid-stride), prepare one atom per thread, and let block p < nprob sum
+// the charges of problem p in a fixed order (for the background Q / Omega).
+__global__ __launch_bounds__(256) void k_bin_init(SplatArgs a)
 {
     __shared__ double red[256];
+    const int64_t gid = blockIdx.x * int64_t(blockDim.x) + threadIdx.x, gstride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = gid; i <= a.nbricks_total; i += gstride) {
+        a.counts[i] = 0;
+        a.cursor[i] = 0;
+    }
+    if (gid < a.natoms) atom_prep(a, int(gid));
     const int p = blockIdx.x;
+    if (p >= a.nprob) return;
     double s = 0.0;
     for (int i = a.atom_off[p] + threadIdx.x; i < a.atom_off[p + 1]; i += 256) s += a.Z[i];
     red[threadIdx.x] = s;
@@ -128,7 +131,7 @@ __global__ __launch_bounds__(256) void k_charge(SplatArgs a, double *qsum)
         if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) qsum[p] = red[0];
+    if (threadIdx.x == 0) a.qsum[p] = red[0];
 }
 
 // Bricks touched by one atom, enumerated t = 0 .. ntouch-1 in a fixed order:
@@ -191,66 +194,37 @@ __global__ __launch_bounds__(256) void k_brick_visit(SplatArgs a)
     }
 }
 
-// exclusive scan of counts[0..n) into offsets[0..n] in three steps over
-// blocks of kScanBlock entries: block sums, then each block scans its own
-// entries after adding the sums of the blocks before it
-constexpr int kScanBlock = 4096;
+// exclusive scan of counts[0..n) into offsets[0..n] by one workgroup:
+// thread t owns a contiguous run of entries, sums it, the workgroup scans
+// the run sums, and each thread writes its run (clamped to the capacity)
+constexpr int kScanThreads = 1024;
 
-__global__ __launch_bounds__(256) void k_scan_sums(SplatArgs a)
+__global__ __launch_bounds__(kScanThreads) void k_scan(SplatArgs a)
 {
-    __shared__ int64_t red[256];
-    const int64_t b0 = int64_t(blockIdx.x) * kScanBlock;
-    int64_t s = 0;
-    for (int i = threadIdx.x; i < kScanBlock; i += 256) {
-        const int64_t e = b0 + i;
-        if (e < a.nbricks_total) s += a.counts[e];
-    }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-        if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) a.bsum[blockIdx.x] = red[0];
-}
-
-__global__ __launch_bounds__(256) void k_scan_blocks(SplatArgs a)
-{
-    __shared__ int64_t part[256];
-    __shared__ int64_t base;
+    __shared__ int64_t part[kScanThreads];
     const int t = threadIdx.x;
-    if (t == 0) {
-        int64_t s = 0;
-        for (int b = 0; b < int(blockIdx.x); ++b) s += a.bsum[b];
-        base = s;
-    }
-    // each thread owns kScanBlock / 256 = 16 consecutive entries
-    constexpr int PER = kScanBlock / 256;
-    const int64_t e0 = int64_t(blockIdx.x) * kScanBlock + t * PER;
-    int32_t c[PER];
+    const int64_t n = a.nbricks_total;
+    const int64_t per = (n + kScanThreads - 1) / kScanThreads;
+    const int64_t e0 = t * per, e1 = (e0 + per) < n ? (e0 + per) : n;
     int64_t s = 0;
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        c[i] = (e0 + i < a.nbricks_total) ? a.counts[e0 + i] : 0;
-        s += c[i];
-    }
+    for (int64_t e = e0; e < e1; ++e) s += a.counts[e];
     part[t] = s;
     __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const int64_t v = (t >= off) ? part[t - off] : 0;
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        const int64_t v = t >= off ? part[t - off] : 0;
         __syncthreads();
         part[t] += v;
         __syncthreads();
     }
-    int64_t run = base + part[t] - s;
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        if (e0 + i < a.nbricks_total) a.offsets[e0 + i] = int32_t(run < a.capacity ? run : a.capacity);
-        run += c[i];
+    int64_t run = part[t] - s;
+    for (int64_t e = e0; e < e1; ++e) {
+        a.offsets[e] = int32_t(run < a.capacity ? run : a.capacity);
+        run += a.counts[e];
     }
-    if (blockIdx.x == gridDim.x - 1 && t == 255) {
-        a.offsets[a.nbricks_total] = int32_t(run < a.capacity ? run : a.capacity);
-        if (run > a.capacity) atomicOr(&a.status->bits, 0x4u);
+    if (t == kScanThreads - 1) {
+        const int64_t total = part[t];
+        a.offsets[n] = int32_t(total < a.capacity ? total : a.capacity);
+        if (total > a.capacity) atomicOr(&a.status->bits, 0x4u);
     }
 }
 
@@ -502,23 +476,20 @@ __global__ __launch_bounds__(256) void k_adjoint_final(SplatArgs a)
 
 hipError_t run_bin(const SplatArgs &a, hipStream_t s)
 {
-    const int nb = int((a.natoms + 255) / 256);
     const int64_t nbt = a.nbricks_total;
-    hipLaunchKernelGGL(k_fill_i32, dim3(1024), dim3(256), 0, s, a.counts, nbt + 1, 0);
-    hipLaunchKernelGGL(k_fill_i32, dim3(1024), dim3(256), 0, s, a.cursor, nbt, 0);
-    hipLaunchKernelGGL(k_charge, dim3(a.nprob), dim3(256), 0, s, a, a.qsum);
+    int init_blocks = int((a.natoms + 255) / 256);
+    if (init_blocks < a.nprob) init_blocks = a.nprob;
+    if (init_blocks < 64) init_blocks = 64;  // enough threads for the brick fill
+    hipLaunchKernelGGL(k_bin_init, dim3(init_blocks), dim3(256), 0, s, a);
     const int nw = int((a.natoms + 3) / 4);  // one wavefront per atom
-    const int nsb = int((nbt + kScanBlock - 1) / kScanBlock);
     if (a.natoms > 0) {
-        hipLaunchKernelGGL(k_atom_prep, dim3(nb), dim3(256), 0, s, a);
         // FP64 kernels read per-atom factor tables; the FP32 matrix-core
         // kernels evaluate the factors themselves
         const int nt = int((int64_t(a.natoms) * 3 * a.wcap + 255) / 256);
         if (a.fp64) hipLaunchKernelGGL(k_atom_tables<double>, dim3(nt), dim3(256), 0, s, a);
         hipLaunchKernelGGL(k_brick_visit<0>, dim3(nw), dim3(256), 0, s, a);
     }
-    hipLaunchKernelGGL(k_scan_sums, dim3(nsb), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(nsb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, a);
     if (a.natoms > 0) hipLaunchKernelGGL(k_brick_visit<1>, dim3(nw), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_brick_sort, dim3(int((nbt + 3) / 4)), dim3(256), 0, s, a);
     return hipGetLastError();
