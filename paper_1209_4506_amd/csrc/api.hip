@@ -150,7 +150,7 @@ struct hartree_plan_s {
     int64_t max_parts = 0;  // E_H partial slots at one pencil per workgroup
     // workspace layout
     size_t o_status = 0, o_desc = 0, o_tw = 0, o_spec = 0, o_parts = 0, o_qsum = 0, o_info = 0, o_counts = 0,
-           o_offsets = 0, o_cursor = 0, o_list = 0, o_lists = 0, o_bpart = 0, o_slot = 0, o_tab = 0, o_rec = 0,
+           o_offsets = 0, o_cursor = 0, o_list = 0, o_lists = 0, o_bpart = 0, o_slot = 0, o_tab = 0, o_rec = 0, o_zero = 0,
            ws_size = 0;
     int32_t cap_pa = 0;
     int32_t wcap = 0;  // per-atom factor table row length
@@ -448,6 +448,7 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
         return at;
     };
     p->o_status = take(sizeof(DeviceStatus));
+    p->o_zero = take(256);
     p->o_desc = take(sizeof(ProbDesc) * nprob);
     p->o_tw = take(cx * (p->twiddles.size() / 2));
     p->o_spec = take(cx * size_t(p->spec_count));
@@ -571,6 +572,7 @@ SplatArgs splat_args(hartree_plan p, int32_t natoms, const double *pos, const do
     a.bpart = reinterpret_cast<double *>(p->ws + p->o_bpart);
     a.slot_of = reinterpret_cast<int32_t *>(p->ws + p->o_slot);
     a.rec = p->fp64 ? nullptr : reinterpret_cast<SlotAtom *>(p->ws + p->o_rec);
+    a.zeros = reinterpret_cast<const float *>(p->ws + p->o_zero);
     a.cap_pa = p->cap_pa;
     a.tab = p->ws + p->o_tab;
     a.wcap = p->wcap;
@@ -670,6 +672,9 @@ hartree_status hartree_bind_workspace(hartree_plan plan, void *workspace, size_t
     std::memset(&st, 0, sizeof(st));
     e = hipMemcpy(ws + plan->o_status, &st, sizeof(st), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "clearing the status word");
+    const unsigned char zero[256] = {};
+    e = hipMemcpy(ws + plan->o_zero, zero, sizeof(zero), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "clearing the zero block");
     plan->ws = ws;
     return ok();
 }
@@ -804,6 +809,13 @@ hartree_status hartree_splat_adjoint_bound(hartree_plan plan, uint64_t token, co
     if (!grad_rho || (a.natoms > 0 && !grad_pos)) return fail(HARTREE_ERR_ARG, "grad_rho or grad_pos is NULL");
     a.grad_rho = grad_rho;
     a.grad_pos = grad_pos;
+    // float4 row loads when every problem's rows are whole, aligned vectors
+    a.grad_rows_vec4 = 0;
+    if (!plan->fp64 && reinterpret_cast<uintptr_t>(grad_rho) % 16 == 0) {
+        a.grad_rows_vec4 = 1;
+        for (const ProbDesc &d : plan->desc)
+            if (d.dims[2] % 4 != 0 || d.grid_off % 4 != 0) a.grad_rows_vec4 = 0;
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = timed(plan, HARTREE_K_ADJOINT, s, [&]() { return run_adjoint(a, s); });
     if (e != hipSuccess) return hip_fail(e, "splat adjoint");

@@ -81,6 +81,8 @@ struct SplatArgs {
     int32_t fp64;
     void *rho;              // splat output grid
     const void *grad_rho;   // adjoint input grid
+    int32_t grad_rows_vec4; // every problem's grad_rho rows start 16-byte aligned with Nc % 4 == 0
+    const float *zeros;     // 64 zero floats in the workspace (never written by kernels)
     double *grad_pos;       // adjoint output
     double *qsum;           // nprob: total charge per problem
     void *tab;              // per-atom 1-D factor tables: max_atoms x 3 x wcap pairs (g, gd) of the precision

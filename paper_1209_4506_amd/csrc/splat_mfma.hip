@@ -208,6 +208,7 @@ __global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
 // adjoint: wave w holds grad_rho of its two row tiles in registers; per
 // group of 16 staged atoms it forms S for both tiles (32 columns n = 16 f +
 // atom) and folds the transverse factors in.
+template <bool VEC>
 __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
 {
     __shared__ StagedG recs[kStage];
@@ -227,8 +228,22 @@ __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
     if (cnt == 0) return;
     const int half = lane >> 5, col = lane & 31;
 
+    // The first records are requested before grad_rho, so that storing them
+    // to LDS (and evaluating the factors) waits for them alone while the
+    // grad_rho loads are still in flight.  (Three named vectors: a local
+    // array here would live in scratch memory.)
+    static_assert(sizeof(StagedG) == 48, "records move as three 16-byte vectors");
+    const int ns0 = cnt < kStage ? cnt : kStage;
+    const uint4 *rsrc = reinterpret_cast<const uint4 *>(a.rec + off + (t < ns0 ? t : 0));
+    const uint4 rr0 = rsrc[0], rr1 = rsrc[1], rr2 = rsrc[2];
+
     // grad_rho of this lane's two A rows (local i = 4 wave + col / 16 and
     // + 2, j = col % 16) at points k = 32 bk + 16 half + m, m = 0 .. 15
+    // Every load is unconditional (an element outside the grid reads a zero
+    // block of the workspace), so no branch or arithmetic on the loaded
+    // values separates the loads from the record wait below: they stay in
+    // flight until the matrix products.  VEC: every problem's rows hold a
+    // multiple of 4 points from a 16-byte aligned start.
     float g0[16], g1[16];
     {
         const float *src = reinterpret_cast<const float *>(a.grad_rho) + d.grid_off;
@@ -237,16 +252,14 @@ __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
         const int k0 = p.b2 * kMK + 16 * half;
         const bool jin = j < d.dims[1];
         const bool in0 = jin && ia < d.dims[0], in1 = jin && ia + 2 < d.dims[0];
-        const int64_t r0 = (int64_t(ia) * d.dims[1] + j) * d.dims[2] + k0;
-        const int64_t r1 = (int64_t(ia + 2) * d.dims[1] + j) * d.dims[2] + k0;
-        const bool vec = ((d.dims[2] & 3) == 0) && ((reinterpret_cast<uintptr_t>(src) & 15) == 0) &&
-                         (k0 + 16 <= d.dims[2]);
-        if (vec) {
-            const float4 z4{0.0f, 0.0f, 0.0f, 0.0f};
+        const float *row0 = src + (in0 ? (int64_t(ia) * d.dims[1] + j) * d.dims[2] + k0 : 0);
+        const float *row1 = src + (in1 ? (int64_t(ia + 2) * d.dims[1] + j) * d.dims[2] + k0 : 0);
+        if constexpr (VEC) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const float4 v0 = in0 ? reinterpret_cast<const float4 *>(src + r0)[q] : z4;
-                const float4 v1 = in1 ? reinterpret_cast<const float4 *>(src + r1)[q] : z4;
+                const bool kin = k0 + 4 * q < d.dims[2];  // whole vectors: Nc is a multiple of 4
+                const float4 v0 = *reinterpret_cast<const float4 *>(in0 && kin ? row0 + 4 * q : a.zeros);
+                const float4 v1 = *reinterpret_cast<const float4 *>(in1 && kin ? row1 + 4 * q : a.zeros);
                 g0[4 * q] = v0.x;
                 g0[4 * q + 1] = v0.y;
                 g0[4 * q + 2] = v0.z;
@@ -260,18 +273,29 @@ __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
 #pragma unroll
             for (int m = 0; m < 16; ++m) {
                 const bool kin = k0 + m < d.dims[2];
-                g0[m] = (in0 && kin) ? src[r0 + m] : 0.0f;
-                g1[m] = (in1 && kin) ? src[r1 + m] : 0.0f;
+                g0[m] = *(in0 && kin ? row0 + m : a.zeros);
+                g1[m] = *(in1 && kin ? row1 + m : a.zeros);
             }
         }
     }
     const int n = col;  // this lane's C column: function f = n / 16 of atom n % 16
     const int f = n >> 4, sl = n & 15;
 
+    // keep the grad_rho loads issued above this point (the compiler would
+    // otherwise sink them below the record store and its wait)
+    asm volatile("" ::: "memory");
+    if (t < ns0) {
+        uint4 *dst = reinterpret_cast<uint4 *>(recs + t);
+        dst[0] = rr0;
+        dst[1] = rr1;
+        dst[2] = rr2;
+    }
+    __syncthreads();
+
     for (int c0 = 0; c0 < cnt; c0 += kAdjChunk) {
         const int ns = (cnt - c0) < kAdjChunk ? (cnt - c0) : kAdjChunk;
         const int ngroup = (ns + kAdjGroup - 1) / kAdjGroup;
-        if (c0 % kStage == 0) {
+        if (c0 > 0 && c0 % kStage == 0) {
             stage_g(recs, a, off, c0, (cnt - c0) < kStage ? (cnt - c0) : kStage, t);
             __syncthreads();
         }
@@ -370,7 +394,10 @@ hipError_t run_gather_mfma(const SplatArgs &a, hipStream_t s)
 
 hipError_t run_adjoint_mfma(const SplatArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_adjoint_mfma, dim3(int(a.nbricks_total)), dim3(kMThreads), 0, s, a);
+    if (a.grad_rows_vec4)
+        hipLaunchKernelGGL(k_adjoint_mfma<true>, dim3(int(a.nbricks_total)), dim3(kMThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_adjoint_mfma<false>, dim3(int(a.nbricks_total)), dim3(kMThreads), 0, s, a);
     return hipGetLastError();
 }
 
