@@ -36,9 +36,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default pass shapes (skip hartree_plan_tune)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of tuned pass shapes: applied when it holds this plan, else written after tuning")
     ap.add_argument("--graph", action="store_true",
                     help="also time the step replayed as one captured HIP graph")
-    ap.add_argument("--cpu-atoms", type=int, default=512, help="atoms in the CPU-oracle sample")
+    ap.add_argument("--cpu-atoms", type=int, default=4096, help="atoms in the CPU-oracle sample (all of them by default)")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (to calibrate HBM byte counters)")
@@ -71,12 +73,12 @@ def source_hash():
 class Step:
     """Preallocated buffers and the four C-ABI calls of one fwd+bwd solve."""
 
-    def __init__(self, prob, precision, torch, H, inputs, tune=True):
+    def __init__(self, prob, precision, torch, H, inputs, tune=True, cache=None):
         self.torch = torch
         dev = torch.device("cuda:0")
         self.plan = H.Plan(prob.cell, prob.dims, precision=precision, device=dev, max_atoms=prob.natoms)
         p = self.plan
-        self.config = p.tune(reps=5) if tune else p.get_config()
+        self.config = p.tune(reps=5, cache=cache) if tune else p.get_config()
         self.pos = torch.tensor(prob.pos, device=dev)
         self.Z = torch.tensor(prob.Z, device=dev)
         self.sig = torch.tensor(prob.sigma, device=dev)
@@ -207,7 +209,7 @@ def main():
     from paper_1209_4506_amd import inputs
 
     prob = inputs.diamond360()
-    step = Step(prob, "fp32", torch, H, inputs, tune=not args.no_tune)
+    step = Step(prob, "fp32", torch, H, inputs, tune=not args.no_tune, cache=args.tune_cache)
     assert step.plan.device_status() == 0
     dt, prof = step.timed(args.steps, args.warmup, profile=True)
     assert step.plan.device_status() == 0, "device status bits set"
@@ -258,7 +260,7 @@ def main():
     if not args.no_fp64:
         del step
         torch.cuda.empty_cache()
-        step64 = Step(prob, "fp64", torch, H, inputs, tune=not args.no_tune)
+        step64 = Step(prob, "fp64", torch, H, inputs, tune=not args.no_tune, cache=args.tune_cache)
         k64 = max(3, args.steps // 4)
         dt64, prof64 = step64.timed(k64, 2, profile=True)
         out["fp64_plain"] = {"value": k64 / dt64, "unit": "solves/s", "ms_per_step": 1000.0 * dt64 / k64,
