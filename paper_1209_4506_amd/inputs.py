@@ -19,6 +19,12 @@ Five named configurations (seed = 1209 + index):
                      from {48, 60, 72, 90, 120, 150, 180, 240}, 16..512 atoms with
                      Z in {1, 4, 6} and sigma in U[0.6, 1.0]; per-problem seed 120900 + p.
 4. ``cubic1024``     cubic a = 150 Bohr, 1024^3 grid, 32768 uniform atoms.
+
+and, on grids with a factor 7 at the paper's own grid spacing (0.2568 Bohr,
+Sec. 5.2.7: 420 x 420 x 210 points for 16,384 diamond atoms):
+
+5. ``diamond16384``  16x16x8 conventional diamond cells (16,384 atoms),
+                     107.85 x 107.85 x 53.93 Bohr, 420 x 420 x 210 grid.
 """
 from __future__ import annotations
 
@@ -95,6 +101,22 @@ def diamond360(seed: int = SEED_BASE + 2) -> Problem:
     return p
 
 
+def diamond16384(seed: int = SEED_BASE + 5) -> Problem:
+    """16x16x8 conventional diamond cells (a = 6.7406 Bohr) on the paper's
+    420 x 420 x 210 grid; 16 atoms chosen for the force checks."""
+    rng = np.random.default_rng(seed)
+    a_conv = 53.93 / 8
+    reps = (16, 16, 8)
+    cells = np.array([[i, j, k] for i in range(reps[0]) for j in range(reps[1]) for k in range(reps[2])], float)
+    sites = (cells[:, None, :] + _DIAMOND_BASIS[None, :, :]).reshape(-1, 3) * a_conv
+    pos = sites + rng.normal(0.0, 0.05, sites.shape)
+    n = pos.shape[0]
+    cell = np.diag([a_conv * reps[0], a_conv * reps[1], a_conv * reps[2]])
+    p = Problem("diamond16384", cell, (420, 420, 210), pos, np.full(n, 4.0), np.full(n, 0.8), seed)
+    p.extra["fd_atoms"] = np.random.default_rng(seed + 7).choice(n, 16, replace=False)
+    return p
+
+
 def batched24(seed: int = SEED_BASE + 3, nprob: int = 24) -> list:
     out = []
     for p in range(nprob):
@@ -117,7 +139,7 @@ def cubic1024(seed: int = SEED_BASE + 4) -> Problem:
                    np.full(n, 4.0), np.full(n, 0.8), seed)
 
 
-CONFIGS = {0: cubic32, 1: diamond180, 2: diamond360, 3: batched24, 4: cubic1024}
+CONFIGS = {0: cubic32, 1: diamond180, 2: diamond360, 3: batched24, 4: cubic1024, 5: diamond16384}
 
 
 def config(i: int):

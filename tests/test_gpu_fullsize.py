@@ -175,6 +175,30 @@ def test_cubic1024_properties(H, oracle_mod):
     torch.cuda.empty_cache()
 
 
+def test_diamond16384_radix7(H, oracle_mod):
+    """The paper's grid (420 x 420 x 210, radix 7 on every axis) with 16,384
+    diamond atoms: sampled density, V and E_H against the oracle solve of the
+    same density, and the FP32 forces of 16 atoms against the oracle adjoint
+    of the oracle potential."""
+    p = inputs.diamond16384()
+    say("case diamond16384 fp32 (radix 7)")
+    plan, rho, V, E, F = run_step(H, p, "fp32")
+    cell9 = p.cell.reshape(9)
+    flat = np.random.default_rng(7).choice(p.npoints, 100, replace=False)
+    ref = oracle_mod.splat_points(cell9, p.dims, p.pos, p.Z, p.sigma, flat)
+    scale = float(torch.max(torch.abs(rho)).item())
+    er = np.abs(sample(rho, flat) - ref).max() / scale
+    V_o, _, eg, _ = oracle_mod.poisson(cell9, rho.double().cpu().numpy())
+    ev = rel_l2(V.double().cpu().numpy(), V_o)
+    ee = abs(float(E[0]) - eg) / eg
+    atoms = p.extra["fd_atoms"]
+    dv = plan.dv()[0]
+    F_o = oracle_mod.splat_adjoint(cell9, p.pos, p.Z, p.sigma, dv * V_o, sel=atoms)
+    ef = np.abs(F.cpu().numpy()[atoms] - F_o).max() / np.abs(F_o).max()
+    say("  rho sampled %.2e  V %.2e  E_H %.2e  forces %.2e" % (er, ev, ee, ef))
+    assert er <= 2e-6 and ev <= 5e-6 and ee <= 1e-6 and ef <= 1e-4
+
+
 def test_batched24_against_oracle(H, oracle_mod):
     probs = inputs.batched24()
     say("case batched24: %d problems, %d points" % (len(probs), sum(q.npoints for q in probs)))
