@@ -61,7 +61,7 @@ typedef enum {
     HARTREE_ERR_ARG = 1,         /* null pointer, negative count, bad enum, ... */
     HARTREE_ERR_DIMS = 2,        /* a grid dimension < 1, too large, or with a prime factor > 7 */
     HARTREE_ERR_CELL = 3,        /* non-finite cell or |det| too small */
-    HARTREE_ERR_UNSUPPORTED = 4, /* valid input the library does not handle (e.g. a non-orthorhombic splat) */
+    HARTREE_ERR_UNSUPPORTED = 4, /* valid input the library does not handle */
     HARTREE_ERR_WORKSPACE = 5,   /* no workspace bound, or the bound one is too small / misaligned */
     HARTREE_ERR_HIP = 6          /* a HIP runtime call failed */
 } hartree_status;
@@ -81,8 +81,9 @@ typedef struct {
 
 /* Create a plan for one periodic cell.
  *   cell  host, 9 doubles: the rows a, b, c (Bohr).  Any non-singular cell is
- *         accepted by the solve; the splat calls need an orthorhombic (diagonal)
- *         cell.
+ *         accepted.  The splat calls use separable per-axis factors (and, in
+ *         FP32, the matrix cores) in diagonal cells with positive edges, and a
+ *         direct per-point evaluation in any other cell.
  *   dims  host, 3 int32: Na, Nb, Nc, each >= 1, <= 4096 and 7-smooth.
  *   precision  HARTREE_FP64 or HARTREE_FP32.
  *   opts  host, nullable.
@@ -141,7 +142,8 @@ hartree_status hartree_backward(hartree_plan plan, const void *grad_v, const dou
 
 /* Gaussian atomic density on the grid (stands in for the density of Eq. (9)):
  *   rho(r) = sum_a Z_a (2 pi s_a^2)^(-3/2) sum_L exp(-|r - R_a - L|^2 / (2 s_a^2))  [- Q / Omega]
- * over lattice vectors L, truncated per axis at cutoff_sigmas * s_a; Q = sum Z_a.
+ * over lattice vectors L, truncated at cutoff_sigmas * s_a (per axis in a
+ * diagonal cell, a sphere in any other cell); Q = sum Z_a.
  *   natoms  atom count (host int; for a batched plan the total over problems),
  *   pos     natoms x 3 Cartesian positions (any, wrapped into the cell),
  *   Z, sigma  natoms charges and widths (sigma > 0, <= max_sigma),
@@ -149,7 +151,7 @@ hartree_status hartree_backward(hartree_plan plan, const void *grad_v, const dou
  *           each problem's atoms (NULL for single plans),
  *   rho_out grid of the plan's precision (overwritten),
  *   subtract_background  nonzero subtracts Q / Omega (a neutral cell).
- * Needs an orthorhombic cell (HARTREE_ERR_UNSUPPORTED otherwise). */
+ * Any cell (see hartree_plan_create). */
 hartree_status hartree_splat(hartree_plan plan, int32_t natoms, const double *pos, const double *Z,
                              const double *sigma, const int32_t *atom_offsets, void *rho_out,
                              int32_t subtract_background, void *stream);

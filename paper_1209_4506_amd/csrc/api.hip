@@ -127,6 +127,7 @@ struct hartree_plan_s {
     int fp64 = 0;
     int nprob = 0;
     bool splat_ok = false;
+    bool general = false;  // some cell needs the general-cell splat kernels
     double cutoff = 0.0;
     double max_sigma = 0.0;
     int max_atoms = 0;
@@ -375,7 +376,9 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
         d.L[0] = A[0];
         d.L[1] = A[4];
         d.L[2] = A[8];
-        if (!ortho || A[0] <= 0.0 || A[4] <= 0.0 || A[8] <= 0.0) p->splat_ok = false;
+        for (int k = 0; k < 9; ++k) d.A[k] = A[k];
+        d.separable = (ortho && A[0] > 0.0 && A[4] > 0.0 && A[8] > 0.0) ? 1 : 0;
+        if (!d.separable) p->general = true;
         // pass tiles: default radix plan and pencils per workgroup per axis
         for (int x = 0; x < 3; ++x) {
             // strided axes (a, b): up to 64 pencils side by side; the c axis:
@@ -410,8 +413,12 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
         for (int x = 0; x < 3; ++x) {
             d.bsz[x] = bsz[x];
             d.nbricks[x] = (N[x] + bsz[x] - 1) / bsz[x];
-            const double h = std::fabs(A[4 * x]) / N[x];
-            const double w = std::floor(2.0 * p->cutoff * p->max_sigma / (h > 0 ? h : 1.0)) + 1.0;
+            // spacing of the grid planes across axis x: 2 pi / (|b_x| N_x)
+            // (the edge length / N_x in a diagonal cell)
+            const double bn = std::sqrt(d.B[3 * x] * d.B[3 * x] + d.B[3 * x + 1] * d.B[3 * x + 1] +
+                                        d.B[3 * x + 2] * d.B[3 * x + 2]);
+            const double h = 6.283185307179586476925286766559 / (bn * N[x]);
+            const double w = std::floor(2.0 * p->cutoff * p->max_sigma / h) + 1.0;
             int64_t nbx = d.nbricks[x];  // most bricks one atom's window touches along x
             if (w < N[x]) {
                 const int64_t bnd = int64_t(std::ceil((w - 1.0) / bsz[x])) + 2;
@@ -463,8 +470,8 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
         p->o_lists = take(4 * size_t(p->capacity));
         p->o_bpart = take(24 * size_t(p->capacity));
         p->o_slot = take(4 * size_t(p->capacity));
-        if (!p->fp64) p->o_rec = take(sizeof(SlotAtom) * size_t(p->capacity));
-        if (p->fp64) p->o_tab = take(16 * size_t(p->max_atoms) * 3 * size_t(p->wcap));
+        if (!p->fp64 && !p->general) p->o_rec = take(sizeof(SlotAtom) * size_t(p->capacity));
+        if (p->fp64 && !p->general) p->o_tab = take(16 * size_t(p->max_atoms) * 3 * size_t(p->wcap));
     }
     p->ws_size = o;
     *out = p;
@@ -571,7 +578,8 @@ SplatArgs splat_args(hartree_plan p, int32_t natoms, const double *pos, const do
     a.list_sorted = reinterpret_cast<int32_t *>(p->ws + p->o_lists);
     a.bpart = reinterpret_cast<double *>(p->ws + p->o_bpart);
     a.slot_of = reinterpret_cast<int32_t *>(p->ws + p->o_slot);
-    a.rec = p->fp64 ? nullptr : reinterpret_cast<SlotAtom *>(p->ws + p->o_rec);
+    a.rec = (p->fp64 || p->general) ? nullptr : reinterpret_cast<SlotAtom *>(p->ws + p->o_rec);
+    a.general = p->general ? 1 : 0;
     a.zeros = reinterpret_cast<const float *>(p->ws + p->o_zero);
     a.cap_pa = p->cap_pa;
     a.tab = p->ws + p->o_tab;
@@ -587,8 +595,7 @@ SplatArgs splat_args(hartree_plan p, int32_t natoms, const double *pos, const do
 hartree_status check_atoms(hartree_plan p, int32_t natoms, const double *pos, const double *Z, const double *sigma,
                            const int32_t *atom_offsets)
 {
-    if (!p->splat_ok)
-        return fail(HARTREE_ERR_UNSUPPORTED, "the splat needs orthorhombic (diagonal, positive) cells");
+    if (!p->splat_ok) return fail(HARTREE_ERR_UNSUPPORTED, "the plan has no splat workspace");
     if (natoms < 0) return fail(HARTREE_ERR_ARG, "natoms < 0");
     if (natoms > p->max_atoms)
         return fail(HARTREE_ERR_ARG, "natoms %d exceeds the plan's max_atoms %d", natoms, p->max_atoms);

@@ -66,6 +66,9 @@ struct ProbDesc {
     double eh_scale;    // Omega / (2 npts^2)
     double dv;          // Omega / npts
     double L[3];        // cell edges (orthorhombic cells)
+    double A[9];        // cell rows a, b, c (any cell)
+    int32_t separable;  // 1: diagonal cell with positive edges (separable splat)
+    int32_t pad4;
     int32_t part_off;   // first E_H partial slot of this problem
     int32_t nparts;     // number of E_H partial slots
     int64_t brick_off;  // first brick of this problem (splat bins)

@@ -79,6 +79,7 @@ struct SplatArgs {
     DeviceStatus *status;
     int32_t subtract_background;
     int32_t fp64;
+    int32_t general;        // 1: some cell is not diagonal-positive: the general-cell kernels run
     void *rho;              // splat output grid
     const void *grad_rho;   // adjoint input grid
     int32_t grad_rows_vec4; // every problem's grad_rho rows start 16-byte aligned with Nc % 4 == 0
@@ -95,5 +96,7 @@ hipError_t run_adjoint(const SplatArgs &a, hipStream_t s);
 hipError_t run_adjoint_final(const SplatArgs &a, hipStream_t s);
 hipError_t run_gather_mfma(const SplatArgs &a, hipStream_t s);
 hipError_t run_adjoint_mfma(const SplatArgs &a, hipStream_t s);
+hipError_t run_gather_general(const SplatArgs &a, hipStream_t s);
+hipError_t run_adjoint_general(const SplatArgs &a, hipStream_t s);
 
 }  // namespace hartree

@@ -55,16 +55,35 @@ __device__ __forceinline__ void atom_prep(const SplatArgs &a, int atom)
         return;
     }
     const double rc = a.cutoff * s;
-    for (int x = 0; x < 3; ++x) {
-        const double L = d.L[x];
-        double X = a.pos[3 * atom + x];
-        X -= floor(X / L) * L;
-        if (X >= L) X -= L;
-        if (X < 0.0) X = 0.0;
-        const double h = L / d.dims[x];
-        in.X[x] = X;
-        in.lo[x] = int(ceil((X - rc) / h));
-        in.hi[x] = int(floor((X + rc) / h));
+    if (d.separable) {
+        for (int x = 0; x < 3; ++x) {
+            const double L = d.L[x];
+            double X = a.pos[3 * atom + x];
+            X -= floor(X / L) * L;
+            if (X >= L) X -= L;
+            if (X < 0.0) X = 0.0;
+            const double h = L / d.dims[x];
+            in.X[x] = X;
+            in.lo[x] = int(ceil((X - rc) / h));
+            in.hi[x] = int(floor((X + rc) / h));
+        }
+    } else {
+        // any cell: fractional coordinate f_x = R . b_x / (2 pi), wrapped
+        // into [0, 1); the cutoff sphere spans f_x +- rc |b_x| / (2 pi)
+        const double inv2pi = 0.15915494309189533576888376337251;
+        double f[3];
+        for (int x = 0; x < 3; ++x) {
+            const double *bx = d.B + 3 * x;
+            double fx = (a.pos[3 * atom] * bx[0] + a.pos[3 * atom + 1] * bx[1] + a.pos[3 * atom + 2] * bx[2]) * inv2pi;
+            fx -= floor(fx);
+            if (fx >= 1.0) fx -= 1.0;
+            if (fx < 0.0) fx = 0.0;
+            f[x] = fx;
+            const double e = rc * sqrt(bx[0] * bx[0] + bx[1] * bx[1] + bx[2] * bx[2]) * inv2pi;
+            in.lo[x] = int(ceil((fx - e) * d.dims[x]));
+            in.hi[x] = int(floor((fx + e) * d.dims[x]));
+        }
+        for (int c = 0; c < 3; ++c) in.X[c] = f[0] * d.A[c] + f[1] * d.A[3 + c] + f[2] * d.A[6 + c];
     }
     in.w = z * pow(6.283185307179586476925286766559 * s * s, -1.5);
     in.inv2s2 = 1.0 / (2.0 * s * s);
@@ -486,7 +505,7 @@ hipError_t run_bin(const SplatArgs &a, hipStream_t s)
         // FP64 kernels read per-atom factor tables; the FP32 matrix-core
         // kernels evaluate the factors themselves
         const int nt = int((int64_t(a.natoms) * 3 * a.wcap + 255) / 256);
-        if (a.fp64) hipLaunchKernelGGL(k_atom_tables<double>, dim3(nt), dim3(256), 0, s, a);
+        if (a.fp64 && !a.general) hipLaunchKernelGGL(k_atom_tables<double>, dim3(nt), dim3(256), 0, s, a);
         hipLaunchKernelGGL(k_brick_visit<0>, dim3(nw), dim3(256), 0, s, a);
     }
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, a);
@@ -498,6 +517,7 @@ hipError_t run_bin(const SplatArgs &a, hipStream_t s)
 // FP32 runs on the matrix cores (splat_mfma.hip); FP64 on the vector units
 hipError_t run_gather(const SplatArgs &a, hipStream_t s)
 {
+    if (a.general) return run_gather_general(a, s);
     if (!a.fp64) return run_gather_mfma(a, s);
     hipLaunchKernelGGL(k_splat_gather<double>, dim3(int(a.nbricks_total)), dim3(kBrickThreads), 0, s, a, a.qsum);
     return hipGetLastError();
@@ -505,6 +525,7 @@ hipError_t run_gather(const SplatArgs &a, hipStream_t s)
 
 hipError_t run_adjoint(const SplatArgs &a, hipStream_t s)
 {
+    if (a.general) return run_adjoint_general(a, s);
     if (!a.fp64) return run_adjoint_mfma(a, s);
     hipLaunchKernelGGL(k_splat_adjoint<double>, dim3(int(a.nbricks_total)), dim3(kBrickThreads), 0, s, a);
     return hipGetLastError();

@@ -169,3 +169,35 @@ def small_problem(dims, natoms: int, seed: int, L=(9.0, 10.0, 11.0), zs=(1.0, 4.
     Z = rng.choice(np.asarray(zs), natoms)
     sigma = rng.uniform(sig[0], sig[1], natoms)
     return Problem("small", np.diag(edges), tuple(int(v) for v in dims), pos, Z, sigma, seed)
+
+
+def small_cell_problem(cell, dims, natoms: int, seed: int, zs=(1.0, 4.0, 6.0), sig=(0.6, 1.0)) -> Problem:
+    """Atoms at uniform fractional positions of any (e.g. triclinic) cell; some
+    positions are pushed outside the cell to exercise the wrapping."""
+    rng = np.random.default_rng(seed)
+    cell = np.asarray(cell, dtype=np.float64)
+    frac = rng.random((natoms, 3)) + rng.integers(-1, 2, (natoms, 3))
+    pos = frac @ cell
+    Z = rng.choice(np.asarray(zs), natoms)
+    sigma = rng.uniform(sig[0], sig[1], natoms)
+    return Problem("small_cell", cell, tuple(int(v) for v in dims), pos, Z, sigma, seed)
+
+
+def diamond_fcc1024(seed: int = SEED_BASE + 6) -> Problem:
+    """Diamond in its primitive (FCC, rhombohedral) cell, 8 x 8 x 8 primitive
+    cells of 2 atoms (1,024 atoms), on a 160^3 grid: a non-orthogonal cell for
+    the general-cell splat."""
+    rng = np.random.default_rng(seed)
+    a_conv = 53.93 / 8
+    prim = 0.5 * a_conv * np.array([[0.0, 1.0, 1.0], [1.0, 0.0, 1.0], [1.0, 1.0, 0.0]])
+    reps = 8
+    cell = reps * prim
+    idx = np.array([[i, j, k] for i in range(reps) for j in range(reps) for k in range(reps)], float)
+    # two atoms per primitive cell, at fractional (0, 0, 0) and (1/4, 1/4, 1/4)
+    basis = np.array([[0.0, 0.0, 0.0], [0.25, 0.25, 0.25]]) @ prim
+    sites = ((idx @ prim)[:, None, :] + basis[None, :, :]).reshape(-1, 3)
+    pos = sites + rng.normal(0.0, 0.05, sites.shape)
+    n = pos.shape[0]
+    p = Problem("diamond_fcc1024", cell, (160, 160, 160), pos, np.full(n, 4.0), np.full(n, 0.8), seed)
+    p.extra["fd_atoms"] = np.random.default_rng(seed + 7).choice(n, 16, replace=False)
+    return p

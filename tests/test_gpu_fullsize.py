@@ -199,6 +199,27 @@ def test_diamond16384_radix7(H, oracle_mod):
     assert er <= 2e-6 and ev <= 5e-6 and ee <= 1e-6 and ef <= 1e-4
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_diamond_fcc_general_cell(H, oracle_mod, prec):
+    """Diamond in its primitive FCC cell (1,024 atoms, 160^3): the general-cell
+    splat and adjoint against the oracle, end to end."""
+    p = inputs.diamond_fcc1024()
+    say("case diamond_fcc1024", prec)
+    plan, rho, V, E, F = run_step(H, p, prec)
+    cell9 = p.cell.reshape(9)
+    rho_o = oracle_mod.splat(cell9, p.dims, p.pos, p.Z, p.sigma)
+    V_o, _, E_o, _ = oracle_mod.poisson(cell9, rho_o)
+    atoms = p.extra["fd_atoms"]
+    F_o = oracle_mod.splat_adjoint(cell9, p.pos, p.Z, p.sigma, plan.dv()[0] * V_o, sel=atoms)
+    er = float(np.abs(rho.double().cpu().numpy() - rho_o).max() / np.abs(rho_o).max())
+    ev = rel_l2(V.double().cpu().numpy(), V_o)
+    ee = abs(float(E[0]) - E_o) / E_o
+    ef = float(np.abs(F.cpu().numpy()[atoms] - F_o).max() / np.abs(F_o).max())
+    say("  rho %.2e  V %.2e  E_H %.2e  forces %.2e" % (er, ev, ee, ef))
+    tol = dict(fp64=(1e-12, 1e-12, 1e-12, 1e-10), fp32=(2e-6, 5e-6, 1e-6, 1e-4))[prec]
+    assert er <= tol[0] and ev <= tol[1] and ee <= tol[2] and ef <= tol[3]
+
+
 def test_batched24_against_oracle(H, oracle_mod):
     probs = inputs.batched24()
     say("case batched24: %d problems, %d points" % (len(probs), sum(q.npoints for q in probs)))

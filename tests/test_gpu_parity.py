@@ -104,6 +104,10 @@ SPLAT_CASES = {
     # wider than the cell, so several periodic images meet on one grid point
     "tight_images": lambda: inputs.small_problem((30, 36, 40), 20, seed=3, L=(8.0, 8.5, 9.0)),
     "ragged": lambda: inputs.small_problem((45, 27, 50), 37, seed=4, L=(12.0, 7.5, 14.0), sig=(0.6, 0.9)),
+    # general (non-diagonal) cells: the direct-evaluation kernels
+    "triclinic": lambda: inputs.small_cell_problem(CELLS["triclinic"], (36, 32, 40), 30, seed=5),
+    "triclinic_tight": lambda: inputs.small_cell_problem(
+        np.array([[7.0, 0.0, 0.0], [2.0, 7.5, 0.0], [-1.5, 1.0, 8.0]]), (28, 30, 35), 14, seed=6),
 }
 
 
@@ -198,12 +202,12 @@ def test_rejects_arguments(H):
     with pytest.raises(H.HartreeError) as ei:
         H.Plan(np.zeros((3, 3)), (8, 8, 8))
     assert ei.value.code == 3
-    tri = H.Plan(CELLS["triclinic"], (8, 8, 8), max_atoms=4)
     pos = torch.zeros((1, 3), dtype=torch.float64, device="cuda")
     one = torch.ones(1, dtype=torch.float64, device="cuda")
-    with pytest.raises(H.HartreeError) as ei:
-        tri.splat(pos, one, one)
-    assert ei.value.code == 4
+    tri = H.Plan(CELLS["triclinic"], (8, 8, 8), max_atoms=4)
+    with pytest.raises(H.HartreeError) as ei:  # more atoms than the plan was sized for
+        tri.splat(torch.zeros((5, 3), dtype=torch.float64, device="cuda"), torch.ones(5), torch.ones(5))
+    assert ei.value.code == 1
     plan = H.Plan(np.eye(3) * 8, (8, 8, 8), max_atoms=4, max_sigma=1.0)
     with pytest.raises(H.HartreeError) as ei:
         plan.splat(torch.zeros((5, 3), dtype=torch.float64, device="cuda"), torch.ones(5), torch.ones(5))
