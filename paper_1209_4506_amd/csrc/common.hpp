@@ -101,12 +101,13 @@ struct AtomInfo {
 // at offset r0[x] (mod n) from the window start lo; an unwrapped offset r
 // inside the window width wl has displacement r h - xb, xb = X - lo h.
 struct SlotAtom {
-    float xb[3];
+    float xb[3];    // X - lo h, rounded to float ...
+    float xbl[3];   // ... and the rounding remainder (xb + xbl = X - lo h to double accuracy)
     int32_t r0[3];
     int32_t wl[3];  // 0 for an atom that touches nothing
     float inv2s2;   // 1 / (2 sigma^2)
     float w;        // Z (2 pi sigma^2)^(-3/2)
-    int32_t pad;
+    int32_t pad[2];
 };
 
 struct DeviceStatus {

@@ -27,7 +27,7 @@ constexpr int gen_max_points()
 
 template <typename T>
 struct StagedC {
-    T rb[3];
+    T rb[3], rbl[3];  // rb and its rounding remainder (FP32 carries rb in two floats)
     int r0[3];   // (first index of the brick - lo_x) mod N_x
     int wl[3];   // window width per axis (0: touches nothing)
     T inv2s2, w, rc2;
@@ -48,7 +48,10 @@ __device__ __forceinline__ void stage_general(StagedC<T> *dst, const SplatArgs &
         s.r0[x] = wrapi(bidx[x] * d.bsz[x] - in.lo[x], d.dims[x]);
         s.wl[x] = in.hi[x] >= in.lo[x] ? in.hi[x] - in.lo[x] + 1 : 0;
     }
-    for (int c = 0; c < 3; ++c) s.rb[c] = T(rb[c]);
+    for (int c = 0; c < 3; ++c) {
+        s.rb[c] = T(rb[c]);
+        s.rbl[c] = T(rb[c] - double(s.rb[c]));
+    }
     s.inv2s2 = T(in.inv2s2);
     s.w = T(in.w);
     const double rc = a.cutoff * sqrt(0.5 / in.inv2s2);
@@ -58,9 +61,12 @@ __device__ __forceinline__ void stage_general(StagedC<T> *dst, const SplatArgs &
 
 // Sum over the images of one atom inside its window of f(e, d) for the point
 // at local offsets l = (li, lj, lk) of the brick (g = global index < N).
+// e3 / e3l: the grid steps a / Na, b / Nb, c / Nc and their rounding
+// remainders; each displacement component is formed with one rounding of
+// the large terms (fma chain) plus the small remainder terms
 template <typename T, typename F>
 __device__ __forceinline__ void for_images(const StagedC<T> &at, const int l[3], const int n[3], const T e3[9],
-                                           F f)
+                                           const T e3l[9], F f)
 {
     int u0[3];
     for (int x = 0; x < 3; ++x) {
@@ -73,7 +79,8 @@ __device__ __forceinline__ void for_images(const StagedC<T> &at, const int l[3],
             for (int uc = u0[2]; uc < at.wl[2]; uc += n[2]) {
                 T dv[3];
                 for (int c = 0; c < 3; ++c)
-                    dv[c] = T(ua) * e3[c] + T(ub) * e3[3 + c] + T(uc) * e3[6 + c] - at.rb[c];
+                    dv[c] = fma(T(ua), e3[c], fma(T(ub), e3[3 + c], fma(T(uc), e3[6 + c], -at.rb[c]))) +
+                            (T(ua) * e3l[c] + T(ub) * e3l[3 + c] + T(uc) * e3l[6 + c] - at.rbl[c]);
                 const T d2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
                 if (d2 <= at.rc2) f(expT<T>(-d2 * at.inv2s2), dv);
             }
@@ -122,9 +129,13 @@ __global__ __launch_bounds__(kGenThreads) void k_splat_general(SplatArgs a)
     const int prob = brick_prob(a, b);
     const ProbDesc &d = a.desc[prob];
     const BrickGeom g = brick_geom(d, b);
-    T e3[9];
+    T e3[9], e3l[9];
     for (int x = 0; x < 3; ++x)
-        for (int c = 0; c < 3; ++c) e3[3 * x + c] = T(d.A[3 * x + c] / d.dims[x]);
+        for (int c = 0; c < 3; ++c) {
+            const double e = d.A[3 * x + c] / d.dims[x];
+            e3[3 * x + c] = T(e);
+            e3l[3 * x + c] = T(e - double(e3[3 * x + c]));
+        }
     const int t = threadIdx.x;
     const int64_t off = a.offsets[b];
     const int cnt = int(a.offsets[b + 1] - off);
@@ -142,7 +153,7 @@ __global__ __launch_bounds__(kGenThreads) void k_splat_general(SplatArgs a)
 #pragma unroll 1
             for (int q = 0; q < nc; ++q) {
                 const StagedC<T> &at = atoms[q];
-                for_images<T>(at, l, g.n, e3, [&](T e, const T *) { s += at.w * e; });
+                for_images<T>(at, l, g.n, e3, e3l, [&](T e, const T *) { s += at.w * e; });
             }
             acc[p] = s;
         }
@@ -179,9 +190,13 @@ __global__ __launch_bounds__(kGenThreads) void k_adjoint_general(SplatArgs a)
     const int prob = brick_prob(a, b);
     const ProbDesc &d = a.desc[prob];
     const BrickGeom g = brick_geom(d, b);
-    T e3[9];
+    T e3[9], e3l[9];
     for (int x = 0; x < 3; ++x)
-        for (int c = 0; c < 3; ++c) e3[3 * x + c] = T(d.A[3 * x + c] / d.dims[x]);
+        for (int c = 0; c < 3; ++c) {
+            const double e = d.A[3 * x + c] / d.dims[x];
+            e3[3 * x + c] = T(e);
+            e3l[3 * x + c] = T(e - double(e3[3 * x + c]));
+        }
     const int t = threadIdx.x, wave = t >> 6;
     const int64_t off = a.offsets[b];
     const int cnt = int(a.offsets[b + 1] - off);
@@ -212,7 +227,7 @@ __global__ __launch_bounds__(kGenThreads) void k_adjoint_general(SplatArgs a)
                 brick_point(g, p, l);
                 if (!point_in_grid(g, l)) continue;
                 const T gv = gr[p];
-                for_images<T>(at, l, g.n, e3, [&](T e, const T *dv) {
+                for_images<T>(at, l, g.n, e3, e3l, [&](T e, const T *dv) {
                     const T s = gv * e;
                     f0 += s * dv[0];
                     f1 += s * dv[1];

@@ -68,15 +68,24 @@ __device__ __forceinline__ BrickPos brick_pos(const ProbDesc &d, int64_t b)
 typedef SlotAtom StagedG;
 
 // the problem's per-axis grid data, kept in registers
+// (the spacing h as a float plus its rounding remainder hl)
 struct AxisGrid {
     int n0, n1, n2;
     float h0, h1, h2;
+    float hl0, hl1, hl2;
 };
 
 __device__ __forceinline__ AxisGrid axis_grid(const ProbDesc &d)
 {
-    return {d.dims[0], d.dims[1], d.dims[2], float(d.L[0] / d.dims[0]), float(d.L[1] / d.dims[1]),
-            float(d.L[2] / d.dims[2])};
+    const double h[3] = {d.L[0] / d.dims[0], d.L[1] / d.dims[1], d.L[2] / d.dims[2]};
+    const float hf[3] = {float(h[0]), float(h[1]), float(h[2])};
+    return {d.dims[0], d.dims[1], d.dims[2], hf[0], hf[1], hf[2], float(h[0] - hf[0]), float(h[1] - hf[1]),
+            float(h[2] - hf[2])};
+}
+
+__device__ __forceinline__ float pick(int m0, int m1, int m2, float v0, float v1, float v2)
+{
+    return __int_as_float((__float_as_int(v0) & m0) | (__float_as_int(v1) & m1) | (__float_as_int(v2) & m2));
 }
 
 // threads t < nc copy the records of list entries c0 + t to LDS
@@ -101,11 +110,10 @@ __device__ __forceinline__ Cx<float> brick_entry(const AxisGrid &ag, const Brick
     // fields is turned into an indexed local array, i.e. scratch memory
     const int m0 = -int(x == 0), m1 = -int(x == 1), m2 = -int(x == 2);
     const int n = (ag.n0 & m0) | (ag.n1 & m1) | (ag.n2 & m2);
-    const float h = __int_as_float((__float_as_int(ag.h0) & m0) | (__float_as_int(ag.h1) & m1) |
-                                   (__float_as_int(ag.h2) & m2));
+    const float h = pick(m0, m1, m2, ag.h0, ag.h1, ag.h2), hl = pick(m0, m1, m2, ag.hl0, ag.hl1, ag.hl2);
     const int g = ((p.b0 * kMI) & m0) + ((p.b1 * kMJ) & m1) + ((p.b2 * kMK) & m2) + qq;
-    const float xb = __int_as_float((__float_as_int(at.xb[0]) & m0) | (__float_as_int(at.xb[1]) & m1) |
-                                    (__float_as_int(at.xb[2]) & m2));
+    const float xb = pick(m0, m1, m2, at.xb[0], at.xb[1], at.xb[2]);
+    const float xbl = pick(m0, m1, m2, at.xbl[0], at.xbl[1], at.xbl[2]);
     const int r0 = (at.r0[0] & m0) | (at.r0[1] & m1) | (at.r0[2] & m2);
     const int wl = (at.wl[0] & m0) | (at.wl[1] & m1) | (at.wl[2] & m2);
     float gs = 0.0f, gds = 0.0f;
@@ -113,7 +121,8 @@ __device__ __forceinline__ Cx<float> brick_entry(const AxisGrid &ag, const Brick
         int r = r0 + qq;
         if (r >= n) r -= n;
         for (; r < wl; r += n) {
-            const float dd = float(r) * h - xb;
+            // r h - xb with h and xb each carried as two floats: one rounding
+            const float dd = fmaf(float(r), h, -xb) + (float(r) * hl - xbl);
             const float e = expf(-dd * dd * at.inv2s2);
             gs += e;
             gds += e * dd;
@@ -230,12 +239,12 @@ __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
 
     // The first records are requested before grad_rho, so that storing them
     // to LDS (and evaluating the factors) waits for them alone while the
-    // grad_rho loads are still in flight.  (Three named vectors: a local
-    // array here would live in scratch memory.)
-    static_assert(sizeof(StagedG) == 48, "records move as three 16-byte vectors");
+    // grad_rho loads are still in flight.  (Named vectors: a local array
+    // here would live in scratch memory.)
+    static_assert(sizeof(StagedG) == 64, "records move as four 16-byte vectors");
     const int ns0 = cnt < kStage ? cnt : kStage;
     const uint4 *rsrc = reinterpret_cast<const uint4 *>(a.rec + off + (t < ns0 ? t : 0));
-    const uint4 rr0 = rsrc[0], rr1 = rsrc[1], rr2 = rsrc[2];
+    const uint4 rr0 = rsrc[0], rr1 = rsrc[1], rr2 = rsrc[2], rr3 = rsrc[3];
 
     // grad_rho of this lane's two A rows (local i = 4 wave + col / 16 and
     // + 2, j = col % 16) at points k = 32 bk + 16 half + m, m = 0 .. 15
@@ -289,6 +298,7 @@ __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
         dst[0] = rr0;
         dst[1] = rr1;
         dst[2] = rr2;
+        dst[3] = rr3;
     }
     __syncthreads();
 
