@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--graph", action="store_true",
                     help="also time the step replayed as one captured HIP graph")
     ap.add_argument("--cpu-atoms", type=int, default=4096, help="atoms in the CPU-oracle sample (all of them by default)")
+    ap.add_argument("--atom-order", choices=("given", "shuffled", "bisection"), default="given",
+                    help="atom order handed to the library: as generated (lattice order), a random "
+                         "permutation, or the recursive-bisection order of hartree_atom_partition")
+    ap.add_argument("--atom-parts", type=int, default=64, help="parts of the bisection order")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (to calibrate HBM byte counters)")
@@ -68,6 +72,24 @@ def source_hash():
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
+
+
+def reorder_atoms(prob, mode, nparts, H):
+    """The same atoms in another order; returns (problem, host ms of the partition)."""
+    import dataclasses
+
+    import numpy as np
+
+    if mode == "given":
+        return prob, None
+    t0 = time.perf_counter()
+    if mode == "shuffled":
+        perm = np.random.default_rng(prob.seed + 7).permutation(prob.natoms)
+    else:
+        perm = H.atom_partition(prob.pos, nparts)[0]
+    ms = 1000.0 * (time.perf_counter() - t0)
+    return dataclasses.replace(prob, pos=prob.pos[perm].copy(), Z=prob.Z[perm].copy(),
+                               sigma=prob.sigma[perm].copy()), ms
 
 
 class Step:
@@ -208,7 +230,7 @@ def main():
     import paper_1209_4506_amd.hartree as H
     from paper_1209_4506_amd import inputs
 
-    prob = inputs.diamond360()
+    prob, part_ms = reorder_atoms(inputs.diamond360(), args.atom_order, args.atom_parts, H)
     step = Step(prob, "fp32", torch, H, inputs, tune=not args.no_tune, cache=args.tune_cache)
     assert step.plan.device_status() == 0
     dt, prof = step.timed(args.steps, args.warmup, profile=True)
@@ -257,6 +279,9 @@ def main():
     }
     if graph is not None:
         out["graph_replay"] = graph
+    if args.atom_order != "given":
+        out["atom_order"] = {"mode": args.atom_order, "parts": args.atom_parts if args.atom_order == "bisection" else None,
+                             "host_ms": part_ms}
     if not args.no_fp64:
         del step
         torch.cuda.empty_cache()

@@ -264,6 +264,34 @@ hartree_status hartree_plan_get_config(hartree_plan plan, int32_t *cfg);
 hartree_status hartree_plan_set_config(hartree_plan plan, const int32_t *cfg);
 hartree_status hartree_plan_tune(hartree_plan plan, void *scratch, int32_t reps, void *stream);
 
+/* Atom decomposition (Sec. 3.1): the modified recursive bisection (Sec. 3.1.2)
+ * along inertia-tensor principal axes (Eq. (11)-(18)) with per-atom weights
+ * (Eq. (19)), as laid out in Sec. 3.1.5.  Host code on HOST memory; no device
+ * work, callable without a GPU.
+ *   pos        natoms x 3 doubles, Cartesian positions (Bohr) as given: the
+ *              cell is not consulted, so wrap periodic images first if the
+ *              parts should be compact in the wrapped cell;
+ *   weights    natoms doubles, each finite and > 0 (e.g. Etime_i / Mtime of
+ *              Eq. (19)), or NULL for unit weights;
+ *   nparts     number of parts (processes), >= 1, any value;
+ *   order      out, natoms int32: atom indices grouped by part, parts in the
+ *              order of the bisection tree's leaves (lower projection first),
+ *              atoms inside a part in the order of their last projection;
+ *   part       out, natoms int32: part of each atom, or NULL;
+ *   part_start out, nparts + 1 int32: part p is order[part_start[p] ..
+ *              part_start[p + 1]), or NULL.
+ * A tree node with one part or no atoms is a leaf; otherwise its first
+ * ceil(n/2) parts take the atoms of lowest projection on the axis that
+ * maximises sum_i w_i t_i^2, as many as bring their weight nearest to that
+ * share of the node's weight (ties: the lower side takes one more).  The
+ * centre of Eq. (12) is normalised by the node's total weight, and the axis's
+ * sign makes its largest component positive.  Parts may be empty when nparts
+ * exceeds natoms.  Deterministic: ties in projection go by atom index.
+ * HARTREE_ERR_ARG for a negative count, nparts < 1, a NULL pos (natoms > 0)
+ * or order, a non-finite position, or a weight that is not finite and > 0. */
+hartree_status hartree_atom_partition(int32_t natoms, const double *pos, const double *weights, int32_t nparts,
+                                      int32_t *order, int32_t *part, int32_t *part_start);
+
 /* Description of the last error on the calling thread ("" if none). */
 const char *hartree_last_error(void);
 

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhartree.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["api.hip", "fft_host.hip", "splat.hip", "splat_mfma.hip", "splat_general.hip"] + ["fft_%s_%s.hip" % (k, t) for k in ("a", "b", "r2c", "c2r") for t in ("f32", "f64")]
+SOURCES = ["api.hip", "fft_host.hip", "splat.hip", "splat_mfma.hip", "splat_general.hip", "partition.cpp"] + ["fft_%s_%s.hip" % (k, t) for k in ("a", "b", "r2c", "c2r") for t in ("f32", "f64")]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -11,6 +11,7 @@
 
 #include "../../include/hartree.h"
 #include "fft_core.hpp"
+#include "partition.hpp"
 #include "kernels.hpp"
 
 using namespace hartree;
@@ -1161,6 +1162,14 @@ hartree_status hartree_plan_tune(hartree_plan plan, void *scratch, int32_t reps,
     hartree_status st2 = apply_config(plan, cfg.data());
     if (result != HARTREE_OK) return result;
     return st2 == HARTREE_OK ? ok() : st2;
+}
+
+hartree_status hartree_atom_partition(int32_t natoms, const double *pos, const double *weights, int32_t nparts,
+                                      int32_t *order, int32_t *part, int32_t *part_start)
+{
+    const char *err = bisect_atoms(natoms, pos, weights, nparts, order, part, part_start);
+    if (err) return fail(HARTREE_ERR_ARG, "%s", err);
+    return ok();
 }
 
 const char *hartree_last_error(void) { return g_last_error.c_str(); }

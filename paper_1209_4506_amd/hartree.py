@@ -13,6 +13,8 @@ Names follow the C ABI:
 * ``Plan.backward``        -- hartree_backward: P (grad_v + grad_e dV rho)
 * ``Plan.splat``           -- hartree_splat: Gaussian atomic density
 * ``Plan.splat_adjoint``   -- hartree_splat_adjoint: d/dR of sum grad_rho * rho
+* ``atom_partition``       -- hartree_atom_partition: recursive bisection of
+                              the atoms along inertia-tensor principal axes
 * ``HartreeFn``            -- autograd function (pos -> V, E_H) whose backward
                               applies the symmetric P and the splat adjoint
 """
@@ -74,6 +76,7 @@ def _load():
         "hartree_plan_get_config": [vp, P(i32)],
         "hartree_plan_set_config": [vp, P(i32)],
         "hartree_plan_tune": [vp, vp, i32, vp],
+        "hartree_atom_partition": [i32, P(d), P(d), i32, P(i32), P(i32), P(i32)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -95,7 +98,7 @@ EXPORTED = ["hartree_plan_create", "hartree_plan_create_batched", "hartree_plan_
             "hartree_device_status", "hartree_atoms_bind", "hartree_splat_bound", "hartree_splat_adjoint_bound",
             "hartree_profile_begin", "hartree_profile_end", "hartree_graph_begin", "hartree_graph_end",
             "hartree_graph_launch", "hartree_plan_get_config", "hartree_plan_set_config", "hartree_plan_tune",
-            "hartree_last_error"]
+            "hartree_atom_partition", "hartree_last_error"]
 
 # hartree_kernel_id order
 KERNELS = ["r2c", "r2c_bwd", "fft_b", "fft_a", "fft_a_bwd", "fft_a_eonly", "fft_b_inv", "c2r", "finalize",
@@ -121,6 +124,45 @@ def _opts(cutoff_sigmas=0.0, max_sigma=0.0, max_atoms=0):
     o.max_sigma = float(max_sigma)
     o.max_atoms = int(max_atoms)
     return o
+
+
+def weights_from_times(etime):
+    """Load-balancing weights of Eq. (19): each atom's processing time over the
+    longest one."""
+    t = np.asarray(etime, dtype=np.float64)
+    if t.size == 0:
+        return t.copy()
+    return t / t.max()
+
+
+def atom_partition(pos, nparts, weights=None):
+    """hartree_atom_partition on host arrays (Sec. 3.1).
+
+    ``pos``: (natoms, 3) positions; ``weights``: (natoms,) positive or None.
+    Returns ``(order, part, part_start)`` as int32 numpy arrays: atom indices
+    grouped by part, the part of each atom, and the nparts + 1 offsets of the
+    parts in ``order``.
+    """
+    if isinstance(pos, torch.Tensor):
+        pos = pos.detach().cpu().numpy()
+    pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+    n = pos.shape[0]
+    w = None
+    if weights is not None:
+        if isinstance(weights, torch.Tensor):
+            weights = weights.detach().cpu().numpy()
+        w = np.ascontiguousarray(weights, dtype=np.float64).reshape(-1)
+        if w.shape[0] != n:
+            raise HartreeError(1, "weights must have one entry per atom")
+    order = np.empty(n, dtype=np.int32)
+    part = np.empty(n, dtype=np.int32)
+    start = np.empty(max(int(nparts), 0) + 1, dtype=np.int32)
+    P = ctypes.POINTER
+    dp = lambda a: a.ctypes.data_as(P(ctypes.c_double))  # noqa: E731
+    ip = lambda a: a.ctypes.data_as(P(ctypes.c_int32))  # noqa: E731
+    _check(LIB.hartree_atom_partition(n, dp(pos) if n else None, dp(w) if w is not None else None, int(nparts),
+                                      ip(order), ip(part), ip(start)))
+    return order, part, start
 
 
 class Plan:

@@ -194,6 +194,40 @@ def test_bitwise_reproducible(H):
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("mode", ["bisection", "shuffled"])
+def test_atom_order_equivariance(H, prec, mode):
+    """The atoms in another order (the recursive-bisection order of
+    hartree_atom_partition, or a random one) give the same density and the
+    same forces, permuted: only the rounding order of the sums may change."""
+    say("case atom order", mode, prec, "diamond180")
+    p = inputs.diamond180()
+    if mode == "bisection":
+        perm = H.atom_partition(p.pos, 16)[0].astype(np.int64)
+    else:
+        perm = np.random.default_rng(17).permutation(p.natoms)
+    plan = H.Plan(p.cell, p.dims, precision=prec, max_atoms=p.natoms)
+    g = to_dev(inputs.random_grid(p.dims, 23), plan.dtype)
+    res = []
+    for idx in (np.arange(p.natoms), perm):
+        pos = torch.tensor(p.pos[idx], device="cuda")
+        Z = torch.tensor(p.Z[idx], device="cuda")
+        sig = torch.tensor(p.sigma[idx], device="cuda")
+        tok = plan.bind_atoms(pos, Z, sig)
+        rho = plan.splat_bound(tok).double().cpu().numpy()
+        f = plan.splat_adjoint_bound(tok, g).cpu().numpy()
+        res.append((rho, f))
+    assert plan.device_status() == 0
+    (rho0, f0), (rho1, f1) = res
+    back = np.empty_like(f1)
+    back[perm] = f1
+    er = np.abs(rho1 - rho0).max() / np.abs(rho0).max()
+    ef = np.abs(back - f0).max() / np.abs(f0).max()
+    say("  rho max-rel %.3e  grad max-rel %.3e" % (er, ef))
+    assert er <= (1e-13 if prec == "fp64" else 2e-6)
+    assert ef <= (1e-11 if prec == "fp64" else 1e-5)
+
+
 def test_rejects_arguments(H):
     say("case argument errors")
     with pytest.raises(H.HartreeError) as ei:
