@@ -100,13 +100,18 @@ struct AtomInfo {
 // (written by the binning sort): along axis x the brick's first point lies
 // at offset r0[x] (mod n) from the window start lo; an unwrapped offset r
 // inside the window width wl has displacement r h - xb, xb = X - lo h.
+// One axis of an atom relative to a brick (16 bytes: one vector load).
+struct SlotAxis {
+    float xb;    // X - lo h, rounded to float ...
+    float xbl;   // ... and the rounding remainder (xb + xbl = X - lo h to double accuracy)
+    int32_t r0;  // offset of the brick's first point from the window start, mod n
+    int32_t wl;  // window width in points; 0 for an atom that touches nothing
+};
+
 struct SlotAtom {
-    float xb[3];    // X - lo h, rounded to float ...
-    float xbl[3];   // ... and the rounding remainder (xb + xbl = X - lo h to double accuracy)
-    int32_t r0[3];
-    int32_t wl[3];  // 0 for an atom that touches nothing
-    float inv2s2;   // 1 / (2 sigma^2)
-    float w;        // Z (2 pi sigma^2)^(-3/2)
+    SlotAxis ax[3];
+    float c2;  // log2(e) / (2 sigma^2): the 1-D factor is 2^(-d^2 c2)
+    float w;   // Z (2 pi sigma^2)^(-3/2)
     int32_t pad[2];
 };
 

@@ -294,12 +294,12 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a)
                 const int n = d.dims[x];
                 const double h = d.L[x] / n;
                 const double xb = in.X[x] - in.lo[x] * h;
-                r.xb[x] = float(xb);
-                r.xbl[x] = float(xb - double(r.xb[x]));
-                r.r0[x] = wrapi(bc[x] * d.bsz[x] - in.lo[x], n);
-                r.wl[x] = in.hi[x] >= in.lo[x] ? in.hi[x] - in.lo[x] + 1 : 0;
+                r.ax[x].xb = float(xb);
+                r.ax[x].xbl = float(xb - double(r.ax[x].xb));
+                r.ax[x].r0 = wrapi(bc[x] * d.bsz[x] - in.lo[x], n);
+                r.ax[x].wl = in.hi[x] >= in.lo[x] ? in.hi[x] - in.lo[x] + 1 : 0;
             }
-            r.inv2s2 = float(in.inv2s2);
+            r.c2 = float(1.4426950408889634073599246810019 * in.inv2s2);
             r.w = float(in.w);
             r.pad[0] = r.pad[1] = 0;
             a.rec[off + rank] = r;

@@ -10,7 +10,7 @@
 //            F_a = sum_c [gdx gy S0, gx gdy S0, gx gy S1]
 //
 // with the per-axis factors gx, gdx, ... (1-D periodic Gaussians and their
-// displacement-weighted sums) read from the per-atom tables.  The 256
+// displacement-weighted sums) evaluated in the kernel from per-slot records.  The 256
 // columns (c = 16 i + j) form 8 row tiles of 32; wavefront w owns tiles 2w
 // and 2w + 1, i.e. local i = 4w, 4w + 1 and 4w + 2, 4w + 3.
 //
@@ -67,25 +67,31 @@ __device__ __forceinline__ BrickPos brick_pos(const ProbDesc &d, int64_t b)
 // exp(-d^2 / (2 sigma^2)).
 typedef SlotAtom StagedG;
 
-// the problem's per-axis grid data, kept in registers
-// (the spacing h as a float plus its rounding remainder hl)
-struct AxisGrid {
-    int n0, n1, n2;
-    float h0, h1, h2;
-    float hl0, hl1, hl2;
+// What lane q (0 .. 63) of a wavefront evaluates for every atom: entry q of
+// the atom's factor row over this brick, q < 16 along a, q < 32 along b, the
+// rest along c.  Fixed per lane for the whole kernel, kept in registers: the
+// axis, the point's offset within the brick and its grid index, the axis
+// length, and the spacing h as a float plus its rounding remainder hl.
+struct LaneAxis {
+    int x, qq, g, n;
+    float h, hl;
 };
 
-__device__ __forceinline__ AxisGrid axis_grid(const ProbDesc &d)
-{
-    const double h[3] = {d.L[0] / d.dims[0], d.L[1] / d.dims[1], d.L[2] / d.dims[2]};
-    const float hf[3] = {float(h[0]), float(h[1]), float(h[2])};
-    return {d.dims[0], d.dims[1], d.dims[2], hf[0], hf[1], hf[2], float(h[0] - hf[0]), float(h[1] - hf[1]),
-            float(h[2] - hf[2])};
-}
+static_assert(kRow == 64, "one factor entry per lane");
+static_assert(kMI == kMJ, "a and b share one brick edge");
 
-__device__ __forceinline__ float pick(int m0, int m1, int m2, float v0, float v1, float v2)
+__device__ __forceinline__ LaneAxis lane_axis(const ProbDesc &d, const BrickPos &p, int q)
 {
-    return __int_as_float((__float_as_int(v0) & m0) | (__float_as_int(v1) & m1) | (__float_as_int(v2) & m2));
+    LaneAxis la;
+    la.x = q < kMI ? 0 : (q < kMI + kMJ ? 1 : 2);
+    la.qq = q - (la.x == 0 ? 0 : (la.x == 1 ? kMI : kMI + kMJ));
+    const int b = la.x == 0 ? p.b0 * kMI : (la.x == 1 ? p.b1 * kMJ : p.b2 * kMK);
+    la.g = b + la.qq;
+    la.n = d.dims[la.x];
+    const double h = d.L[la.x] / la.n;
+    la.h = float(h);
+    la.hl = float(h - double(la.h));
+    return la;
 }
 
 // threads t < nc copy the records of list entries c0 + t to LDS
@@ -94,52 +100,66 @@ __device__ __forceinline__ void stage_g(StagedG *dst, const SplatArgs &a, int64_
     if (t < nc) dst[t] = a.rec[off + c0 + t];
 }
 
-// Entry q (0 .. 63) of one staged atom's factors over this brick: q < 16
-// along a, q < 32 along b, the rest along c; returns (g, gd) with gd the
-// displacement-weighted factor.  A wavefront fills one atom per round, lane =
-// entry.
-static_assert(kRow == 64, "one factor entry per lane");
-static_assert(kMI == kMJ, "a and b share one brick edge");
+struct Entry {
+    float g, gd, w;  // factor, displacement-weighted factor, the atom's weight
+    bool more;       // the window holds further images of this point
+};
 
-__device__ __forceinline__ Cx<float> brick_entry(const AxisGrid &ag, const BrickPos &p, const StagedG &at, int q,
-                                                 bool use)
+// This lane's entry of one staged atom (a record in LDS): g = sum over the
+// unwrapped images r, r + n, ... inside the window of 2^(-d^2 c2) with
+// d = r h - xb, and gd = the same sum weighted by d.  brick_entry takes the
+// first image without branches; more_images adds the others, which exist
+// only for windows wider than the cell (callers run it when any lane of any
+// atom reports `more`, so the common path stays straight-line code).
+__device__ __forceinline__ float axis_disp(const LaneAxis &la, float xb, float xbl, int r)
 {
-    const int x = q < kMI ? 0 : (q < kMI + kMJ ? 1 : 2);
-    const int qq = q - (x == 0 ? 0 : (x == 1 ? kMI : kMI + kMJ));
-    // per-axis values selected with bit masks: a select chain over struct
-    // fields is turned into an indexed local array, i.e. scratch memory
-    const int m0 = -int(x == 0), m1 = -int(x == 1), m2 = -int(x == 2);
-    const int n = (ag.n0 & m0) | (ag.n1 & m1) | (ag.n2 & m2);
-    const float h = pick(m0, m1, m2, ag.h0, ag.h1, ag.h2), hl = pick(m0, m1, m2, ag.hl0, ag.hl1, ag.hl2);
-    const int g = ((p.b0 * kMI) & m0) + ((p.b1 * kMJ) & m1) + ((p.b2 * kMK) & m2) + qq;
-    const float xb = pick(m0, m1, m2, at.xb[0], at.xb[1], at.xb[2]);
-    const float xbl = pick(m0, m1, m2, at.xbl[0], at.xbl[1], at.xbl[2]);
-    const int r0 = (at.r0[0] & m0) | (at.r0[1] & m1) | (at.r0[2] & m2);
-    const int wl = (at.wl[0] & m0) | (at.wl[1] & m1) | (at.wl[2] & m2);
-    float gs = 0.0f, gds = 0.0f;
-    if (use && g < n) {
-        int r = r0 + qq;
-        if (r >= n) r -= n;
-        for (; r < wl; r += n) {
-            // r h - xb with h and xb each carried as two floats: one rounding
-            const float dd = fmaf(float(r), h, -xb) + (float(r) * hl - xbl);
-            const float e = expf(-dd * dd * at.inv2s2);
-            gs += e;
-            gds += e * dd;
-        }
-    }
-    return Cx<float>{gs, gds};
+    // r h - xb with h and xb each carried as two floats: one rounding
+    return fmaf(float(r), la.h, -xb) + (float(r) * la.hl - xbl);
 }
+
+__device__ __forceinline__ Entry brick_entry(const LaneAxis &la, const StagedG *at, bool use)
+{
+    const float4 rx = *reinterpret_cast<const float4 *>(&at->ax[la.x]);
+    const float2 cw = *reinterpret_cast<const float2 *>(&at->c2);
+    const int r0 = __float_as_int(rx.z), wl = __float_as_int(rx.w);
+    const bool ok = use && la.g < la.n;
+    int r = r0 + la.qq;
+    r = r >= la.n ? r - la.n : r;
+    const float dd = axis_disp(la, rx.x, rx.y, r);
+    float e = __builtin_amdgcn_exp2f(-(dd * dd) * cw.x);
+    e = (ok && r < wl) ? e : 0.0f;
+    return Entry{e, e * dd, cw.y, ok && r + la.n < wl};
+}
+
+__device__ __forceinline__ void more_images(const LaneAxis &la, const StagedG *at, bool use, float &gs, float &gds)
+{
+    const float4 rx = *reinterpret_cast<const float4 *>(&at->ax[la.x]);
+    const float c2 = at->c2;
+    const int r0 = __float_as_int(rx.z), wl = __float_as_int(rx.w);
+    if (!(use && la.g < la.n)) return;
+    int r = r0 + la.qq;
+    r = r >= la.n ? r - la.n : r;
+    for (r += la.n; r < wl; r += la.n) {
+        const float dd = axis_disp(la, rx.x, rx.y, r);
+        const float e = __builtin_amdgcn_exp2f(-(dd * dd) * c2);
+        gs += e;
+        gds += e * dd;
+    }
+}
+
+// LDS pitch of a staged atom's factor row (64 entries): the z entries of
+// atoms 2m and 2m + 1, read by the two lane halves together, fall in
+// different halves of the 64 banks
+constexpr int kFacPitch = 96;
 
 __global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
 {
     __shared__ StagedG recs[kStage];
-    __shared__ float gxw[kSplatChunk][kMI + 1], gy[kSplatChunk][kMJ + 1], gz[kSplatChunk][kMK + 1];
+    __shared__ float fac[kSplatChunk][kFacPitch];  // per atom: W gx (16), gy (16), gz (32)
     const int64_t b = brick_of_block();
     const int prob = brick_prob(a, b);
     const ProbDesc &d = a.desc[prob];
     const BrickPos p = brick_pos(d, b);
-    const AxisGrid ag = axis_grid(d);
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
     const int64_t off = a.offsets[b];
@@ -148,6 +168,7 @@ __global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
     // this lane's A rows: column 32 (2 wave + u) + col, i.e. local
     // i = 4 wave + 2 u + col / 16 and j = col % 16, for u = 0, 1
     const int i0 = 4 * wave + (col >> 4), jj = col & 15;
+    const LaneAxis la = lane_axis(d, p, lane);
 
     floatx16 acc0, acc1;
 #pragma unroll
@@ -166,35 +187,40 @@ __global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
         const StagedG *atoms = recs + c0 % kStage;
         {
             constexpr int R = kSplatChunk / 4;  // rounds: atoms per wavefront
-            float v[R];
+            float v[R], wv[R];
+            bool more = false;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int s = wave + 4 * r;
-                const StagedG &at = atoms[s < ns ? s : 0];
-                float x = brick_entry(ag, p, at, lane, s < ns).x;
-                if (lane < kMI) x *= at.w;
-                v[r] = x;
+                const Entry e = brick_entry(la, atoms + (s < ns ? s : 0), s < ns);
+                v[r] = e.g;
+                wv[r] = e.w;
+                more = more || e.more;
+            }
+            if (__builtin_expect(__any(more), 0)) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int s = wave + 4 * r;
+                    float gd = 0.0f;
+                    more_images(la, atoms + (s < ns ? s : 0), s < ns, v[r], gd);
+                }
             }
 #pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (la.x == 0) v[r] *= wv[r];
+#pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int s = wave + 4 * r;
-                if (s < 2 * npair) {  // a padding atom gets zero rows
-                    if (lane < kMI)
-                        gxw[s][lane] = v[r];
-                    else if (lane < kMI + kMJ)
-                        gy[s][lane - kMI] = v[r];
-                    else
-                        gz[s][lane - kMI - kMJ] = v[r];
-                }
+                if (s < 2 * npair) fac[s][lane] = v[r];  // a padding atom gets zero rows
             }
         }
         __syncthreads();
         for (int m = 0; m < npair; ++m) {
             const int s = 2 * m + kk;
-            const float y = gy[s][jj];
-            const float bv = gz[s][col];
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(gxw[s][i0] * y, bv, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(gxw[s][i0 + 2] * y, bv, acc1, 0, 0, 0);
+            const float y = fac[s][kMI + jj];
+            const float bv = fac[s][kMI + kMJ + col];
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(fac[s][i0] * y, bv, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(fac[s][i0 + 2] * y, bv, acc1, 0, 0, 0);
         }
         __syncthreads();
     }
@@ -221,21 +247,20 @@ template <bool VEC>
 __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
 {
     __shared__ StagedG recs[kStage];
-    __shared__ float gx[kAdjChunk][kMI + 1], gdx[kAdjChunk][kMI + 1];
-    __shared__ float gy[kAdjChunk][kMJ + 1], gdy[kAdjChunk][kMJ + 1];
+    __shared__ float gxy[kAdjChunk][kMI + kMJ + 1], gdxy[kAdjChunk][kMI + kMJ + 1];  // gx | gy, gdx | gdy
     __shared__ float gzt[kAdjGroups][2 * kAdjGroup][kMK + 1];  // per group: gz rows, then gdz rows
     __shared__ float red[4][2][2 * kAdjGroup][kAdjGroups][2];  // [wave][lane half][n][group][component]
     const int64_t b = brick_of_block();
     const int prob = brick_prob(a, b);
     const ProbDesc &d = a.desc[prob];
     const BrickPos p = brick_pos(d, b);
-    const AxisGrid ag = axis_grid(d);
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
     const int64_t off = a.offsets[b];
     const int cnt = int(a.offsets[b + 1] - off);
     if (cnt == 0) return;
     const int half = lane >> 5, col = lane & 31;
+    const LaneAxis la = lane_axis(d, p, lane);
 
     // The first records are requested before grad_rho, so that storing them
     // to LDS (and evaluating the factors) waits for them alone while the
@@ -312,27 +337,32 @@ __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
         const StagedG *atoms = recs + c0 % kStage;
         {
             constexpr int R = kAdjChunk / 4;  // rounds: atoms per wavefront
-            Cx<float> v[R];
+            Entry v[R];
+            bool more = false;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int s = wave + 4 * r;
-                v[r] = brick_entry(ag, p, atoms[s < ns ? s : 0], lane, s < ns);
+                v[r] = brick_entry(la, atoms + (s < ns ? s : 0), s < ns);
+                more = more || v[r].more;
             }
+            if (__builtin_expect(__any(more), 0)) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int s = wave + 4 * r;
+                    more_images(la, atoms + (s < ns ? s : 0), s < ns, v[r].g, v[r].gd);
+                }
+            }
+            const bool xy = lane < kMI + kMJ;
+            const int zq = lane - kMI - kMJ;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int s = wave + 4 * r;
                 if (s < ngroup * kAdjGroup) {  // padding atoms give zero columns
-                    if (lane < kMI) {
-                        gx[s][lane] = v[r].x;
-                        gdx[s][lane] = v[r].y;
-                    } else if (lane < kMI + kMJ) {
-                        gy[s][lane - kMI] = v[r].x;
-                        gdy[s][lane - kMI] = v[r].y;
-                    } else {
-                        const int g = s / kAdjGroup, st = s - g * kAdjGroup;
-                        gzt[g][st][lane - kMI - kMJ] = v[r].x;
-                        gzt[g][kAdjGroup + st][lane - kMI - kMJ] = v[r].y;
-                    }
+                    const int g = s / kAdjGroup, st = s - g * kAdjGroup;
+                    float *pg = xy ? &gxy[s][lane] : &gzt[g][st][zq];
+                    float *pd = xy ? &gdxy[s][lane] : &gzt[g][kAdjGroup + st][zq];
+                    *pg = v[r].g;
+                    *pd = v[r].gd;
                 }
             }
         }
@@ -347,8 +377,8 @@ __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
                 const int j = mfma_row(r, lane) & 15;
-                yv[r] = gy[s][j];
-                dyv[r] = gdy[s][j];
+                yv[r] = gxy[s][kMI + j];
+                dyv[r] = gdxy[s][kMI + j];
             }
             float ax = 0.0f, ay = 0.0f;  // f = 0: (x, y) components; f = 1: z in ax
 #pragma unroll
@@ -370,10 +400,10 @@ __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
                         sdy += dyv[r] * acc[8 * h + r];
                     }
                     if (f == 0) {
-                        ax += gdx[s][i] * sy;
-                        ay += gx[s][i] * sdy;
+                        ax += gdxy[s][i] * sy;
+                        ay += gxy[s][i] * sdy;
                     } else {
-                        ax += gx[s][i] * sy;
+                        ax += gxy[s][i] * sy;
                     }
                 }
             }
