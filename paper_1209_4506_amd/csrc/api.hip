@@ -156,6 +156,7 @@ struct hartree_plan_s {
            ws_size = 0;
     int32_t cap_pa = 0;
     int32_t wcap = 0;  // per-atom factor table row length
+    bool wide = false;  // some truncation window can hold two images of one grid point
     unsigned char *ws = nullptr;
     // profiling: events bracketing each kernel group
     struct ProfRec {
@@ -420,6 +421,7 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
                                         d.B[3 * x + 2] * d.B[3 * x + 2]);
             const double h = 6.283185307179586476925286766559 / (bn * N[x]);
             const double w = std::floor(2.0 * p->cutoff * p->max_sigma / h) + 1.0;
+            if (w + 1.0 > N[x]) p->wide = true;  // window points (+1 for rounding) exceed the axis
             int64_t nbx = d.nbricks[x];  // most bricks one atom's window touches along x
             if (w < N[x]) {
                 const int64_t bnd = int64_t(std::ceil((w - 1.0) / bsz[x])) + 2;
@@ -581,6 +583,7 @@ SplatArgs splat_args(hartree_plan p, int32_t natoms, const double *pos, const do
     a.slot_of = reinterpret_cast<int32_t *>(p->ws + p->o_slot);
     a.rec = (p->fp64 || p->general) ? nullptr : reinterpret_cast<SlotAtom *>(p->ws + p->o_rec);
     a.general = p->general ? 1 : 0;
+    a.wide = p->wide ? 1 : 0;
     a.zeros = reinterpret_cast<const float *>(p->ws + p->o_zero);
     a.cap_pa = p->cap_pa;
     a.tab = p->ws + p->o_tab;

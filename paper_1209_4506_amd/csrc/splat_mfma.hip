@@ -35,12 +35,9 @@ __device__ __forceinline__ int mfma_row(int r, int lane) { return 8 * (r >> 2) +
 __device__ __forceinline__ int64_t brick_of_block() { return xcd_remap(blockIdx.x, gridDim.x); }
 
 constexpr int kMThreads = 256;   // four wavefronts per brick
-constexpr int kSplatChunk = 64;  // atoms staged per pass (splat)
-constexpr int kAdjChunk = 32;    // atoms staged per pass (adjoint)
 constexpr int kAdjGroup = 16;    // atoms per MFMA column tile: 16 atoms x (g, gd)
-constexpr int kAdjGroups = kAdjChunk / kAdjGroup;
 constexpr int kStage = 128;      // atom records staged at once (whole lists, almost always)
-static_assert(kStage % kSplatChunk == 0 && kStage % kAdjChunk == 0 && kStage <= kMThreads, "record staging");
+static_assert(kStage % kAdjGroup == 0 && kStage <= kMThreads, "record staging");
 constexpr int kRow = kMI + kMJ + kMK;  // table entries one atom needs in one brick
 
 // A brick's position (brick index per axis), kept in registers
@@ -152,10 +149,65 @@ __device__ __forceinline__ void more_images(const LaneAxis &la, const StagedG *a
 // different halves of the 64 banks
 constexpr int kFacPitch = 96;
 
+// Splat pipeline step: kSub atoms (kSub / 2 matrix products per tile).
+// While the products of step c run on the matrix cores, the wavefronts
+// evaluate the factors of step c + 1 into the other LDS buffer, so the
+// vector work fills the matrix cores' shadow.
+constexpr int kSub = 8;
+static_assert(kSub % 4 == 0 && kStage % kSub == 0, "pipeline step");
+
+// factors of staged atoms s0 .. s0 + kSub - 1 into dst (zeros past nb):
+// row s: W gx (entries 0 .. 15), gy (16 .. 31), gz (32 .. 63).  WIDE: some
+// window may hold several images of a point (otherwise the first image is
+// the only one, and the step stays one straight-line block)
+template <bool WIDE>
+__device__ __forceinline__ void splat_factors(float (*dst)[kFacPitch], const StagedG *recs, const LaneAxis &la,
+                                              int s0, int nb, int wave, int lane)
+{
+    constexpr int R = kSub / 4;  // atoms per wavefront
+    float v[R], wv[R];
+    bool more = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int s = s0 + wave + 4 * r;
+        const Entry e = brick_entry(la, recs + (s < nb ? s : 0), s < nb);
+        v[r] = e.g;
+        wv[r] = e.w;
+        more = more || e.more;
+    }
+    if constexpr (WIDE) {
+        if (__any(more)) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int s = s0 + wave + 4 * r;
+                float gd = 0.0f;
+                more_images(la, recs + (s < nb ? s : 0), s < nb, v[r], gd);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[wave + 4 * r][lane] = la.x == 0 ? v[r] * wv[r] : v[r];
+}
+
+// products of one step: atom 2 m + kk of the step in K slot kk
+__device__ __forceinline__ void splat_products(const float (*f)[kFacPitch], int kk, int col, int i0, int jj,
+                                               floatx16 &acc0, floatx16 &acc1)
+{
+#pragma unroll
+    for (int m = 0; m < kSub / 2; ++m) {
+        const int s = 2 * m + kk;
+        const float y = f[s][kMI + jj];
+        const float bv = f[s][kMI + kMJ + col];
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(f[s][i0] * y, bv, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(f[s][i0 + 2] * y, bv, acc1, 0, 0, 0);
+    }
+}
+
+template <bool WIDE>
 __global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
 {
     __shared__ StagedG recs[kStage];
-    __shared__ float fac[kSplatChunk][kFacPitch];  // per atom: W gx (16), gy (16), gz (32)
+    __shared__ float fac[2][kSub][kFacPitch];  // double buffer of pipeline steps
     const int64_t b = brick_of_block();
     const int prob = brick_prob(a, b);
     const ProbDesc &d = a.desc[prob];
@@ -170,86 +222,180 @@ __global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
     const int i0 = 4 * wave + (col >> 4), jj = col & 15;
     const LaneAxis la = lane_axis(d, p, lane);
 
+    // the accumulators start at the background -Q / Omega
+    const float bg = a.subtract_background ? float(a.qsum[prob] / (d.L[0] * d.L[1] * d.L[2])) : 0.0f;
     floatx16 acc0, acc1;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        acc0[r] = 0.0f;
-        acc1[r] = 0.0f;
+        acc0[r] = -bg;
+        acc1[r] = -bg;
     }
 
-    for (int c0 = 0; c0 < cnt; c0 += kSplatChunk) {
-        const int ns = (cnt - c0) < kSplatChunk ? (cnt - c0) : kSplatChunk;
-        const int npair = (ns + 1) >> 1;
-        if (c0 % kStage == 0) {
-            stage_g(recs, a, off, c0, (cnt - c0) < kStage ? (cnt - c0) : kStage, t);
+    for (int blk = 0; blk < cnt; blk += kStage) {
+        const int nb = (cnt - blk) < kStage ? (cnt - blk) : kStage;
+        stage_g(recs, a, off, blk, nb, t);
+        __syncthreads();
+        const int nsub = (nb + kSub - 1) / kSub;
+        splat_factors<WIDE>(fac[0], recs, la, 0, nb, wave, lane);
+        __syncthreads();
+        for (int c = 0; c + 1 < nsub; ++c) {
+            splat_factors<WIDE>(fac[(c + 1) & 1], recs, la, (c + 1) * kSub, nb, wave, lane);
+            splat_products(fac[c & 1], kk, col, i0, jj, acc0, acc1);
             __syncthreads();
         }
-        const StagedG *atoms = recs + c0 % kStage;
-        {
-            constexpr int R = kSplatChunk / 4;  // rounds: atoms per wavefront
-            float v[R], wv[R];
-            bool more = false;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int s = wave + 4 * r;
-                const Entry e = brick_entry(la, atoms + (s < ns ? s : 0), s < ns);
-                v[r] = e.g;
-                wv[r] = e.w;
-                more = more || e.more;
-            }
-            if (__builtin_expect(__any(more), 0)) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int s = wave + 4 * r;
-                    float gd = 0.0f;
-                    more_images(la, atoms + (s < ns ? s : 0), s < ns, v[r], gd);
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (la.x == 0) v[r] *= wv[r];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int s = wave + 4 * r;
-                if (s < 2 * npair) fac[s][lane] = v[r];  // a padding atom gets zero rows
-            }
-        }
-        __syncthreads();
-        for (int m = 0; m < npair; ++m) {
-            const int s = 2 * m + kk;
-            const float y = fac[s][kMI + jj];
-            const float bv = fac[s][kMI + kMJ + col];
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(fac[s][i0] * y, bv, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(fac[s][i0 + 2] * y, bv, acc1, 0, 0, 0);
-        }
-        __syncthreads();
+        splat_products(fac[(nsub - 1) & 1], kk, col, i0, jj, acc0, acc1);
+        __syncthreads();  // recs and fac are reused by the next block
     }
-    const float bg = a.subtract_background ? float(a.qsum[prob] / (d.L[0] * d.L[1] * d.L[2])) : 0.0f;
+    float *out = reinterpret_cast<float *>(a.rho) + d.grid_off;
+    const int64_t sb = d.dims[2], sa = int64_t(d.dims[1]) * d.dims[2];  // row strides along b and a
+    if ((p.b0 + 1) * kMI <= d.dims[0] && (p.b1 + 1) * kMJ <= d.dims[1] && (p.b2 + 1) * kMK <= d.dims[2]) {
+        // a brick inside the grid: the row of accumulator element r is
+        // uniform across the wavefront apart from the lane's j offset 4 kk,
+        // so each store is a wavefront-uniform base plus a 32-bit lane offset
+        const int w = __builtin_amdgcn_readfirstlane(wave);
+        float *base = out + (int64_t(p.b0 * kMI + 4 * w) * d.dims[1] + p.b1 * kMJ) * sb + p.b2 * kMK;
+        const uint32_t loff = uint32_t(4 * kk * d.dims[2] + col);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int c8 = 8 * (r >> 2) + (r & 3);  // mfma_row without the lane's 4 kk (never crosses a 16-row line)
+            float *row = base + ((c8 >> 4) * sa + (c8 & 15) * sb);
+            row[loff] = acc0[r];
+            row[2 * sa + loff] = acc1[r];
+        }
+        return;
+    }
     const int k = p.b2 * kMK + col;
     if (k >= d.dims[2]) return;
-    float *out = reinterpret_cast<float *>(a.rho) + d.grid_off;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int c = mfma_row(r, lane);  // row within the tile: local i offset c / 16, j = c % 16
         const int j = p.b1 * kMJ + (c & 15);
         const int ia = p.b0 * kMI + 4 * wave + (c >> 4);
         if (j < d.dims[1]) {
-            if (ia < d.dims[0]) out[(int64_t(ia) * d.dims[1] + j) * d.dims[2] + k] = acc0[r] - bg;
-            if (ia + 2 < d.dims[0]) out[(int64_t(ia + 2) * d.dims[1] + j) * d.dims[2] + k] = acc1[r] - bg;
+            if (ia < d.dims[0]) out[(int64_t(ia) * d.dims[1] + j) * d.dims[2] + k] = acc0[r];
+            if (ia + 2 < d.dims[0]) out[(int64_t(ia + 2) * d.dims[1] + j) * d.dims[2] + k] = acc1[r];
         }
+    }
+}
+
+// Adjoint pipeline step: one group of kAdjGroup atoms.  Its factors sit in
+// one of two LDS buffers: gx | gy and gdx | gdy rows per atom, and the gz,
+// gdz rows of the group's 32 matrix columns.
+struct AdjBuf {
+    float gxy[kAdjGroup][kMI + kMJ + 1], gdxy[kAdjGroup][kMI + kMJ + 1];
+    float gz[2 * kAdjGroup][kMK + 1];  // columns n < 16: gz of atom n; n >= 16: gdz of atom n - 16
+};
+
+// factors of staged atoms s0 .. s0 + kAdjGroup - 1 into buf (zeros past nb)
+template <bool WIDE>
+__device__ __forceinline__ void adjoint_factors(AdjBuf &buf, const StagedG *recs, const LaneAxis &la, int s0, int nb,
+                                                int wave, int lane)
+{
+    constexpr int R = kAdjGroup / 4;  // atoms per wavefront
+    Entry v[R];
+    bool more = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int s = s0 + wave + 4 * r;
+        v[r] = brick_entry(la, recs + (s < nb ? s : 0), s < nb);
+        more = more || v[r].more;
+    }
+    if constexpr (WIDE) {
+        if (__any(more)) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int s = s0 + wave + 4 * r;
+                more_images(la, recs + (s < nb ? s : 0), s < nb, v[r].g, v[r].gd);
+            }
+        }
+    }
+    const bool xy = lane < kMI + kMJ;
+    const int zq = lane - kMI - kMJ;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int st = wave + 4 * r;
+        float *pg = xy ? &buf.gxy[st][lane] : &buf.gz[st][zq];
+        float *pd = xy ? &buf.gdxy[st][lane] : &buf.gz[kAdjGroup + st][zq];
+        *pg = v[r].g;
+        *pd = v[r].gd;
+    }
+}
+
+// One group's products and fold.  Lane l holds S[row][n] for column
+// n = l % 32 (function f = n / 16 of atom n % 16) and 16 rows of each of its
+// two tiles: row r of tile u is local i = 4 wave + 2 u + r / 8 and
+// j = 8 ((r / 4) % 2) + 4 half + r % 4, so the eight j values (and their gy,
+// gdy) are the same for both tiles and both halves r / 8.  Writes the lane's
+// two partial components to red[n][0 .. 1].
+__device__ __forceinline__ void adjoint_group(const AdjBuf &buf, const float (&g0)[16], const float (&g1)[16], int wave,
+                                              int lane, float (*red)[2])
+{
+    const int half = lane >> 5, n = lane & 31;
+    const int f = n >> 4, sl = n & 15;
+    float yv[8], dyv[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int j = mfma_row(r, lane) & 15;
+        yv[r] = buf.gxy[sl][kMI + j];
+        dyv[r] = buf.gdxy[sl][kMI + j];
+    }
+    float ax = 0.0f, ay = 0.0f;  // f = 0: (x, y) components; f = 1: z in ax
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        floatx16 acc;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+#pragma unroll
+        for (int m = 0; m < 16; ++m)
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(u == 0 ? g0[m] : g1[m], buf.gz[n][16 * half + m], acc, 0, 0, 0);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = 4 * wave + 2 * u + h;
+            float sy = 0.0f, sdy = 0.0f;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                sy += yv[r] * acc[8 * h + r];
+                sdy += dyv[r] * acc[8 * h + r];
+            }
+            if (f == 0) {
+                ax += buf.gdxy[sl][i] * sy;
+                ay += buf.gxy[sl][i] * sdy;
+            } else {
+                ax += buf.gxy[sl][i] * sy;
+            }
+        }
+    }
+    red[n][0] = ax;
+    red[n][1] = ay;
+}
+
+// fixed-order sum over the 4 waves and 2 lane halves, in double, of the
+// partials of atoms s0 .. s0 + kAdjGroup - 1 (below nb): threads t < 48
+__device__ __forceinline__ void adjoint_reduce(const SplatArgs &a, const float (*red)[2][2 * kAdjGroup][2], int64_t slot0,
+                                               int s0, int nb, int t)
+{
+    if (t < 3 * kAdjGroup) {
+        const int st = t / 3, x = t - 3 * st;
+        const int nn = x == 2 ? kAdjGroup + st : st;
+        const int comp = x == 1 ? 1 : 0;
+        double v = 0.0;
+        for (int w = 0; w < 4; ++w) v += double(red[w][0][nn][comp]) + double(red[w][1][nn][comp]);
+        const int64_t slot = slot0 + s0 + st;
+        if (s0 + st < nb && slot < a.capacity) a.bpart[slot * 3 + x] = v;
     }
 }
 
 // adjoint: wave w holds grad_rho of its two row tiles in registers; per
 // group of 16 staged atoms it forms S for both tiles (32 columns n = 16 f +
-// atom) and folds the transverse factors in.
-template <bool VEC>
+// atom) and folds the transverse factors in.  While a group's products run
+// on the matrix cores, the factors of the next group are evaluated, and the
+// previous group's partials are reduced.
+template <bool VEC, bool WIDE>
 __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
 {
     __shared__ StagedG recs[kStage];
-    __shared__ float gxy[kAdjChunk][kMI + kMJ + 1], gdxy[kAdjChunk][kMI + kMJ + 1];  // gx | gy, gdx | gdy
-    __shared__ float gzt[kAdjGroups][2 * kAdjGroup][kMK + 1];  // per group: gz rows, then gdz rows
-    __shared__ float red[4][2][2 * kAdjGroup][kAdjGroups][2];  // [wave][lane half][n][group][component]
+    __shared__ AdjBuf buf[2];
+    __shared__ float red[2][4][2][2 * kAdjGroup][2];  // [step parity][wave][lane half][n][component]
     const int64_t b = brick_of_block();
     const int prob = brick_prob(a, b);
     const ProbDesc &d = a.desc[prob];
@@ -312,8 +458,6 @@ __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
             }
         }
     }
-    const int n = col;  // this lane's C column: function f = n / 16 of atom n % 16
-    const int f = n >> 4, sl = n & 15;
 
     // keep the grad_rho loads issued above this point (the compiler would
     // otherwise sink them below the record store and its wait)
@@ -327,117 +471,48 @@ __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
     }
     __syncthreads();
 
-    for (int c0 = 0; c0 < cnt; c0 += kAdjChunk) {
-        const int ns = (cnt - c0) < kAdjChunk ? (cnt - c0) : kAdjChunk;
-        const int ngroup = (ns + kAdjGroup - 1) / kAdjGroup;
-        if (c0 > 0 && c0 % kStage == 0) {
-            stage_g(recs, a, off, c0, (cnt - c0) < kStage ? (cnt - c0) : kStage, t);
+    for (int blk = 0; blk < cnt; blk += kStage) {
+        const int nb = (cnt - blk) < kStage ? (cnt - blk) : kStage;
+        if (blk > 0) {
+            stage_g(recs, a, off, blk, nb, t);
             __syncthreads();
         }
-        const StagedG *atoms = recs + c0 % kStage;
-        {
-            constexpr int R = kAdjChunk / 4;  // rounds: atoms per wavefront
-            Entry v[R];
-            bool more = false;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int s = wave + 4 * r;
-                v[r] = brick_entry(la, atoms + (s < ns ? s : 0), s < ns);
-                more = more || v[r].more;
-            }
-            if (__builtin_expect(__any(more), 0)) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int s = wave + 4 * r;
-                    more_images(la, atoms + (s < ns ? s : 0), s < ns, v[r].g, v[r].gd);
-                }
-            }
-            const bool xy = lane < kMI + kMJ;
-            const int zq = lane - kMI - kMJ;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int s = wave + 4 * r;
-                if (s < ngroup * kAdjGroup) {  // padding atoms give zero columns
-                    const int g = s / kAdjGroup, st = s - g * kAdjGroup;
-                    float *pg = xy ? &gxy[s][lane] : &gzt[g][st][zq];
-                    float *pd = xy ? &gdxy[s][lane] : &gzt[g][kAdjGroup + st][zq];
-                    *pg = v[r].g;
-                    *pd = v[r].gd;
-                }
-            }
-        }
+        const int ngroup = (nb + kAdjGroup - 1) / kAdjGroup;
+        adjoint_factors<WIDE>(buf[0], recs, la, 0, nb, wave, lane);
         __syncthreads();
-        for (int g = 0; g < ngroup; ++g) {
-            // lane holds S[row][n] for 16 rows of each of its two tiles: row
-            // r of tile u is local i = 4 wave + 2 u + r / 8 and
-            // j = 8 ((r / 4) % 2) + 4 half + r % 4, so the eight j values (and
-            // their gy, gdy) are the same for both tiles and both halves r / 8
-            const int s = g * kAdjGroup + sl;
-            float yv[8], dyv[8];
-#pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const int j = mfma_row(r, lane) & 15;
-                yv[r] = gxy[s][kMI + j];
-                dyv[r] = gdxy[s][kMI + j];
-            }
-            float ax = 0.0f, ay = 0.0f;  // f = 0: (x, y) components; f = 1: z in ax
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                floatx16 acc;
-#pragma unroll
-                for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-#pragma unroll
-                for (int m = 0; m < 16; ++m)
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(u == 0 ? g0[m] : g1[m], gzt[g][n][16 * half + m], acc,
-                                                               0, 0, 0);
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int i = 4 * wave + 2 * u + h;
-                    float sy = 0.0f, sdy = 0.0f;
-#pragma unroll
-                    for (int r = 0; r < 8; ++r) {
-                        sy += yv[r] * acc[8 * h + r];
-                        sdy += dyv[r] * acc[8 * h + r];
-                    }
-                    if (f == 0) {
-                        ax += gdxy[s][i] * sy;
-                        ay += gxy[s][i] * sdy;
-                    } else {
-                        ax += gxy[s][i] * sy;
-                    }
-                }
-            }
-            red[wave][half][n][g][0] = ax;
-            red[wave][half][n][g][1] = ay;
+        for (int gi = 0; gi < ngroup; ++gi) {
+            if (gi > 0) adjoint_reduce(a, red[(gi - 1) & 1], off + blk, (gi - 1) * kAdjGroup, nb, t);
+            if (gi + 1 < ngroup)
+                adjoint_factors<WIDE>(buf[(gi + 1) & 1], recs, la, (gi + 1) * kAdjGroup, nb, wave, lane);
+            adjoint_group(buf[gi & 1], g0, g1, wave, lane, red[gi & 1][wave][half]);
+            __syncthreads();
         }
-        __syncthreads();
-        // fixed-order sum over the 4 waves and 2 lane halves, in double
-        for (int e = t; e < ns * 3; e += kMThreads) {
-            const int s2 = e / 3, x = e - s2 * 3;
-            const int g = s2 / kAdjGroup, st = s2 - g * kAdjGroup;
-            const int nn = x == 2 ? kAdjGroup + st : st;
-            const int comp = x == 1 ? 1 : 0;
-            double v = 0.0;
-            for (int w = 0; w < 4; ++w) v += double(red[w][0][nn][g][comp]) + double(red[w][1][nn][g][comp]);
-            const int64_t slot = off + c0 + s2;
-            if (slot < a.capacity) a.bpart[slot * 3 + x] = v;
-        }
-        __syncthreads();
+        adjoint_reduce(a, red[(ngroup - 1) & 1], off + blk, (ngroup - 1) * kAdjGroup, nb, t);
+        __syncthreads();  // recs, buf and red are reused by the next block
     }
 }
 
 hipError_t run_gather_mfma(const SplatArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_splat_mfma, dim3(int(a.nbricks_total)), dim3(kMThreads), 0, s, a);
+    const dim3 grid(int(a.nbricks_total)), block(kMThreads);
+    if (a.wide)
+        hipLaunchKernelGGL(k_splat_mfma<true>, grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL(k_splat_mfma<false>, grid, block, 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t run_adjoint_mfma(const SplatArgs &a, hipStream_t s)
 {
-    if (a.grad_rows_vec4)
-        hipLaunchKernelGGL(k_adjoint_mfma<true>, dim3(int(a.nbricks_total)), dim3(kMThreads), 0, s, a);
+    const dim3 grid(int(a.nbricks_total)), block(kMThreads);
+    if (a.grad_rows_vec4 && !a.wide)
+        hipLaunchKernelGGL((k_adjoint_mfma<true, false>), grid, block, 0, s, a);
+    else if (a.grad_rows_vec4)
+        hipLaunchKernelGGL((k_adjoint_mfma<true, true>), grid, block, 0, s, a);
+    else if (!a.wide)
+        hipLaunchKernelGGL((k_adjoint_mfma<false, false>), grid, block, 0, s, a);
     else
-        hipLaunchKernelGGL(k_adjoint_mfma<false>, dim3(int(a.nbricks_total)), dim3(kMThreads), 0, s, a);
+        hipLaunchKernelGGL((k_adjoint_mfma<false, true>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 
