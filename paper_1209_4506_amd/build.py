@@ -38,9 +38,15 @@ def _hipcc() -> str:
     return "hipcc"
 
 
+# per-source extra flags: the matrix-core kernels keep their accumulators in
+# ordinary vector registers (no copies out of the accumulation registers
+# before the vector code that folds the products)
+EXTRA_FLAGS = {"splat_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc(), *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [_hipcc(), *HIPCC_FLAGS, *EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed on %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr[-20000:]))

@@ -584,6 +584,14 @@ SplatArgs splat_args(hartree_plan p, int32_t natoms, const double *pos, const do
     a.rec = (p->fp64 || p->general) ? nullptr : reinterpret_cast<SlotAtom *>(p->ws + p->o_rec);
     a.general = p->general ? 1 : 0;
     a.wide = p->wide ? 1 : 0;
+    // a prime stride that does not divide natoms permutes the atoms
+    a.visit_stride = 1;
+    for (int32_t pr : {1009, 1013, 1019}) {
+        if (natoms % pr != 0) {
+            a.visit_stride = pr;
+            break;
+        }
+    }
     a.zeros = reinterpret_cast<const float *>(p->ws + p->o_zero);
     a.cap_pa = p->cap_pa;
     a.tab = p->ws + p->o_tab;
@@ -686,6 +694,13 @@ hartree_status hartree_bind_workspace(hartree_plan plan, void *workspace, size_t
     const unsigned char zero[256] = {};
     e = hipMemcpy(ws + plan->o_zero, zero, sizeof(zero), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "clearing the zero block");
+    if (plan->splat_ok) {
+        // binning keeps its brick counters cleared from one call to the next
+        e = hipMemset(ws + plan->o_counts, 0, 4 * size_t(plan->nbricks + 1));
+        if (e == hipSuccess) e = hipMemset(ws + plan->o_cursor, 0, 4 * size_t(plan->nbricks + 1));
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "clearing the brick counters");
+    }
     plan->ws = ws;
     return ok();
 }

@@ -13,13 +13,13 @@
 // index, and every sum below runs in a fixed order, so results do not depend
 // on scheduling.
 //
-//   init    zero the brick counters; per atom: wrapped position, weight,
-//           window [lo, hi] per axis; per problem: Q = sum Z (fixed order),
-//           for the background Q / Omega
-//   count   per atom: +1 on each touched brick
-//   scan    exclusive prefix sum of the brick counts
+//   count   per atom: wrapped position, weight, window [lo, hi] per axis;
+//           +1 on each touched brick
+//   scan    per problem: Q = sum Z (fixed order), for the background
+//           Q / Omega; exclusive prefix sum of the brick counts
 //   fill    per atom: write its index into each touched brick's list
-//   sort    per brick: order the list by atom index
+//   sort    per brick: order the list by atom index; clear the brick's
+//           counters for the next binning
 //   gather  per brick: rho = sum over its atoms of w gx(i) gy(j) gz(k) [- Q/Omega]
 //   adjoint per brick: partial sum_r grad_rho(r) g(r) d(r) for each of its atoms
 //   final   per atom: fixed-order sum of its partials over the touched bricks
@@ -27,7 +27,9 @@
 
 namespace hartree {
 
-__device__ __forceinline__ void atom_prep(const SplatArgs &a, int atom)
+// An atom's wrapped position, weight and window per axis; `report` sets
+// the device status bits for an invalid atom (which then touches nothing).
+__device__ __forceinline__ AtomInfo atom_prep(const SplatArgs &a, int atom, bool report)
 {
     const int prob = find_prob_atom(a, atom);
     const ProbDesc &d = a.desc[prob];
@@ -38,10 +40,10 @@ __device__ __forceinline__ void atom_prep(const SplatArgs &a, int atom)
     bool ok = isfinite(s) && s > 0.0 && isfinite(z);
     for (int x = 0; x < 3; ++x) ok = ok && isfinite(a.pos[3 * atom + x]);
     if (ok && s > a.max_sigma) {
-        atomicOr(&a.status->bits, 0x2u);
+        if (report) atomicOr(&a.status->bits, 0x2u);
         ok = false;
     } else if (!ok) {
-        atomicOr(&a.status->bits, 0x1u);
+        if (report) atomicOr(&a.status->bits, 0x1u);
     }
     if (!ok) {
         for (int x = 0; x < 3; ++x) {
@@ -51,8 +53,7 @@ __device__ __forceinline__ void atom_prep(const SplatArgs &a, int atom)
         }
         in.w = 0.0;
         in.inv2s2 = 0.0;
-        a.info[atom] = in;
-        return;
+        return in;
     }
     const double rc = a.cutoff * s;
     if (d.separable) {
@@ -87,7 +88,7 @@ __device__ __forceinline__ void atom_prep(const SplatArgs &a, int atom)
     }
     in.w = z * pow(6.283185307179586476925286766559 * s * s, -1.5);
     in.inv2s2 = 1.0 / (2.0 * s * s);
-    a.info[atom] = in;
+    return in;
 }
 
 // Per-atom 1-D factor tables (see splat_common.hpp): one thread per
@@ -128,31 +129,6 @@ __global__ __launch_bounds__(256) void k_atom_tables(SplatArgs a)
     reinterpret_cast<Cx<T> *>(a.tab)[e] = Cx<T>{g, gd};
 }
 
-// Binning set-up in one launch: zero the brick counts and cursors
-// (grid-stride), prepare one atom per thread, and let block p < nprob sum
-// the charges of problem p in a fixed order (for the background Q / Omega).
-__global__ __launch_bounds__(256) void k_bin_init(SplatArgs a)
-{
-    __shared__ double red[256];
-    const int64_t gid = blockIdx.x * int64_t(blockDim.x) + threadIdx.x, gstride = int64_t(gridDim.x) * blockDim.x;
-    for (int64_t i = gid; i <= a.nbricks_total; i += gstride) {
-        a.counts[i] = 0;
-        a.cursor[i] = 0;
-    }
-    if (gid < a.natoms) atom_prep(a, int(gid));
-    const int p = blockIdx.x;
-    if (p >= a.nprob) return;
-    double s = 0.0;
-    for (int i = a.atom_off[p] + threadIdx.x; i < a.atom_off[p + 1]; i += 256) s += a.Z[i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-        if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) a.qsum[p] = red[0];
-}
-
 // Bricks touched by one atom, enumerated t = 0 .. ntouch-1 in a fixed order:
 // t = (u * ct[1] + v) * ct[2] + w over the circular ranges of the three axes.
 struct Touch {
@@ -190,14 +166,25 @@ __device__ __forceinline__ int touch_index(const Touch &t, const ProbDesc &d, in
     return (u * t.ct[1] + v) * t.ct[2] + w;
 }
 
-// one wavefront per atom, lanes over the bricks it touches
+// one wavefront per atom, lanes over the bricks it touches.  Wavefront w
+// takes atom (w * visit_stride) mod natoms (a stride coprime to natoms), so
+// that atoms adjacent in the input, which touch the same bricks, do not
+// contend for the same counters at the same time.  The count pass also
+// prepares the atom (every lane computes it, lane 0 stores it).
 template <int MODE>  // 0: count, 1: fill
 __global__ __launch_bounds__(256) void k_brick_visit(SplatArgs a)
 {
-    const int atom = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (atom >= a.natoms) return;
-    const AtomInfo in = a.info[atom];
+    if (w >= a.natoms) return;
+    const int atom = int((int64_t(w) * a.visit_stride) % a.natoms);
+    AtomInfo in;
+    if (MODE == 0) {
+        in = atom_prep(a, atom, lane == 0);
+        if (lane == 0) a.info[atom] = in;
+    } else {
+        in = a.info[atom];
+    }
     const ProbDesc &d = a.desc[in.prob];
     const Touch t = atom_touch(in, d);
     const int nt = t.ntouch();
@@ -215,13 +202,28 @@ __global__ __launch_bounds__(256) void k_brick_visit(SplatArgs a)
 
 // exclusive scan of counts[0..n) into offsets[0..n] by one workgroup:
 // thread t owns a contiguous run of entries, sums it, the workgroup scans
-// the run sums, and each thread writes its run (clamped to the capacity)
+// the run sums, and each thread writes its run (clamped to the capacity).
+// The same workgroup first sums each problem's charges Q = sum Z in a
+// fixed order (for the background Q / Omega).
 constexpr int kScanThreads = 1024;
 
 __global__ __launch_bounds__(kScanThreads) void k_scan(SplatArgs a)
 {
     __shared__ int64_t part[kScanThreads];
+    __shared__ double qred[kScanThreads];
     const int t = threadIdx.x;
+    for (int p = 0; p < a.nprob; ++p) {
+        double q = 0.0;
+        for (int i = a.atom_off[p] + t; i < a.atom_off[p + 1]; i += kScanThreads) q += a.Z[i];
+        qred[t] = q;
+        __syncthreads();
+        for (int w = kScanThreads / 2; w >= 1; w >>= 1) {
+            if (t < w) qred[t] += qred[t + w];
+            __syncthreads();
+        }
+        if (t == 0) a.qsum[p] = qred[0];
+        __syncthreads();
+    }
     const int64_t n = a.nbricks_total;
     const int64_t per = (n + kScanThreads - 1) / kScanThreads;
     const int64_t e0 = t * per, e1 = (e0 + per) < n ? (e0 + per) : n;
@@ -263,6 +265,12 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a)
     if (b < a.nbricks_total) {
         off = a.offsets[b];
         cnt = int(a.offsets[b + 1] - off);
+        // the next binning starts from zero counters (their last readers,
+        // the scan and the fill, have finished)
+        if (lane == 0) {
+            a.counts[b] = 0;
+            a.cursor[b] = 0;
+        }
     }
     const bool in_lds = cnt <= kSortLds;
     if (in_lds)
@@ -495,20 +503,19 @@ __global__ __launch_bounds__(256) void k_adjoint_final(SplatArgs a)
 
 // ------------------------------------------------------------- host side
 
+// The brick counters and cursors are zero on entry: the workspace binding
+// clears them and every binning's sort pass leaves them cleared.
 hipError_t run_bin(const SplatArgs &a, hipStream_t s)
 {
     const int64_t nbt = a.nbricks_total;
-    int init_blocks = int((a.natoms + 255) / 256);
-    if (init_blocks < a.nprob) init_blocks = a.nprob;
-    if (init_blocks < 64) init_blocks = 64;  // enough threads for the brick fill
-    hipLaunchKernelGGL(k_bin_init, dim3(init_blocks), dim3(256), 0, s, a);
     const int nw = int((a.natoms + 3) / 4);  // one wavefront per atom
     if (a.natoms > 0) {
         // FP64 kernels read per-atom factor tables; the FP32 matrix-core
         // kernels evaluate the factors themselves
         const int nt = int((int64_t(a.natoms) * 3 * a.wcap + 255) / 256);
-        if (a.fp64 && !a.general) hipLaunchKernelGGL(k_atom_tables<double>, dim3(nt), dim3(256), 0, s, a);
+        // the count pass prepares the atoms (AtomInfo): it runs first
         hipLaunchKernelGGL(k_brick_visit<0>, dim3(nw), dim3(256), 0, s, a);
+        if (a.fp64 && !a.general) hipLaunchKernelGGL(k_atom_tables<double>, dim3(nt), dim3(256), 0, s, a);
     }
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, a);
     if (a.natoms > 0) hipLaunchKernelGGL(k_brick_visit<1>, dim3(nw), dim3(256), 0, s, a);

@@ -425,8 +425,31 @@ __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
     // flight until the matrix products.  VEC: every problem's rows hold a
     // multiple of 4 points from a 16-byte aligned start.
     float g0[16], g1[16];
-    {
-        const float *src = reinterpret_cast<const float *>(a.grad_rho) + d.grid_off;
+    const float *src = reinterpret_cast<const float *>(a.grad_rho) + d.grid_off;
+    const bool interior =
+        (p.b0 + 1) * kMI <= d.dims[0] && (p.b1 + 1) * kMJ <= d.dims[1] && (p.b2 + 1) * kMK <= d.dims[2];
+    if (VEC && interior) {
+        // a brick inside the grid: a wavefront-uniform base plus a 32-bit
+        // lane offset, every load in range
+        const int w = __builtin_amdgcn_readfirstlane(wave);
+        const int64_t sb = d.dims[2], sa = int64_t(d.dims[1]) * d.dims[2];
+        const float *base = src + (int64_t(p.b0 * kMI + 4 * w) * d.dims[1] + p.b1 * kMJ) * sb + p.b2 * kMK;
+        const uint32_t loff = uint32_t(((col >> 4) * d.dims[1] + (col & 15)) * d.dims[2] + 16 * half);
+        const float4 *r0 = reinterpret_cast<const float4 *>(base + loff);
+        const float4 *r1 = reinterpret_cast<const float4 *>(base + 2 * sa + loff);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 v0 = r0[q], v1 = r1[q];
+            g0[4 * q] = v0.x;
+            g0[4 * q + 1] = v0.y;
+            g0[4 * q + 2] = v0.z;
+            g0[4 * q + 3] = v0.w;
+            g1[4 * q] = v1.x;
+            g1[4 * q + 1] = v1.y;
+            g1[4 * q + 2] = v1.z;
+            g1[4 * q + 3] = v1.w;
+        }
+    } else {
         const int j = p.b1 * kMJ + (col & 15);
         const int ia = p.b0 * kMI + 4 * wave + (col >> 4);
         const int k0 = p.b2 * kMK + 16 * half;

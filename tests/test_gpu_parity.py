@@ -228,6 +228,51 @@ def test_atom_order_equivariance(H, prec, mode):
     assert ef <= (1e-11 if prec == "fp64" else 1e-5)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("fill", [0x00, 0xFF])
+def test_workspace_contents_do_not_matter(H, oracle_mod, prec, fill):
+    """A workspace handed over full of arbitrary bytes gives the same bits as
+    any other: every kernel writes what it reads (the binding clears the
+    parts that must start at zero).  Regression: the per-atom table pass
+    once ran before the pass that prepares the atoms."""
+    say("case workspace filled with 0x%02x" % fill, prec)
+    outs = []
+    for case in ("ragged", "tight_images"):
+        p = SPLAT_CASES[case]()
+        plan = H.Plan(p.cell, p.dims, precision=prec, max_atoms=p.natoms, bind=False)
+        need = plan.workspace_size()
+        raw = torch.full((need + 256,), fill, dtype=torch.uint8, device="cuda")
+        shift = (-raw.data_ptr()) % 256
+        plan.bind(raw[shift:shift + need])
+        pos, Z, sig = _atoms(p)
+        g = to_dev(inputs.random_grid(p.dims, 31), plan.dtype)
+        rho = plan.splat(pos, Z, sig)
+        V, E = plan.solve(rho)
+        f = plan.splat_adjoint(pos, Z, sig, g)
+        torch.cuda.synchronize()
+        assert plan.device_status() == 0
+        outs.append([rho.cpu(), V.cpu(), E.cpu(), f.cpu()])
+        ref = oracle_splat_cache(oracle_mod, p)
+        assert np.abs(rho.double().cpu().numpy() - ref).max() / np.abs(ref).max() <= (1e-12 if prec == "fp64" else 2e-6)
+    key = (prec,)
+    if key in _WS_REF:
+        for a, b in zip(sum(_WS_REF[key], []), sum(outs, [])):
+            assert torch.equal(a, b)
+    else:
+        _WS_REF[key] = outs
+
+
+_WS_REF = {}
+_SPLAT_REF = {}
+
+
+def oracle_splat_cache(oracle_mod, p):
+    key = (p.name, p.seed, p.dims)
+    if key not in _SPLAT_REF:
+        _SPLAT_REF[key] = oracle_mod.splat(p.cell.reshape(9), p.dims, p.pos, p.Z, p.sigma)
+    return _SPLAT_REF[key]
+
+
 def test_rejects_arguments(H):
     say("case argument errors")
     with pytest.raises(H.HartreeError) as ei:
