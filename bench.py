@@ -29,6 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PEAK_MFMA_F32_TFLOPS = 157.3  # MI355X dense FP32 matrix-core peak
+BRICK_POINTS_F32 = 16 * 16 * 32  # points of one FP32 splat brick
 METRIC = "Hartree solves/sec & HBM GB/s, 360^3 FP32 fwd+bwd vs FP64 plain"
 
 
@@ -185,6 +187,34 @@ def kernel_bytes(name, prob, s):
     }.get(name)
 
 
+def kernel_flops(name, pairs):
+    """Algorithmic matrix-core flops of one launch of the splat or adjoint:
+    per (atom, brick) pair one multiply-add per brick point (splat: the
+    density; adjoint: two, the factor and its displacement-weighted form)."""
+    per = {"splat": 2, "adjoint": 4}.get(name)
+    return None if per is None else per * BRICK_POINTS_F32 * pairs
+
+
+def roofline_of(name, prob, s, pairs, avg_ms, precision="fp32"):
+    """Roofline entry of one kernel group from its average launch time: the
+    matrix-core kernels (splat, adjoint) against the FP32 MFMA peak, the
+    grid passes against HBM."""
+    fl = kernel_flops(name, pairs)
+    by = kernel_bytes(name, prob, s)
+    if fl is not None:
+        ach = fl / (avg_ms * 1e-3) / 1e12
+        return {"bound": "mfma", "kernel": name, "achieved": ach, "peak": PEAK_MFMA_F32_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_MFMA_F32_TFLOPS, "traffic": traffic_for(name, precision),
+                "flops_per_launch": fl, "atom_brick_pairs": pairs, "bytes_per_launch": by,
+                "hbm_gbs": by / (avg_ms * 1e-3) / 1e9, "avg_launch_us": 1000.0 * avg_ms}
+    if by is None:
+        return None
+    ach = by / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": name, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": ach / PEAK_HBM_GBS, "traffic": traffic_for(name, precision), "bytes_per_launch": by,
+            "avg_launch_us": 1000.0 * avg_ms}
+
+
 def traffic_for(kernel, precision):
     """Counter-measured HBM bytes per launch, if taken on the current sources."""
     f = os.path.join(ROOT, "profiles", "traffic_diamond360.json")
@@ -268,10 +298,10 @@ def main():
     model_bytes = 23 * s * n
     # dominant kernel group by time
     groups = {k: v for k, v in prof.items()}
-    dom = max((k for k in groups if kernel_bytes(k, prob, s)), key=lambda k: groups[k][0])
-    dom_ms = groups[dom][0] / groups[dom][1]
-    dom_bytes = kernel_bytes(dom, prob, s)
-    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    pairs = step.plan.atoms_pairs()
+    rooflines = {k: roofline_of(k, prob, s, pairs, v[0] / v[1]) for k, v in groups.items()}
+    rooflines = {k: v for k, v in rooflines.items() if v is not None}
+    dom = max(rooflines, key=lambda k: groups[k][0])
     per_kernel = {k: {"avg_us": round(1000.0 * v[0] / v[1], 2), "launches": v[1],
                       "share": round(v[0] / sum(x[0] for x in groups.values()), 4)} for k, v in groups.items()}
     out = {
@@ -293,9 +323,9 @@ def main():
                                "+ adjoint per step",
                    "grid": list(prob.dims), "atoms": prob.natoms, "precision": "fp32"},
         "hbm_gbs_model": model_bytes / (ms * 1e-3) / 1e9,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_for(dom, "fp32"),
-                     "bytes_per_launch": dom_bytes, "avg_launch_us": 1000.0 * dom_ms},
+        "roofline": rooflines[dom],
+        "kernel_rooflines": {k: {"bound": v["bound"], "achieved": round(v["achieved"], 2), "unit": v["unit"],
+                                 "frac": round(v["frac"], 4)} for k, v in rooflines.items()},
         "kernels": per_kernel,
         "pass_config": step.config.reshape(-1).tolist(),
         "source_hash": source_hash(),

@@ -195,7 +195,8 @@ hartree_status hartree_profile_end(hartree_plan plan, double *total_ms, int64_t 
 
 /* Atom binning shared by a splat and its adjoint.  hartree_splat and
  * hartree_splat_adjoint each bin their atoms into bricks of the grid (sorted
- * per-brick lists and per-atom 1-D factor tables in the workspace) before
+ * per-brick lists with per-slot atom records (FP32) or per-atom 1-D factor
+ * tables (FP64) in the workspace) before
  * their main kernels.  When both run on the same atoms -- a forward splat and
  * the backward pass of the same positions -- the binning can be done once:
  *   hartree_atoms_bind  bins the atoms (same arguments as hartree_splat) and
@@ -211,6 +212,13 @@ hartree_status hartree_splat_bound(hartree_plan plan, uint64_t token, void *rho_
                                    void *stream);
 hartree_status hartree_splat_adjoint_bound(hartree_plan plan, uint64_t token, const void *grad_rho, double *grad_pos,
                                            void *stream);
+
+/* Size of the last binding (by hartree_atoms_bind, hartree_splat or
+ * hartree_splat_adjoint): the number of (atom, brick) pairs in the per-brick
+ * lists, i.e. the work of the splat and adjoint kernels.  Read synchronously
+ * from the workspace after the work on `stream`; HARTREE_ERR_ARG during a
+ * graph capture or for a NULL pointer. */
+hartree_status hartree_atoms_pairs(hartree_plan plan, int64_t *pairs, void *stream);
 
 /* Read (synchronously) and clear the device status word (HARTREE_DEV_* bits).
  * Refused (HARTREE_ERR_ARG) while a graph capture is open on the plan. */

@@ -872,6 +872,26 @@ hartree_status hartree_splat_adjoint(hartree_plan plan, int32_t natoms, const do
     return hartree_splat_adjoint_bound(plan, token, grad_rho, grad_pos, stream);
 }
 
+hartree_status hartree_atoms_pairs(hartree_plan plan, int64_t *pairs, void *stream)
+{
+    hartree_status st = check_ws(plan);
+    if (st != HARTREE_OK) return st;
+    if (plan->capturing) return fail(HARTREE_ERR_ARG, "the binding size cannot be read during graph capture");
+    if (!pairs) return fail(HARTREE_ERR_ARG, "pairs is NULL");
+    if (!plan->splat_ok) {
+        *pairs = 0;
+        return ok();
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int32_t v = 0;
+    hipError_t e = hipMemcpyAsync(&v, plan->ws + plan->o_offsets + 4 * size_t(plan->nbricks), 4,
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "reading the binding size");
+    *pairs = v;
+    return ok();
+}
+
 hartree_status hartree_device_status(hartree_plan plan, uint32_t *bits, void *stream)
 {
     hartree_status st = check_ws(plan);

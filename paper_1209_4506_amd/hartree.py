@@ -77,6 +77,7 @@ def _load():
         "hartree_plan_set_config": [vp, P(i32)],
         "hartree_plan_tune": [vp, vp, i32, vp],
         "hartree_atom_partition": [i32, P(d), P(d), i32, P(i32), P(i32), P(i32)],
+        "hartree_atoms_pairs": [vp, P(i64), vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -98,7 +99,7 @@ EXPORTED = ["hartree_plan_create", "hartree_plan_create_batched", "hartree_plan_
             "hartree_device_status", "hartree_atoms_bind", "hartree_splat_bound", "hartree_splat_adjoint_bound",
             "hartree_profile_begin", "hartree_profile_end", "hartree_graph_begin", "hartree_graph_end",
             "hartree_graph_launch", "hartree_plan_get_config", "hartree_plan_set_config", "hartree_plan_tune",
-            "hartree_atom_partition", "hartree_last_error"]
+            "hartree_atom_partition", "hartree_atoms_pairs", "hartree_last_error"]
 
 # hartree_kernel_id order
 KERNELS = ["r2c", "r2c_bwd", "fft_b", "fft_a", "fft_a_bwd", "fft_a_eonly", "fft_b_inv", "c2r", "finalize",
@@ -308,6 +309,12 @@ class Plan:
                                       stream or _stream(self.device)))
         self._bound = (pos, Z, sigma, n)  # keep the converted arrays alive
         return int(token.value)
+
+    def atoms_pairs(self, stream=None) -> int:
+        """(atom, brick) pairs of the last binding (synchronous)."""
+        n = ctypes.c_int64()
+        _check(LIB.hartree_atoms_pairs(self._h, ctypes.byref(n), stream or _stream(self.device)))
+        return int(n.value)
 
     def splat_bound(self, token, out=None, subtract_background=True, stream=None):
         out = self.empty_grid() if out is None else self._grid(out, "out")

@@ -273,6 +273,35 @@ def oracle_splat_cache(oracle_mod, p):
     return _SPLAT_REF[key]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ["cubic32", "ragged", "tight_images"])
+def test_binding_pairs(H, prec, case):
+    """hartree_atoms_pairs equals the number of (atom, brick) pairs that the
+    truncation windows define: per axis the bricks holding a grid index of
+    [ceil((X - rc) / h), floor((X + rc) / h)] taken modulo the axis length
+    (bricks of 16 x 16 x 32 points in FP32, 8 x 8 x 32 in FP64)."""
+    say("case binding pairs", prec, case)
+    p = SPLAT_CASES[case]()
+    plan = H.Plan(p.cell, p.dims, precision=prec, max_atoms=p.natoms)
+    pos, Z, sig = _atoms(p)
+    plan.bind_atoms(pos, Z, sig)
+    got = plan.atoms_pairs()
+    bsz = (16, 16, 32) if prec == "fp32" else (8, 8, 32)
+    rc_sig = 6.0 if prec == "fp32" else 8.0
+    L = np.diag(p.cell)
+    want = 0
+    for i in range(p.natoms):
+        cnt = 1
+        for x in range(3):
+            n, h = p.dims[x], L[x] / p.dims[x]
+            X = p.pos[i, x] % L[x]
+            rc = rc_sig * p.sigma[i]
+            lo, hi = int(np.ceil((X - rc) / h)), int(np.floor((X + rc) / h))
+            cnt *= len({(g % n) // bsz[x] for g in range(lo, hi + 1)})
+        want += cnt
+    assert got == want
+
+
 def test_rejects_arguments(H):
     say("case argument errors")
     with pytest.raises(H.HartreeError) as ei:
