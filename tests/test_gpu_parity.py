@@ -302,6 +302,73 @@ def test_binding_pairs(H, prec, case):
     assert got == want
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_zero_atoms(H, prec):
+    """No atoms: the density is zero (no charge, no background), the binding
+    is empty, and the adjoint has nothing to write."""
+    say("case zero atoms", prec)
+    plan = H.Plan(np.eye(3) * 9.0, (24, 30, 36), precision=prec, max_atoms=4)
+    e = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+    z = torch.zeros(0, dtype=torch.float64, device="cuda")
+    rho = plan.splat(e, z, z)
+    assert plan.atoms_pairs() == 0
+    assert torch.count_nonzero(rho).item() == 0
+    f = plan.splat_adjoint(e, z, z, torch.ones_like(rho))
+    assert f.shape == (0, 3)
+    V, E = plan.solve(rho)
+    assert torch.count_nonzero(V).item() == 0 and float(E[0]) == 0.0
+    assert plan.device_status() == 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ["ragged", "triclinic", "tight_images"])
+def test_periodic_images_of_atoms(H, prec, case):
+    """Atoms given anywhere in space (shifted by whole cell vectors, also
+    negative) give the density and forces of their images in the cell."""
+    say("case periodic images", prec, case)
+    p = SPLAT_CASES[case]()
+    plan = H.Plan(p.cell, p.dims, precision=prec, max_atoms=p.natoms)
+    rng = np.random.default_rng(19)
+    shifts = rng.integers(-3, 4, size=(p.natoms, 3)) @ p.cell
+    g = to_dev(inputs.random_grid(p.dims, 29), plan.dtype)
+    res = []
+    for pos_np in (p.pos, p.pos + shifts):
+        pos = torch.tensor(pos_np, device="cuda")
+        Z = torch.tensor(p.Z, device="cuda")
+        sig = torch.tensor(p.sigma, device="cuda")
+        res.append((plan.splat(pos, Z, sig).double().cpu().numpy(), plan.splat_adjoint(pos, Z, sig, g).cpu().numpy()))
+    assert plan.device_status() == 0
+    (r0, f0), (r1, f1) = res
+    er = np.abs(r1 - r0).max() / np.abs(r0).max()
+    ef = np.abs(f1 - f0).max() / np.abs(f0).max()
+    say("  rho max-rel %.3e  grad max-rel %.3e" % (er, ef))
+    assert er <= (1e-12 if prec == "fp64" else 2e-6)
+    assert ef <= (1e-10 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_invalid_atoms_reported(H, prec):
+    """A non-finite position or a width <= 0 sets HARTREE_DEV_BAD_ATOM; such
+    an atom touches no grid point and gets a zero force."""
+    say("case invalid atoms", prec)
+    p = inputs.cubic32()
+    plan = H.Plan(p.cell, p.dims, precision=prec, max_atoms=p.natoms)
+    for bad in ("pos", "sigma"):
+        pos = torch.tensor(p.pos, device="cuda")
+        Z = torch.tensor(p.Z, device="cuda")
+        sig = torch.tensor(p.sigma, device="cuda")
+        if bad == "pos":
+            pos[3, 1] = float("nan")
+        else:
+            sig[3] = 0.0
+        rho = plan.splat(pos, Z, sig)
+        assert plan.device_status() & H.DEV_BAD_ATOM
+        f = plan.splat_adjoint(pos, Z, sig, torch.ones_like(rho))
+        assert plan.device_status() & H.DEV_BAD_ATOM
+        assert torch.count_nonzero(f[3]).item() == 0
+        assert torch.isfinite(f).all()
+
+
 def test_rejects_arguments(H):
     say("case argument errors")
     with pytest.raises(H.HartreeError) as ei:
