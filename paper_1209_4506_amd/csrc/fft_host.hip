@@ -14,19 +14,36 @@ hipError_t run_a_f64(int, int, int, hipStream_t, const PassArgs &);
 
 // ---------------------------------------------------------------- E_H
 // one workgroup per problem: fixed-order sum of that problem's partials
-__global__ __launch_bounds__(256) void k_finalize(const ProbDesc *desc, const double *partials, double *e_h)
+// one workgroup per problem: each thread sums its strided share of the
+// partials in four independent chains (the loads issue together), then a
+// fixed butterfly per wavefront and a fixed-order sum over the wavefronts
+constexpr int kFinThreads = 1024;
+
+__global__ __launch_bounds__(kFinThreads) void k_finalize(const ProbDesc *desc, const double *partials, double *e_h)
 {
-    __shared__ double red[256];
+    __shared__ double red[kFinThreads / 64];
     const ProbDesc &d = desc[blockIdx.x];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < d.nparts; i += 256) s += partials[d.part_off + i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-        if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
+    const double *pp = partials + d.part_off;
+    const int t = threadIdx.x;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int i = t;
+    for (; i + 3 * kFinThreads < d.nparts; i += 4 * kFinThreads) {
+        s0 += pp[i];
+        s1 += pp[i + kFinThreads];
+        s2 += pp[i + 2 * kFinThreads];
+        s3 += pp[i + 3 * kFinThreads];
     }
-    if (threadIdx.x == 0) e_h[blockIdx.x] = d.eh_scale * red[0];
+    for (; i < d.nparts; i += kFinThreads) s0 += pp[i];
+    double s = (s0 + s1) + (s2 + s3);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((t & 63) == 0) red[t >> 6] = s;
+    __syncthreads();
+    if (t == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < kFinThreads / 64; ++w) tot += red[w];
+        e_h[blockIdx.x] = d.eh_scale * tot;
+    }
 }
 
 // Pencils per workgroup for a length and its stage radices (log2; -1 if the
@@ -188,7 +205,7 @@ hipError_t run_zero(void *p, size_t bytes, hipStream_t s)
 
 hipError_t run_finalize(const ProbDesc *desc, const double *partials, double *e_h, int nprob, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(nprob), dim3(256), 0, s, desc, partials, e_h);
+    hipLaunchKernelGGL(k_finalize, dim3(nprob), dim3(kFinThreads), 0, s, desc, partials, e_h);
     return hipGetLastError();
 }
 

@@ -209,19 +209,22 @@ constexpr int kScanThreads = 1024;
 
 __global__ __launch_bounds__(kScanThreads) void k_scan(SplatArgs a)
 {
-    __shared__ int64_t part[kScanThreads];
-    __shared__ double qred[kScanThreads];
-    const int t = threadIdx.x;
+    constexpr int NW = kScanThreads / 64;
+    __shared__ int64_t wtot[NW];
+    __shared__ double qw[NW];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     for (int p = 0; p < a.nprob; ++p) {
         double q = 0.0;
         for (int i = a.atom_off[p] + t; i < a.atom_off[p + 1]; i += kScanThreads) q += a.Z[i];
-        qred[t] = q;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) q += __shfl_xor(q, off, 64);
+        if (lane == 0) qw[w] = q;
         __syncthreads();
-        for (int w = kScanThreads / 2; w >= 1; w >>= 1) {
-            if (t < w) qred[t] += qred[t + w];
-            __syncthreads();
+        if (t == 0) {
+            double tot = 0.0;
+            for (int k = 0; k < NW; ++k) tot += qw[k];
+            a.qsum[p] = tot;
         }
-        if (t == 0) a.qsum[p] = qred[0];
         __syncthreads();
     }
     const int64_t n = a.nbricks_total;
@@ -229,21 +232,24 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(SplatArgs a)
     const int64_t e0 = t * per, e1 = (e0 + per) < n ? (e0 + per) : n;
     int64_t s = 0;
     for (int64_t e = e0; e < e1; ++e) s += a.counts[e];
-    part[t] = s;
-    __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-        const int64_t v = t >= off ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
+    // inclusive scan of the run sums within the wavefront, then across them
+    int64_t x = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
     }
-    int64_t run = part[t] - s;
+    if (lane == 63) wtot[w] = x;
+    __syncthreads();
+    int64_t before = 0;
+    for (int k = 0; k < w; ++k) before += wtot[k];
+    int64_t run = before + x - s;
     for (int64_t e = e0; e < e1; ++e) {
         a.offsets[e] = int32_t(run < a.capacity ? run : a.capacity);
         run += a.counts[e];
     }
     if (t == kScanThreads - 1) {
-        const int64_t total = part[t];
+        const int64_t total = before + x;
         a.offsets[n] = int32_t(total < a.capacity ? total : a.capacity);
         if (total > a.capacity) atomicOr(&a.status->bits, 0x4u);
     }
