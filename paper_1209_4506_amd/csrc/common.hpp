@@ -110,9 +110,10 @@ struct SlotAxis {
 
 struct SlotAtom {
     SlotAxis ax[3];
-    float c2;  // log2(e) / (2 sigma^2): the 1-D factor is 2^(-d^2 c2)
-    float w;   // Z (2 pi sigma^2)^(-3/2)
-    int32_t pad[2];
+    float c2;       // log2(e) / (2 sigma^2): the 1-D factor is 2^(-d^2 c2)
+    float w;        // Z (2 pi sigma^2)^(-3/2)
+    int32_t atom;   // the atom's index ...
+    int32_t touch;  // ... and this brick's place in its enumeration of touched bricks
 };
 
 struct DeviceStatus {

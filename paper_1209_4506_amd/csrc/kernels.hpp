@@ -72,7 +72,8 @@ struct SplatArgs {
     int32_t *list_sorted;   // capacity
     int32_t *slot_of;       // max_atoms x cap_pa: sorted-list slot of each (atom, touched brick)
     SlotAtom *rec;          // capacity (FP32 plans): the sorted lists' atoms relative to their brick
-    double *bpart;          // capacity x 3 (adjoint partials)
+    double *bpart;          // capacity x 3 (adjoint partials): per list slot, or per (atom, touched brick)
+                            // (atom * cap_pa + touch) where the per-slot records exist (rec != nullptr)
     int64_t capacity;
     int32_t cap_pa;         // most bricks one atom can touch
     int64_t nbricks_total;

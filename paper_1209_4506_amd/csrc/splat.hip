@@ -297,7 +297,10 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a)
         a.list_sorted[off + rank] = v;
         const AtomInfo in = a.info[v];
         const Touch t = atom_touch(in, d);
-        a.slot_of[int64_t(v) * a.cap_pa + touch_index(t, d, b - d.brick_off)] = int32_t(off + rank);
+        const int ti = touch_index(t, d, b - d.brick_off);
+        // with records, the adjoint writes its partials under (atom, touch)
+        // directly; otherwise the slot map leads the reduction to them
+        if (!a.rec) a.slot_of[int64_t(v) * a.cap_pa + ti] = int32_t(off + rank);
         if (a.rec) {
             // the atom relative to this brick, for the FP32 splat kernels
             const int64_t lb = b - d.brick_off;
@@ -315,7 +318,8 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a)
             }
             r.c2 = float(1.4426950408889634073599246810019 * in.inv2s2);
             r.w = float(in.w);
-            r.pad[0] = r.pad[1] = 0;
+            r.atom = v;
+            r.touch = ti;
             a.rec[off + rank] = r;
         }
     }
@@ -484,13 +488,23 @@ __global__ __launch_bounds__(256) void k_adjoint_final(SplatArgs a)
     const Touch t = atom_touch(in, d);
     const int nt = t.ntouch();
     double f0 = 0.0, f1 = 0.0, f2 = 0.0;
-    const int32_t *slots = a.slot_of + int64_t(atom) * a.cap_pa;
-    for (int i = lane; i < nt; i += 64) {
-        const int64_t s = slots[i];
-        if (s >= 0 && s < a.capacity) {
-            f0 += a.bpart[s * 3 + 0];
-            f1 += a.bpart[s * 3 + 1];
-            f2 += a.bpart[s * 3 + 2];
+    if (a.rec) {
+        // partials stored per (atom, touched brick): one contiguous row
+        const double *row = a.bpart + int64_t(atom) * a.cap_pa * 3;
+        for (int i = lane; i < nt; i += 64) {
+            f0 += row[i * 3 + 0];
+            f1 += row[i * 3 + 1];
+            f2 += row[i * 3 + 2];
+        }
+    } else {
+        const int32_t *slots = a.slot_of + int64_t(atom) * a.cap_pa;
+        for (int i = lane; i < nt; i += 64) {
+            const int64_t s = slots[i];
+            if (s >= 0 && s < a.capacity) {
+                f0 += a.bpart[s * 3 + 0];
+                f1 += a.bpart[s * 3 + 1];
+                f2 += a.bpart[s * 3 + 2];
+            }
         }
     }
 #pragma unroll

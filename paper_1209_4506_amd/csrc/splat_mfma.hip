@@ -370,9 +370,10 @@ __device__ __forceinline__ void adjoint_group(const AdjBuf &buf, const float (&g
 }
 
 // fixed-order sum over the 4 waves and 2 lane halves, in double, of the
-// partials of atoms s0 .. s0 + kAdjGroup - 1 (below nb): threads t < 48
-__device__ __forceinline__ void adjoint_reduce(const SplatArgs &a, const float (*red)[2][2 * kAdjGroup][2], int64_t slot0,
-                                               int s0, int nb, int t)
+// partials of staged atoms s0 .. s0 + kAdjGroup - 1 (below nb), stored
+// under (atom, touched brick) from their records: threads t < 48
+__device__ __forceinline__ void adjoint_reduce(const SplatArgs &a, const float (*red)[2][2 * kAdjGroup][2],
+                                               const StagedG *recs, int s0, int nb, int t)
 {
     if (t < 3 * kAdjGroup) {
         const int st = t / 3, x = t - 3 * st;
@@ -380,8 +381,10 @@ __device__ __forceinline__ void adjoint_reduce(const SplatArgs &a, const float (
         const int comp = x == 1 ? 1 : 0;
         double v = 0.0;
         for (int w = 0; w < 4; ++w) v += double(red[w][0][nn][comp]) + double(red[w][1][nn][comp]);
-        const int64_t slot = slot0 + s0 + st;
-        if (s0 + st < nb && slot < a.capacity) a.bpart[slot * 3 + x] = v;
+        if (s0 + st < nb) {
+            const StagedG &r = recs[s0 + st];
+            a.bpart[(int64_t(r.atom) * a.cap_pa + r.touch) * 3 + x] = v;
+        }
     }
 }
 
@@ -504,13 +507,13 @@ __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
         adjoint_factors<WIDE>(buf[0], recs, la, 0, nb, wave, lane);
         __syncthreads();
         for (int gi = 0; gi < ngroup; ++gi) {
-            if (gi > 0) adjoint_reduce(a, red[(gi - 1) & 1], off + blk, (gi - 1) * kAdjGroup, nb, t);
+            if (gi > 0) adjoint_reduce(a, red[(gi - 1) & 1], recs, (gi - 1) * kAdjGroup, nb, t);
             if (gi + 1 < ngroup)
                 adjoint_factors<WIDE>(buf[(gi + 1) & 1], recs, la, (gi + 1) * kAdjGroup, nb, wave, lane);
             adjoint_group(buf[gi & 1], g0, g1, wave, lane, red[gi & 1][wave][half]);
             __syncthreads();
         }
-        adjoint_reduce(a, red[(ngroup - 1) & 1], off + blk, (ngroup - 1) * kAdjGroup, nb, t);
+        adjoint_reduce(a, red[(ngroup - 1) & 1], recs, (ngroup - 1) * kAdjGroup, nb, t);
         __syncthreads();  // recs, buf and red are reused by the next block
     }
 }
