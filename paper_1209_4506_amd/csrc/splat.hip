@@ -325,6 +325,51 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a)
     }
 }
 
+// Factor entries of the staged atoms 0 .. nc-1 over one brick, from the
+// per-atom tables: kBI entries along a (times the weight W when WEIGHT), kBJ
+// along b and kBK along c, and the displacement-weighted entries too when D.
+// Every thread issues all its table loads before it stores any entry, so the
+// loads are in flight together.
+template <typename T, bool D, bool WEIGHT>
+__device__ __forceinline__ void fill_factors(const SplatArgs &a, const StagedAtom *atoms, int nc, int nb0, int nb1,
+                                             int nb2, int bi, int bj, int bk, T (*gx)[kBI], T (*gdx)[kBI],
+                                             T (*gy)[kBJ], T (*gdy)[kBJ], T (*gz)[kBK], T (*gdz)[kBK], int t)
+{
+    constexpr int E = kBI + kBJ + kBK;
+    constexpr int R = (kChunk * E + kBrickThreads - 1) / kBrickThreads;
+    static_assert(kBI == kBJ, "a and b share one brick edge");
+    Cx<T> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = t + r * kBrickThreads;
+        const bool ok = e < nc * E;
+        const int s = ok ? e / E : 0;
+        const int q = ok ? e - s * E : 0;
+        const int x = q < kBI ? 0 : (q < kBI + kBJ ? 1 : 2);
+        const int qq = q - (x == 0 ? 0 : (x == 1 ? kBI : kBI + kBJ));
+        const int nb = x == 0 ? nb0 : (x == 1 ? nb1 : nb2);
+        const int bx = x == 0 ? bi : (x == 1 ? bj : bk);
+        v[r] = table_factor<T>(a, nb, x == 2 ? kBK : kBI, bx, qq, atoms[s], x, ok);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = t + r * kBrickThreads;
+        if (e < nc * E) {
+            const int s = e / E, q = e - s * E;
+            if (q < kBI) {
+                gx[s][q] = WEIGHT ? v[r].x * T(atoms[s].w) : v[r].x;
+                if (D) gdx[s][q] = v[r].y;
+            } else if (q < kBI + kBJ) {
+                gy[s][q - kBI] = v[r].x;
+                if (D) gdy[s][q - kBI] = v[r].y;
+            } else {
+                gz[s][q - kBI - kBJ] = v[r].x;
+                if (D) gdz[s][q - kBI - kBJ] = v[r].y;
+            }
+        }
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBrickThreads) void k_splat_gather(SplatArgs a, const double *qsum)
 {
@@ -355,19 +400,8 @@ __global__ __launch_bounds__(kBrickThreads) void k_splat_gather(SplatArgs a, con
         // tables: per atom 8 + 8 + 32 entries
         stage_atoms(atoms, a, d, off, c0, nc, t);
         __syncthreads();
-        for (int e = t; e < nc * (kBI + kBJ + kBK); e += kBrickThreads) {
-            const int s = e / (kBI + kBJ + kBK), q = e % (kBI + kBJ + kBK);
-            const StagedAtom &in = atoms[s];
-            if (q < kBI) {
-                gx[s][q] = table_factor<T>(a, nb0, kBI, bi, q, in, 0).x * T(in.w);
-            } else if (q < kBI + kBJ) {
-                const int qq = q - kBI;
-                gy[s][qq] = table_factor<T>(a, nb1, kBJ, bj, qq, in, 1).x;
-            } else {
-                const int qq = q - kBI - kBJ;
-                gz[s][qq] = table_factor<T>(a, nb2, kBK, bk, qq, in, 2).x;
-            }
-        }
+        fill_factors<T, false, true>(a, atoms, nc, nb0, nb1, nb2, bi, bj, bk, gx, nullptr, gy, nullptr, gz, nullptr,
+                                     t);
         __syncthreads();
         for (int s = 0; s < nc; ++s) {
             const T c = gx[s][ci] * gy[s][cj];
@@ -384,22 +418,27 @@ __global__ __launch_bounds__(kBrickThreads) void k_splat_gather(SplatArgs a, con
         if (k0 + r < d.dims[2]) out[k0 + r] = acc[r] - bg;
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_sum_t(T v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
+// Adjoint on the vector units (FP64), per brick of 8 x 8 columns by 32
+// points, as two contractions with no cross-lane reductions:
+//   A  thread = column c (its 32 grad_rho values in registers) for atoms
+//      s = wave, wave + 4, ...:  S0[c][s] = sum_k g[c][k] gz_s(k) and
+//      S1[c][s] = sum_k g[c][k] gdz_s(k) (gz, gdz broadcast from LDS);
+//   B  thread = (atom s, component x):  F_x = sum_i X_i sum_j Y_j S[(i, j)][s]
+//      with (X, Y, S) = (gdx, gy, S0), (gx, gdy, S0), (gx, gy, S1),
+//      written as the atom's partial for this brick.
 template <typename T>
 __global__ __launch_bounds__(kBrickThreads) void k_splat_adjoint(SplatArgs a)
 {
+    constexpr int NC = kBI * kBJ;   // columns per brick
+    constexpr int GP = kBK + 1;     // grad_rho tile pitch
+    constexpr int SP = kChunk + 1;  // S pitch
+    static_assert(NC == 64 && kBrickThreads == 4 * NC, "one column per lane, four wavefronts");
     __shared__ StagedAtom atoms[kChunk];
     __shared__ T gx[kChunk][kBI], gdx[kChunk][kBI], gy[kChunk][kBJ], gdy[kChunk][kBJ];
     __shared__ __align__(16) T gz[kChunk][kBK];
     __shared__ __align__(16) T gdz[kChunk][kBK];
-    __shared__ T red[4][kChunk][3];
+    __shared__ T tile[NC * (GP > SP ? GP : SP)];  // the grad_rho tile, then S0
+    __shared__ T s1t[NC * SP];
     const int64_t b = blockIdx.x;
     const int prob = brick_prob(a, b);
     const ProbDesc &d = a.desc[prob];
@@ -410,67 +449,63 @@ __global__ __launch_bounds__(kBrickThreads) void k_splat_adjoint(SplatArgs a)
     const int bi = bij / d.nbricks[1];
     const int nb0 = d.nbricks[0], nb1 = d.nbricks[1], nb2 = d.nbricks[2];
     const int t = threadIdx.x;
-    const int ci = (t & 63) >> 3, cj = t & 7, strip = t >> 6;
-    const int i = bi * kBI + ci, j = bj * kBJ + cj, k0 = bk * kBK + strip * kStrip;
+    const int c = t & 63, w = t >> 6;
     const int64_t off = a.offsets[b];
     const int cnt = int(a.offsets[b + 1] - off);
     if (cnt == 0) return;
 
-    T gr[kStrip];
+    // grad_rho tile (zero outside the grid): consecutive threads read
+    // consecutive points of a column
     {
-        const bool inb = (i < d.dims[0]) && (j < d.dims[1]);
-        const T *src = reinterpret_cast<const T *>(a.grad_rho) + d.grid_off +
-                       (int64_t(inb ? i : 0) * d.dims[1] + (inb ? j : 0)) * d.dims[2];
-#pragma unroll
-        for (int r = 0; r < kStrip; ++r) gr[r] = (inb && k0 + r < d.dims[2]) ? src[k0 + r] : T(0);
+        const T *src = reinterpret_cast<const T *>(a.grad_rho) + d.grid_off;
+        for (int e = t; e < NC * kBK; e += kBrickThreads) {
+            const int cc = e / kBK, k = e - cc * kBK;
+            const int i = bi * kBI + (cc >> 3), j = bj * kBJ + (cc & 7), kk = bk * kBK + k;
+            const bool in = i < d.dims[0] && j < d.dims[1] && kk < d.dims[2];
+            tile[cc * GP + k] = in ? src[(int64_t(i) * d.dims[1] + j) * d.dims[2] + kk] : T(0);
+        }
     }
+    __syncthreads();
+    T g[kBK];
+#pragma unroll
+    for (int k = 0; k < kBK; ++k) g[k] = tile[c * GP + k];
+    __syncthreads();  // the tile's space now holds S0
+    T *s0t = tile;
 
     for (int c0 = 0; c0 < cnt; c0 += kChunk) {
         const int nc = (cnt - c0) < kChunk ? (cnt - c0) : kChunk;
         stage_atoms(atoms, a, d, off, c0, nc, t);
         __syncthreads();
-        for (int e = t; e < nc * (kBI + kBJ + kBK); e += kBrickThreads) {
-            const int s = e / (kBI + kBJ + kBK), q = e % (kBI + kBJ + kBK);
-            const StagedAtom &in = atoms[s];
-            if (q < kBI) {
-                const Cx<T> v = table_factor<T>(a, nb0, kBI, bi, q, in, 0);
-                gx[s][q] = v.x;
-                gdx[s][q] = v.y;
-            } else if (q < kBI + kBJ) {
-                const int qq = q - kBI;
-                const Cx<T> v = table_factor<T>(a, nb1, kBJ, bj, qq, in, 1);
-                gy[s][qq] = v.x;
-                gdy[s][qq] = v.y;
-            } else {
-                const int qq = q - kBI - kBJ;
-                const Cx<T> v = table_factor<T>(a, nb2, kBK, bk, qq, in, 2);
-                gz[s][qq] = v.x;
-                gdz[s][qq] = v.y;
-            }
-        }
+        fill_factors<T, true, false>(a, atoms, nc, nb0, nb1, nb2, bi, bj, bk, gx, gdx, gy, gdy, gz, gdz, t);
         __syncthreads();
-        for (int s = 0; s < nc; ++s) {
-            T s0 = T(0), s1 = T(0);
+        // A: contraction along k
+        for (int s = w; s < nc; s += 4) {
+            T a0 = T(0), a1 = T(0);
 #pragma unroll
-            for (int r = 0; r < kStrip; ++r) {
-                s0 += gr[r] * gz[s][strip * kStrip + r];
-                s1 += gr[r] * gdz[s][strip * kStrip + r];
+            for (int k = 0; k < kBK; ++k) {
+                a0 += g[k] * gz[s][k];
+                a1 += g[k] * gdz[s][k];
             }
-            const T fx = wave_sum_t<T>(gdx[s][ci] * gy[s][cj] * s0);
-            const T fy = wave_sum_t<T>(gx[s][ci] * gdy[s][cj] * s0);
-            const T fz = wave_sum_t<T>(gx[s][ci] * gy[s][cj] * s1);
-            if ((t & 63) == 0) {
-                red[strip][s][0] = fx;
-                red[strip][s][1] = fy;
-                red[strip][s][2] = fz;
-            }
+            s0t[c * SP + s] = a0;
+            s1t[c * SP + s] = a1;
         }
         __syncthreads();
-        for (int e = t; e < nc * 3; e += kBrickThreads) {
-            const int s = e / 3, x = e % 3;
-            const double v = double(red[0][s][x]) + double(red[1][s][x]) + double(red[2][s][x]) + double(red[3][s][x]);
+        // B: the transverse factors, per (atom, component)
+        if (t < 3 * nc) {
+            const int s = t / 3, x = t - 3 * s;
+            const T *X = x == 0 ? gdx[s] : gx[s];
+            const T *Y = x == 1 ? gdy[s] : gy[s];
+            const T *S = (x == 2 ? s1t : s0t) + s;
+            T f = T(0);
+#pragma unroll
+            for (int i = 0; i < kBI; ++i) {
+                T inner = T(0);
+#pragma unroll
+                for (int j = 0; j < kBJ; ++j) inner += Y[j] * S[(i * kBJ + j) * SP];
+                f += X[i] * inner;
+            }
             const int64_t slot = off + c0 + s;
-            if (slot < a.capacity) a.bpart[slot * 3 + x] = v;
+            if (slot < a.capacity) a.bpart[slot * 3 + x] = double(f);
         }
         __syncthreads();
     }
