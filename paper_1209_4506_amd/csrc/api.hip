@@ -584,6 +584,11 @@ SplatArgs splat_args(hartree_plan p, int32_t natoms, const double *pos, const do
     a.rec = (p->fp64 || p->general) ? nullptr : reinterpret_cast<SlotAtom *>(p->ws + p->o_rec);
     a.general = p->general ? 1 : 0;
     a.wide = p->wide ? 1 : 0;
+    // |g|, |gd| of a c-axis factor stay below 4 max(1, max_sigma) (a few
+    // images at most, |d| e^(-d^2 / 2 sigma^2) <= 0.61 sigma): scaled by
+    // 2^b_exp they stay below 2^14, inside the 16-bit range
+    a.b_exp = int(std::floor(std::log2(16384.0 / (4.0 * std::max(1.0, p->max_sigma)))));
+    a.b_exp = std::min(14, std::max(-60, a.b_exp));
     // a prime stride that does not divide natoms permutes the atoms
     a.visit_stride = 1;
     for (int32_t pr : {1009, 1013, 1019}) {

@@ -83,6 +83,7 @@ struct SplatArgs {
     int32_t general;        // 1: some cell is not diagonal-positive: the general-cell kernels run
     int32_t wide;           // 1: a truncation window may be wider than its cell (several images per point)
     int32_t visit_stride;   // coprime to natoms: binning visits atom (w * visit_stride) mod natoms
+    int32_t b_exp;          // FP32 adjoint: the c-axis factors enter the 16-bit products scaled by 2^b_exp
     void *rho;              // splat output grid
     const void *grad_rho;   // adjoint input grid
     int32_t grad_rows_vec4; // every problem's grad_rho rows start 16-byte aligned with Nc % 4 == 0

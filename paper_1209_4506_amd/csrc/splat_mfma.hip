@@ -27,6 +27,7 @@
 namespace hartree {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ int mfma_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
@@ -281,15 +282,26 @@ __global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
 // Adjoint pipeline step: one group of kAdjGroup atoms.  Its factors sit in
 // one of two LDS buffers: gx | gy and gdx | gdy rows per atom, and the gz,
 // gdz rows of the group's 32 matrix columns.
+// Matrix columns n < 16 hold gz of atom n, n >= 16 gdz of atom n - 16, as
+// the two halves of a 16-bit split (scaled by b_scale): x b_scale =
+// hi + lo, hi = fp16(x b_scale), lo = fp16(x b_scale - hi).  Rows of kBPitch
+// halves keep every 8-half run 16-byte aligned.
+constexpr int kBPitch = kMK + 8;
 struct AdjBuf {
     float gxy[kAdjGroup][kMI + kMJ + 1], gdxy[kAdjGroup][kMI + kMJ + 1];
-    float gz[2 * kAdjGroup][kMK + 1];  // columns n < 16: gz of atom n; n >= 16: gdz of atom n - 16
+    _Float16 bhi[2 * kAdjGroup][kBPitch], blo[2 * kAdjGroup][kBPitch];
 };
+
+__device__ __forceinline__ void split16(float x, _Float16 &hi, _Float16 &lo)
+{
+    hi = _Float16(x);
+    lo = _Float16(x - float(hi));
+}
 
 // factors of staged atoms s0 .. s0 + kAdjGroup - 1 into buf (zeros past nb)
 template <bool WIDE>
 __device__ __forceinline__ void adjoint_factors(AdjBuf &buf, const StagedG *recs, const LaneAxis &la, int s0, int nb,
-                                                int wave, int lane)
+                                                int wave, int lane, float bscale)
 {
     constexpr int R = kAdjGroup / 4;  // atoms per wavefront
     Entry v[R];
@@ -311,13 +323,20 @@ __device__ __forceinline__ void adjoint_factors(AdjBuf &buf, const StagedG *recs
     }
     const bool xy = lane < kMI + kMJ;
     const int zq = lane - kMI - kMJ;
+    if (xy) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int st = wave + 4 * r;
-        float *pg = xy ? &buf.gxy[st][lane] : &buf.gz[st][zq];
-        float *pd = xy ? &buf.gdxy[st][lane] : &buf.gz[kAdjGroup + st][zq];
-        *pg = v[r].g;
-        *pd = v[r].gd;
+        for (int r = 0; r < R; ++r) {
+            const int st = wave + 4 * r;
+            buf.gxy[st][lane] = v[r].g;
+            buf.gdxy[st][lane] = v[r].gd;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int st = wave + 4 * r;
+            split16(v[r].g * bscale, buf.bhi[st][zq], buf.blo[st][zq]);
+            split16(v[r].gd * bscale, buf.bhi[kAdjGroup + st][zq], buf.blo[kAdjGroup + st][zq]);
+        }
     }
 }
 
@@ -327,8 +346,8 @@ __device__ __forceinline__ void adjoint_factors(AdjBuf &buf, const StagedG *recs
 // j = 8 ((r / 4) % 2) + 4 half + r % 4, so the eight j values (and their gy,
 // gdy) are the same for both tiles and both halves r / 8.  Writes the lane's
 // two partial components to red[n][0 .. 1].
-__device__ __forceinline__ void adjoint_group(const AdjBuf &buf, const float (&g0)[16], const float (&g1)[16], int wave,
-                                              int lane, float (*red)[2])
+__device__ __forceinline__ void adjoint_group(const AdjBuf &buf, const half8 (&ah)[2][2], const half8 (&al)[2][2],
+                                              const float (&unscale)[2], int wave, int lane, float (*red)[2])
 {
     const int half = lane >> 5, n = lane & 31;
     const int f = n >> 4, sl = n & 15;
@@ -340,14 +359,30 @@ __device__ __forceinline__ void adjoint_group(const AdjBuf &buf, const float (&g
         dyv[r] = buf.gdxy[sl][kMI + j];
     }
     float ax = 0.0f, ay = 0.0f;  // f = 0: (x, y) components; f = 1: z in ax
+    // B operand: column n at points 16 kap + 8 half + e, e = 0 .. 7, in the
+    // same K slots as the A operand's grad_rho
+    half8 bh[2], bl[2];
+#pragma unroll
+    for (int kap = 0; kap < 2; ++kap) {
+        bh[kap] = *reinterpret_cast<const half8 *>(&buf.bhi[n][16 * kap + 8 * half]);
+        bl[kap] = *reinterpret_cast<const half8 *>(&buf.blo[n][16 * kap + 8 * half]);
+    }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
         floatx16 acc;
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+        // (hi + lo)(hi' + lo') without lo lo': the small terms first
 #pragma unroll
-        for (int m = 0; m < 16; ++m)
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(u == 0 ? g0[m] : g1[m], buf.gz[n][16 * half + m], acc, 0, 0, 0);
+        for (int kap = 0; kap < 2; ++kap) {
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(al[u][kap], bh[kap], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[u][kap], bl[kap], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int kap = 0; kap < 2; ++kap)
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[u][kap], bh[kap], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] *= unscale[u];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int i = 4 * wave + 2 * u + h;
@@ -388,6 +423,43 @@ __device__ __forceinline__ void adjoint_reduce(const SplatArgs &a, const float (
     }
 }
 
+// The wavefront's grad_rho rows of tile u (g0: u = 0, g1: u = 1) as the two
+// halves of a 16-bit split of g 2^k_u, with k_u the power of two that puts
+// the tile's largest magnitude in [2^13, 2^14) (clamped to the float range;
+// an all-zero tile takes k_u = 14).  unscale[u] = 2^-(k_u + b_exp) undoes
+// both operands' scales.
+__device__ __forceinline__ void split_grad(const float (&g0)[16], const float (&g1)[16], half8 (&ah)[2][2],
+                                           half8 (&al)[2][2], float (&unscale)[2], int b_exp)
+{
+    float m0 = 0.0f, m1 = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        m0 = fmaxf(m0, fabsf(g0[q]));
+        m1 = fmaxf(m1, fabsf(g1[q]));
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        m0 = fmaxf(m0, __shfl_xor(m0, off, 64));
+        m1 = fmaxf(m1, __shfl_xor(m1, off, 64));
+    }
+    int k[2] = {14 - __builtin_amdgcn_frexp_expf(m0), 14 - __builtin_amdgcn_frexp_expf(m1)};
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        k[u] = k[u] < -126 ? -126 : (k[u] > 127 ? 127 : k[u]);
+        unscale[u] = __builtin_ldexpf(1.0f, -k[u] - b_exp);
+        const float sc = __builtin_ldexpf(1.0f, k[u]);
+#pragma unroll
+        for (int kap = 0; kap < 2; ++kap)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                _Float16 hi, lo;
+                split16((u == 0 ? g0[8 * kap + e] : g1[8 * kap + e]) * sc, hi, lo);
+                ah[u][kap][e] = hi;
+                al[u][kap][e] = lo;
+            }
+    }
+}
+
 // adjoint: wave w holds grad_rho of its two row tiles in registers; per
 // group of 16 staged atoms it forms S for both tiles (32 columns n = 16 f +
 // atom) and folds the transverse factors in.  While a group's products run
@@ -421,13 +493,18 @@ __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
     const uint4 rr0 = rsrc[0], rr1 = rsrc[1], rr2 = rsrc[2], rr3 = rsrc[3];
 
     // grad_rho of this lane's two A rows (local i = 4 wave + col / 16 and
-    // + 2, j = col % 16) at points k = 32 bk + 16 half + m, m = 0 .. 15
+    // + 2, j = col % 16) at the points of its K slots: entry q = 8 kap + e
+    // (kap = 0, 1; e = 0 .. 7) is point k = 32 bk + 16 kap + 8 half + e, i.e.
+    // float4 v at offset 16 (v / 2) + 4 (v % 2) from 32 bk + 8 half.
     // Every load is unconditional (an element outside the grid reads a zero
     // block of the workspace), so no branch or arithmetic on the loaded
     // values separates the loads from the record wait below: they stay in
     // flight until the matrix products.  VEC: every problem's rows hold a
     // multiple of 4 points from a 16-byte aligned start.
     float g0[16], g1[16];
+    half8 ah[2][2], al[2][2];
+    float unscale[2];
+    const float bscale = __builtin_ldexpf(1.0f, a.b_exp);
     const float *src = reinterpret_cast<const float *>(a.grad_rho) + d.grid_off;
     const bool interior =
         (p.b0 + 1) * kMI <= d.dims[0] && (p.b1 + 1) * kMJ <= d.dims[1] && (p.b2 + 1) * kMK <= d.dims[2];
@@ -437,12 +514,13 @@ __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
         const int w = __builtin_amdgcn_readfirstlane(wave);
         const int64_t sb = d.dims[2], sa = int64_t(d.dims[1]) * d.dims[2];
         const float *base = src + (int64_t(p.b0 * kMI + 4 * w) * d.dims[1] + p.b1 * kMJ) * sb + p.b2 * kMK;
-        const uint32_t loff = uint32_t(((col >> 4) * d.dims[1] + (col & 15)) * d.dims[2] + 16 * half);
+        const uint32_t loff = uint32_t(((col >> 4) * d.dims[1] + (col & 15)) * d.dims[2] + 8 * half);
         const float4 *r0 = reinterpret_cast<const float4 *>(base + loff);
         const float4 *r1 = reinterpret_cast<const float4 *>(base + 2 * sa + loff);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const float4 v0 = r0[q], v1 = r1[q];
+            const int vo = 4 * (q >> 1) + (q & 1);  // float4 offset of slot vector q
+            const float4 v0 = r0[vo], v1 = r1[vo];
             g0[4 * q] = v0.x;
             g0[4 * q + 1] = v0.y;
             g0[4 * q + 2] = v0.z;
@@ -455,7 +533,7 @@ __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
     } else {
         const int j = p.b1 * kMJ + (col & 15);
         const int ia = p.b0 * kMI + 4 * wave + (col >> 4);
-        const int k0 = p.b2 * kMK + 16 * half;
+        const int k0 = p.b2 * kMK + 8 * half;
         const bool jin = j < d.dims[1];
         const bool in0 = jin && ia < d.dims[0], in1 = jin && ia + 2 < d.dims[0];
         const float *row0 = src + (in0 ? (int64_t(ia) * d.dims[1] + j) * d.dims[2] + k0 : 0);
@@ -463,9 +541,10 @@ __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
         if constexpr (VEC) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const bool kin = k0 + 4 * q < d.dims[2];  // whole vectors: Nc is a multiple of 4
-                const float4 v0 = *reinterpret_cast<const float4 *>(in0 && kin ? row0 + 4 * q : a.zeros);
-                const float4 v1 = *reinterpret_cast<const float4 *>(in1 && kin ? row1 + 4 * q : a.zeros);
+                const int ko = 16 * (q >> 1) + 4 * (q & 1);
+                const bool kin = k0 + ko < d.dims[2];  // whole vectors: Nc is a multiple of 4
+                const float4 v0 = *reinterpret_cast<const float4 *>(in0 && kin ? row0 + ko : a.zeros);
+                const float4 v1 = *reinterpret_cast<const float4 *>(in1 && kin ? row1 + ko : a.zeros);
                 g0[4 * q] = v0.x;
                 g0[4 * q + 1] = v0.y;
                 g0[4 * q + 2] = v0.z;
@@ -478,9 +557,10 @@ __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
         } else {
 #pragma unroll
             for (int m = 0; m < 16; ++m) {
-                const bool kin = k0 + m < d.dims[2];
-                g0[m] = *(in0 && kin ? row0 + m : a.zeros);
-                g1[m] = *(in1 && kin ? row1 + m : a.zeros);
+                const int ko = 16 * (m >> 3) + (m & 7);
+                const bool kin = k0 + ko < d.dims[2];
+                g0[m] = *(in0 && kin ? row0 + ko : a.zeros);
+                g1[m] = *(in1 && kin ? row1 + ko : a.zeros);
             }
         }
     }
@@ -504,13 +584,14 @@ __global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
             __syncthreads();
         }
         const int ngroup = (nb + kAdjGroup - 1) / kAdjGroup;
-        adjoint_factors<WIDE>(buf[0], recs, la, 0, nb, wave, lane);
+        adjoint_factors<WIDE>(buf[0], recs, la, 0, nb, wave, lane, bscale);
         __syncthreads();
+        if (blk == 0) split_grad(g0, g1, ah, al, unscale, a.b_exp);
         for (int gi = 0; gi < ngroup; ++gi) {
             if (gi > 0) adjoint_reduce(a, red[(gi - 1) & 1], recs, (gi - 1) * kAdjGroup, nb, t);
             if (gi + 1 < ngroup)
-                adjoint_factors<WIDE>(buf[(gi + 1) & 1], recs, la, (gi + 1) * kAdjGroup, nb, wave, lane);
-            adjoint_group(buf[gi & 1], g0, g1, wave, lane, red[gi & 1][wave][half]);
+                adjoint_factors<WIDE>(buf[(gi + 1) & 1], recs, la, (gi + 1) * kAdjGroup, nb, wave, lane, bscale);
+            adjoint_group(buf[gi & 1], ah, al, unscale, wave, lane, red[gi & 1][wave][half]);
             __syncthreads();
         }
         adjoint_reduce(a, red[(ngroup - 1) & 1], recs, (ngroup - 1) * kAdjGroup, nb, t);
