@@ -382,8 +382,6 @@ __device__ __forceinline__ void adjoint_group(const AdjBuf &buf, const half8 (&a
         for (int kap = 0; kap < 2; ++kap)
             acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[u][kap], bh[kap], acc, 0, 0, 0);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] *= unscale[u];
-#pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int i = 4 * wave + 2 * u + h;
             float sy = 0.0f, sdy = 0.0f;
@@ -392,6 +390,9 @@ __device__ __forceinline__ void adjoint_group(const AdjBuf &buf, const half8 (&a
                 sy += yv[r] * acc[8 * h + r];
                 sdy += dyv[r] * acc[8 * h + r];
             }
+            // the fold is linear in the products: undo the operand scales here
+            sy *= unscale[u];
+            sdy *= unscale[u];
             if (f == 0) {
                 ax += buf.gdxy[sl][i] * sy;
                 ay += buf.gxy[sl][i] * sdy;
@@ -465,8 +466,10 @@ __device__ __forceinline__ void split_grad(const float (&g0)[16], const float (&
 // atom) and folds the transverse factors in.  While a group's products run
 // on the matrix cores, the factors of the next group are evaluated, and the
 // previous group's partials are reduced.
+// Three workgroups per CU (a few registers spill to scratch): measured
+// faster than two without spills.
 template <bool VEC, bool WIDE>
-__global__ __launch_bounds__(kMThreads) void k_adjoint_mfma(SplatArgs a)
+__global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_adjoint_mfma(SplatArgs a)
 {
     __shared__ StagedG recs[kStage];
     __shared__ AdjBuf buf[2];
