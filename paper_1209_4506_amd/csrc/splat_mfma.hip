@@ -1,4 +1,6 @@
-// FP32 splat and splat adjoint on the matrix cores (v_mfma_f32_32x32x2f32).
+// FP32 splat and splat adjoint on the matrix cores: the splat with FP32
+// products (v_mfma_f32_32x32x2f32), the adjoint with 16-bit split products
+// (v_mfma_f32_32x32x16_f16, three per FP32-accurate product).
 //
 // A brick is 16 x 16 columns (i, j) by 32 points along c.  Inside it both
 // operations are dense contractions over the brick's atom list:
@@ -17,11 +19,14 @@
 // Operand layout of v_mfma_f32_32x32x2f32 (C = A B + C, A 32x2, B 2x32):
 // lane l supplies A[l % 32][l / 32] and B[l / 32][l % 32]; after the call
 // lane l holds C[i][l % 32] for i = 8 (r / 4) + 4 (l / 32) + r % 4 in its
-// accumulator element r = 0 .. 15.  Which reduction index sits in which of
-// the two K slots is free as long as A and B agree: the splat puts atom
-// 2 m + l / 32 in slot l / 32 of step m, the adjoint puts point
-// k = 16 (l / 32) + m there, so that each lane's grad_rho values are 16
-// consecutive points of one column, loaded once into registers.
+// accumulator element r = 0 .. 15.  v_mfma_f32_32x32x16_f16 has the same C
+// layout, with 8 K slots per lane: element e of lane l is K slot
+// 8 (l / 32) + e of both A (row l % 32) and B (column l % 32).  Which
+// reduction index sits in which K slot is free as long as A and B agree:
+// the splat puts atom 2 m + l / 32 in slot l / 32 of step m; the adjoint
+// puts point k = 16 kap + 8 (l / 32) + e in slot e of its product kap, so
+// that each lane's grad_rho values are two runs of 8 points of one column,
+// loaded once into registers.
 #include "splat_common.hpp"
 
 namespace hartree {
