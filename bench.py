@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--eager", action="store_true",
                     help="time eager launches only (no HIP graph replay region; value is then the eager rate)")
     ap.add_argument("--cpu-atoms", type=int, default=4096, help="atoms in the CPU-oracle sample (all of them by default)")
+    ap.add_argument("--workload", choices=("diamond360", "batched24"), default="diamond360",
+                    help="the headline 360^3 problem, or 24 uneven orthorhombic problems in one batched plan "
+                         "(solves/s then counts problems)")
     ap.add_argument("--atom-order", choices=("given", "shuffled", "bisection"), default="given",
                     help="atom order handed to the library: as generated (lattice order), a random "
                          "permutation, or the recursive-bisection order of hartree_atom_partition")
@@ -100,30 +103,39 @@ def reorder_atoms(prob, mode, nparts, H):
 
 
 class Step:
-    """Preallocated buffers and the four C-ABI calls of one fwd+bwd solve."""
+    """Preallocated buffers and the four C-ABI calls of one fwd+bwd solve of
+    one problem, or of a batch of problems on one batched plan."""
 
-    def __init__(self, prob, precision, torch, H, inputs, tune=True, cache=None):
+    def __init__(self, probs, precision, torch, H, inputs, tune=True, cache=None):
+        import numpy as np
+
         self.torch = torch
         dev = torch.device("cuda:0")
-        self.plan = H.Plan(prob.cell, prob.dims, precision=precision, device=dev, max_atoms=prob.natoms)
+        batched = len(probs) > 1
+        cells = np.stack([q.cell for q in probs])
+        dims = np.array([q.dims for q in probs])
+        self.counts = [q.natoms for q in probs] if batched else None
+        self.plan = H.Plan(cells if batched else cells[0], dims if batched else dims[0], precision=precision,
+                           device=dev, max_atoms=sum(q.natoms for q in probs))
         p = self.plan
         self.config = p.tune(reps=5, cache=cache) if tune else p.get_config()
-        self.pos = torch.tensor(prob.pos, device=dev)
-        self.Z = torch.tensor(prob.Z, device=dev)
-        self.sig = torch.tensor(prob.sigma, device=dev)
-        dv = p.dv()[0]
-        c = torch.tensor(inputs.random_grid(prob.dims, 1209), device=dev, dtype=torch.float64)
-        self.gv = (c * dv).to(p.dtype).contiguous()
-        self.ge = torch.ones(1, dtype=torch.float64, device=dev)
+        self.pos = torch.tensor(np.concatenate([q.pos for q in probs]), device=dev)
+        self.Z = torch.tensor(np.concatenate([q.Z for q in probs]), device=dev)
+        self.sig = torch.tensor(np.concatenate([q.sigma for q in probs]), device=dev)
+        dvs = p.dv()
+        c = np.concatenate([inputs.random_grid(q.dims, 1209 + i).reshape(-1) * dvs[i] for i, q in enumerate(probs)])
+        self.gv = torch.tensor(c, device=dev).to(p.dtype).reshape(p.empty_grid().shape).contiguous()
+        self.ge = torch.ones(len(probs), dtype=torch.float64, device=dev)
         self.rho = p.empty_grid()
         self.V = p.empty_grid()
-        self.E = torch.empty(1, dtype=torch.float64, device=dev)
+        self.E = torch.empty(len(probs), dtype=torch.float64, device=dev)
         self.grho = p.empty_grid()
-        self.gpos = torch.empty((prob.natoms, 3), dtype=torch.float64, device=dev)
+        self.gpos = torch.empty((self.pos.shape[0], 3), dtype=torch.float64, device=dev)
 
     def __call__(self):
         p = self.plan
-        token = p.bind_atoms(self.pos, self.Z, self.sig)   # binning shared by splat and adjoint
+        # binning shared by splat and adjoint
+        token = p.bind_atoms(self.pos, self.Z, self.sig, atom_counts=self.counts)
         p.splat_bound(token, out=self.rho)
         p.solve(self.rho, v=self.V, e_h=self.E)
         p.backward(grad_v=self.gv, grad_e=self.ge, rho=self.rho, out=self.grho)
@@ -170,22 +182,29 @@ class Step:
         return dt, same
 
 
-def kernel_bytes(name, prob, s):
-    """Algorithmic HBM bytes of one launch of a kernel group (s = bytes per real)."""
-    na, nb, nc = prob.dims
-    n = na * nb * nc
-    spec = na * nb * (nc // 2 + 1) * 2 * s  # half spectrum, complex
-    return {
-        "r2c": n * s + spec,
-        "r2c_bwd": 2 * n * s + spec,
-        "fft_b": 2 * spec,
-        "fft_b_inv": 2 * spec,
-        "fft_a": 2 * spec,
-        "fft_a_bwd": 2 * spec,
-        "c2r": spec + n * s,
-        "splat": n * s,
-        "adjoint": n * s,
-    }.get(name)
+def kernel_bytes(name, probs, s):
+    """Algorithmic HBM bytes of one launch of a kernel group over the
+    problems of the plan (s = bytes per real)."""
+    total = 0
+    for prob in probs:
+        na, nb, nc = prob.dims
+        n = na * nb * nc
+        spec = na * nb * (nc // 2 + 1) * 2 * s  # half spectrum, complex
+        b = {
+            "r2c": n * s + spec,
+            "r2c_bwd": 2 * n * s + spec,
+            "fft_b": 2 * spec,
+            "fft_b_inv": 2 * spec,
+            "fft_a": 2 * spec,
+            "fft_a_bwd": 2 * spec,
+            "c2r": spec + n * s,
+            "splat": n * s,
+            "adjoint": n * s,
+        }.get(name)
+        if b is None:
+            return None
+        total += b
+    return total
 
 
 def kernel_flops(name, pairs):
@@ -202,12 +221,12 @@ def kernel_flops(name, pairs):
 MFMA_EXEC = {"splat": (1, PEAK_MFMA_F32_TFLOPS), "adjoint": (3, PEAK_MFMA_F16_TFLOPS)}
 
 
-def roofline_of(name, prob, s, pairs, avg_ms, precision="fp32"):
+def roofline_of(name, probs, s, pairs, avg_ms, precision="fp32"):
     """Roofline entry of one kernel group from its average launch time: the
     matrix-core kernels (splat, adjoint) against the FP32 MFMA peak, the
     grid passes against HBM."""
     fl = kernel_flops(name, pairs)
-    by = kernel_bytes(name, prob, s)
+    by = kernel_bytes(name, probs, s)
     if fl is not None:
         mult, peak = MFMA_EXEC[name]
         alg = fl / (avg_ms * 1e-3) / 1e12
@@ -287,13 +306,28 @@ def main():
     import paper_1209_4506_amd.hartree as H
     from paper_1209_4506_amd import inputs
 
-    prob, part_ms = reorder_atoms(inputs.diamond360(), args.atom_order, args.atom_parts, H)
-    step = Step(prob, "fp32", torch, H, inputs, tune=not args.no_tune, cache=args.tune_cache)
+    if args.workload == "diamond360":
+        prob, part_ms = reorder_atoms(inputs.diamond360(), args.atom_order, args.atom_parts, H)
+        probs = [prob]
+        workload = ("diamond360: 8x8x8 diamond supercell, a = 53.93 Bohr, 4096 Gaussian atoms (Z = 4, sigma = 0.8 "
+                    "Bohr, N(0, 0.05) displacements, seed 1211), 360^3 grid, FP32 transforms with FP64 E_H and "
+                    "force reductions, splat + solve + backward + adjoint per step")
+        wconf = {"grid": list(prob.dims), "atoms": prob.natoms}
+    else:
+        probs, part_ms = inputs.batched24(), None
+        workload = ("batched24: 24 orthorhombic cells (edges U[8, 40] Bohr, each grid dimension from {48, 60, 72, "
+                    "90, 120, 150, 180, 240}, 16-512 atoms with Z in {1, 4, 6} and sigma U[0.6, 1.0]) in one "
+                    "batched plan, FP32 transforms with FP64 reductions, splat + solve + backward + adjoint of all "
+                    "24 per step; solves count problems")
+        wconf = {"problems": len(probs), "points": int(sum(q.npoints for q in probs)),
+                 "atoms": int(sum(q.natoms for q in probs))}
+    nprob = len(probs)
+    step = Step(probs, "fp32", torch, H, inputs, tune=not args.no_tune, cache=args.tune_cache)
     assert step.plan.device_status() == 0
     # eager region: every kernel group bracketed by HIP events (the roofline)
     dt_eager, prof = step.timed(args.steps, args.warmup, profile=True)
     assert step.plan.device_status() == 0, "device status bits set"
-    eager = {"value": args.steps / dt_eager, "unit": "solves/s", "ms_per_step": 1000.0 * dt_eager / args.steps}
+    eager = {"value": nprob * args.steps / dt_eager, "unit": "solves/s", "ms_per_step": 1000.0 * dt_eager / args.steps}
     if args.eager:
         dt = dt_eager
         mode = "eager launches, per-kernel HIP events"
@@ -305,19 +339,19 @@ def main():
         mode = "HIP graph replay of the whole step (outputs bit-identical to the eager step)"
     ms = 1000.0 * dt / args.steps
     s = 4
-    n = prob.npoints
+    n = sum(q.npoints for q in probs)
     model_bytes = 23 * s * n
     # dominant kernel group by time
     groups = {k: v for k, v in prof.items()}
     pairs = step.plan.atoms_pairs()
-    rooflines = {k: roofline_of(k, prob, s, pairs, v[0] / v[1]) for k, v in groups.items()}
+    rooflines = {k: roofline_of(k, probs, s, pairs, v[0] / v[1]) for k, v in groups.items()}
     rooflines = {k: v for k, v in rooflines.items() if v is not None}
     dom = max(rooflines, key=lambda k: groups[k][0])
     per_kernel = {k: {"avg_us": round(1000.0 * v[0] / v[1], 2), "launches": v[1],
                       "share": round(v[0] / sum(x[0] for x in groups.values()), 4)} for k, v in groups.items()}
     out = {
         "metric": METRIC,
-        "value": args.steps / dt,
+        "value": nprob * args.steps / dt,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -328,11 +362,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "diamond360: 8x8x8 diamond supercell, a = 53.93 Bohr, 4096 Gaussian atoms "
-                               "(Z = 4, sigma = 0.8 Bohr, N(0, 0.05) displacements, seed 1211), 360^3 grid, "
-                               "FP32 transforms with FP64 E_H and force reductions, splat + solve + backward "
-                               "+ adjoint per step",
-                   "grid": list(prob.dims), "atoms": prob.natoms, "precision": "fp32"},
+        "config": dict({"workload": workload}, **wconf, precision="fp32"),
         "hbm_gbs_model": model_bytes / (ms * 1e-3) / 1e9,
         "roofline": rooflines[dom],
         "kernel_rooflines": {k: {"bound": v["bound"], "achieved": round(v["achieved"], 2), "unit": v["unit"],
@@ -349,17 +379,17 @@ def main():
     if not args.no_fp64:
         del step
         torch.cuda.empty_cache()
-        step64 = Step(prob, "fp64", torch, H, inputs, tune=not args.no_tune, cache=args.tune_cache)
+        step64 = Step(probs, "fp64", torch, H, inputs, tune=not args.no_tune, cache=args.tune_cache)
         k64 = max(3, args.steps // 4)
         dt64, prof64 = step64.timed(k64, 2, profile=True)
-        out["fp64_plain"] = {"value": k64 / dt64, "unit": "solves/s", "ms_per_step": 1000.0 * dt64 / k64,
+        out["fp64_plain"] = {"value": nprob * k64 / dt64, "unit": "solves/s", "ms_per_step": 1000.0 * dt64 / k64,
                              "steps": k64, "hbm_gbs_model": 23 * 8 * n / (dt64 / k64) / 1e9,
                              "kernels": {k: round(1000.0 * v[0] / v[1], 2) for k, v in prof64.items()}}
         out["speedup_vs_fp64_plain"] = out["value"] / out["fp64_plain"]["value"]
         del step64
         torch.cuda.empty_cache()
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_atoms, inputs)
+    if not args.no_cpu_baseline and args.workload == "diamond360":
+        out["cpu_baseline"] = cpu_baseline(probs[0], args.cpu_atoms, inputs)
     line = json.dumps(out)
     print(line, flush=True)
     if args.out:

@@ -21,9 +21,10 @@
 // consecutive complex values of each grid row, and the tile passes through
 // LDS only between stages.
 //
-// Radices 2, 3, 4, 5, 7 and 8 are written out; 9, 10 and 16 are built as
-// two-level products of those, so most lengths of interest need at most three
-// stages.
+// Radices 2, 3, 4, 5, 7 and 8 are written out; 9 and 16 are built as
+// two-level Cooley-Tukey products of those, and 6, 10 and 12 (coprime
+// factors) as prime-factor products without inner twiddles, so most lengths
+// of interest need at most three stages.
 #pragma once
 
 #include "common.hpp"
@@ -143,6 +144,42 @@ __device__ __forceinline__ void dft_product(Cx<T> *x)
     }
 }
 
+// inverse of a modulo m (a and m coprime), by search: compile-time only
+constexpr int inv_mod(int a, int m)
+{
+    for (int i = 1; i < m; ++i)
+        if ((a * i) % m == 1) return i;
+    return 1;
+}
+
+// Coprime product radix R = A B (Good-Thomas prime-factor mapping): with the
+// input map n = (B n1 + A n2) mod R and the output map
+// k = (B B' k1 + A A' k2) mod R, where B' = B^-1 mod A and A' = A^-1 mod B,
+// W_R^(n k) = W_A^(n1 k1) W_B^(n2 k2): an A x B two-dimensional DFT with no
+// twiddle factors between the levels.  The maps are register renamings.
+template <typename T, int A, int B, bool INV>
+__device__ __forceinline__ void dft_coprime(Cx<T> *x)
+{
+    constexpr int R = A * B;
+    constexpr int Bi = inv_mod(B % A, A), Ai = inv_mod(A % B, B);
+    Cx<T> y[A][B];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) {
+        Cx<T> t[A];
+#pragma unroll
+        for (int n1 = 0; n1 < A; ++n1) t[n1] = x[(B * n1 + A * n2) % R];
+        butterfly<T, A, INV>(t);
+#pragma unroll
+        for (int k1 = 0; k1 < A; ++k1) y[k1][n2] = t[k1];
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+        butterfly<T, B, INV>(y[k1]);
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) x[(B * Bi * k1 + A * Ai * k2) % R] = y[k1][k2];
+    }
+}
+
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void butterfly(Cx<T> *a)
 {
@@ -176,13 +213,13 @@ __device__ __forceinline__ void butterfly(Cx<T> *a)
     } else if constexpr (R == 3 || R == 5 || R == 7) {
         dft_odd<T, R, INV>(a);
     } else if constexpr (R == 6) {
-        dft_product<T, 2, 3, INV>(a);
+        dft_coprime<T, 2, 3, INV>(a);
     } else if constexpr (R == 9) {
         dft_product<T, 3, 3, INV>(a);
     } else if constexpr (R == 10) {
-        dft_product<T, 2, 5, INV>(a);
+        dft_coprime<T, 2, 5, INV>(a);
     } else if constexpr (R == 12) {
-        dft_product<T, 4, 3, INV>(a);
+        dft_coprime<T, 4, 3, INV>(a);
     } else {
         static_assert(R == 16, "unsupported radix");
         dft_product<T, 4, 4, INV>(a);
@@ -449,15 +486,20 @@ __device__ __forceinline__ void fft_any(const Src &src, Dst &dst, const L &lds, 
 // Radix plans with their own compiled kernels: the stage radices that the
 // plan search picks for common lengths (32, 48, 60, 64, 72, 90, 96, 120, 128,
 // 150, 160, 180, 192, 200, 210, 240, 256, 288, 300, 320, 360, 384, 400, 420,
-// 480, 512, 576, 600, 640, 720, 768, 800, 840, 960, 1024, 2048).  Other
-// lengths run the run-time radix switch.
+// 480, 512, 576, 600, 640, 720, 768, 800, 840, 960, 1024, 2048), then
+// alternatives that the tuner may prefer: radix-6 stages for 360 and 180,
+// whose butterfly counts (36 and 60 per pencil for 360) fill a 64-lane
+// wavefront better than 40, 45 and 72.  Entries are only ever appended, so
+// that stored tuner choices keep their meaning.  Other lengths run the
+// run-time radix switch.
 #define HARTREE_PLANS(X)                                                                                  \
     X(8, 4, 0, 0) X(16, 3, 0, 0) X(5, 4, 3, 0) X(8, 8, 0, 0) X(9, 8, 0, 0) X(10, 9, 0, 0) X(8, 4, 3, 0)   \
     X(8, 5, 3, 0) X(16, 8, 0, 0) X(10, 5, 3, 0) X(16, 10, 0, 0) X(9, 5, 4, 0) X(8, 8, 3, 0)              \
     X(8, 5, 5, 0) X(10, 7, 3, 0) X(10, 8, 3, 0) X(16, 16, 0, 0) X(9, 8, 4, 0) X(10, 10, 3, 0)            \
     X(8, 8, 5, 0) X(9, 8, 5, 0) X(16, 8, 3, 0) X(10, 10, 4, 0) X(7, 5, 4, 3) X(16, 10, 3, 0)             \
     X(8, 8, 8, 0) X(9, 8, 8, 0) X(8, 5, 5, 3) X(10, 8, 8, 0) X(10, 9, 8, 0) X(16, 16, 3, 0)              \
-    X(10, 10, 8, 0) X(8, 7, 5, 3) X(8, 8, 5, 3) X(16, 16, 4, 0) X(16, 16, 8, 0)
+    X(10, 10, 8, 0) X(8, 7, 5, 3) X(8, 8, 5, 3) X(16, 16, 4, 0) X(16, 16, 8, 0)                          \
+    X(10, 6, 6, 0) X(6, 6, 10, 0) X(6, 10, 6, 0) X(10, 6, 3, 0) X(6, 6, 5, 0)
 
 // Blocks are dispatched round-robin over the 8 XCDs (each with its own L2);
 // renumber them so that consecutive work items land on the same XCD, where

@@ -415,6 +415,47 @@ def test_bound_atoms_reuse(H):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("n", [360, 180])
+def test_every_compiled_plan(H, oracle_mod, prec, n):
+    """Every compiled radix plan that factors n, at every tile width the
+    plan accepts, on each axis in turn (the a, b and c passes): the solve and
+    the backward match the oracle.  The tuner may pick any of these, so each
+    is checked, not only the default choice."""
+    cell = CELLS["triclinic"]
+    ft = np.float32 if prec == "fp32" else np.float64
+    checked = 0
+    for x in range(3):
+        dims = [12, 10, 14]
+        dims[x] = n
+        dims = tuple(dims)
+        plan = H.Plan(cell, dims, precision=prec, max_atoms=1)
+        base = plan.get_config()
+        rho = inputs.random_grid(dims, 31 + x).astype(ft)
+        gv = inputs.random_grid(dims, 41 + x).astype(ft)
+        V_o, _, e_recip, _ = oracle_mod.poisson(cell.reshape(9), rho.astype(np.float64))
+        G_o = oracle_mod.backward(cell.reshape(9), rho.astype(np.float64), grad_v=gv.astype(np.float64), grad_e=0.3)
+        rho_d, gv_d = to_dev(rho, plan.dtype), to_dev(gv, plan.dtype)
+        for pid in range(64):
+            for lp in range(7):
+                cfg = base.copy()
+                cfg[0, x] = (pid, lp, 0 if x == 2 else 1)
+                try:
+                    plan.set_config(cfg)
+                except H.HartreeError:
+                    continue
+                say("case compiled plan", prec, dims, "axis", x, "entry", pid, "p_log2", lp)
+                V, E = plan.solve(rho_d)
+                g = plan.backward(grad_v=gv_d, grad_e=torch.tensor([0.3], dtype=torch.float64), rho=rho_d)
+                torch.cuda.synchronize()
+                assert rel_l2(V.double().cpu().numpy(), V_o) <= TOL[prec]["v"]
+                assert abs(float(E[0]) - e_recip) <= TOL[prec]["e"] * abs(e_recip)
+                assert rel_l2(g.double().cpu().numpy(), G_o) <= TOL[prec]["v"]
+                checked += 1
+    # 360 and 180 each have several compiled plans, radix-6 ones among them
+    assert checked >= 12
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_tuned_plan_parity(H, oracle_mod, prec):
     """After hartree_plan_tune (and a config round trip) the solve and the
     backward still match the oracle; a batched plan tunes per length."""
