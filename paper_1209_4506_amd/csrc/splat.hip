@@ -23,6 +23,8 @@
 //   gather  per brick: rho = sum over its atoms of w gx(i) gy(j) gz(k) [- Q/Omega]
 //   adjoint per brick: partial sum_r grad_rho(r) g(r) d(r) for each of its atoms
 //   final   per atom: fixed-order sum of its partials over the touched bricks
+#include <algorithm>
+
 #include "splat_common.hpp"
 
 namespace hartree {
@@ -255,15 +257,23 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(SplatArgs a)
     }
 }
 
-// one wavefront per brick: order the list by atom index (indices are
-// distinct, so an entry's rank is the count of smaller ones), and record
-// each entry's final slot under (atom, brick) for the adjoint's reduction.
-// Lists of up to kSortLds entries are ranked from LDS.
+// one wavefront per brick: order the list by atom index, and record each
+// entry's final slot under (atom, brick) for the adjoint's reduction.  A
+// brick's atoms all belong to its problem, whose indices span
+// [atom_off[p], atom_off[p + 1]).  When every problem's span fits rank_words
+// 32-bit words (rank_words > 0), each entry sets its bit in an LDS bitmap of
+// the span and its rank is the number of set bits below it: prefix sums of
+// the words' bit counts plus one popcount, O(cnt + span / 32) per brick.
+// Otherwise (rank_words = 0) the rank is the count of smaller entries
+// (indices are distinct), O(cnt^2), read from LDS for lists of up to kSortLds
+// entries.
 constexpr int kSortLds = 256;
+constexpr int kRankWords = 1024;  // bitmap ranks for spans of up to 32,768 atoms
 
-__global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a)
+__global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a, int rank_words)
 {
     __shared__ int lst[4][kSortLds];
+    extern __shared__ uint32_t rank_lds[];  // rank_words > 0: [4 waves][bitmap, word prefix][rank_words]
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t b = int64_t(blockIdx.x) * 4 + w;
     int64_t off = 0;
@@ -278,20 +288,57 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a)
             a.cursor[b] = 0;
         }
     }
+    int prob = 0;
+    if (cnt > 0)
+        while (prob + 1 < a.nprob && b >= a.desc[prob + 1].brick_off) ++prob;
+    const int a0 = a.atom_off[prob];
+    const int span = a.atom_off[prob + 1] - a0;
+    const bool bitmap = rank_words > 0;
+    uint32_t *bm = rank_lds + w * 2 * rank_words, *pre = bm + rank_words;
     const bool in_lds = cnt <= kSortLds;
-    if (in_lds)
+    if (bitmap) {
+        for (int i = lane; i < rank_words; i += 64) bm[i] = 0u;
+        __syncthreads();
+        for (int e = lane; e < cnt; e += 64) {
+            const int r = a.list[off + e] - a0;
+            if (unsigned(r) < unsigned(span)) atomicOr(&bm[r >> 5], 1u << (r & 31));
+        }
+        __syncthreads();
+        // exclusive prefix of the words' bit counts: lane l takes a run of
+        // consecutive words, a wavefront scan orders the runs
+        const int nw = (span + 31) >> 5, wpl = (nw + 63) >> 6;
+        const int w0 = lane * wpl < nw ? lane * wpl : nw, w1 = w0 + wpl < nw ? w0 + wpl : nw;
+        int c = 0;
+        for (int i = w0; i < w1; ++i) c += __popc(bm[i]);
+        int x = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        int run = x - c;
+        for (int i = w0; i < w1; ++i) {
+            pre[i] = uint32_t(run);
+            run += __popc(bm[i]);
+        }
+    } else if (in_lds) {
         for (int e = lane; e < cnt; e += 64) lst[w][e] = a.list[off + e];
+    }
     __syncthreads();
     if (cnt == 0) return;
-    int prob = 0;
-    while (prob + 1 < a.nprob && b >= a.desc[prob + 1].brick_off) ++prob;
     const ProbDesc &d = a.desc[prob];
     for (int e = lane; e < cnt; e += 64) {
-        const int v = in_lds ? lst[w][e] : a.list[off + e];
-        int rank = 0;
-        if (in_lds) {
+        int v, rank = 0;
+        if (bitmap) {
+            v = a.list[off + e];
+            const int r = v - a0;
+            if (unsigned(r) >= unsigned(span)) continue;  // not an atom of this problem: never written
+            rank = int(pre[r >> 5]) + __popc(bm[r >> 5] & ((1u << (r & 31)) - 1u));
+        } else if (in_lds) {
+            v = lst[w][e];
             for (int j = 0; j < cnt; ++j) rank += (lst[w][j] < v) ? 1 : 0;
         } else {
+            v = a.list[off + e];
             for (int j = 0; j < cnt; ++j) rank += (a.list[off + j] < v) ? 1 : 0;
         }
         a.list_sorted[off + rank] = v;
@@ -574,7 +621,12 @@ hipError_t run_bin(const SplatArgs &a, hipStream_t s)
     }
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, a);
     if (a.natoms > 0) hipLaunchKernelGGL(k_brick_visit<1>, dim3(nw), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_brick_sort, dim3(int((nbt + 3) / 4)), dim3(256), 0, s, a);
+    int span = 0;
+    for (int p = 0; p < a.nprob; ++p) span = std::max(span, a.atom_off[p + 1] - a.atom_off[p]);
+    const int words = (span + 31) / 32;
+    const int rank_words = words <= kRankWords ? words : 0;
+    hipLaunchKernelGGL(k_brick_sort, dim3(int((nbt + 3) / 4)), dim3(256), size_t(rank_words) * 4 * 2 * 4, s, a,
+                       rank_words);
     return hipGetLastError();
 }
 

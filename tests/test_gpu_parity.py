@@ -150,6 +150,42 @@ def test_splat_adjoint_parity(H, oracle_mod, prec, case):
     assert err <= (1e-10 if prec == "fp64" else 1e-5)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_many_atoms_one_problem(H, oracle_mod, prec):
+    """33,000 atoms in one problem, more than the binning's bitmap ranks cover
+    (32,768 atoms per problem): the brick lists are then ranked by counting.
+    The density at sampled points and the forces on 8 seeded atoms against the
+    oracle; two splats agree bit for bit."""
+    say("case many atoms in one problem", prec)
+    p = inputs.small_problem((192, 192, 96), 33000, seed=12, L=(60.0, 60.0, 30.0), sig=(0.6, 0.7))
+    cell9 = p.cell.reshape(9)
+    plan = H.Plan(p.cell, p.dims, precision=prec, max_atoms=p.natoms)
+    pos, Z, sig = _atoms(p)
+    rho = plan.splat(pos, Z, sig)
+    rho2 = plan.splat(pos, Z, sig)
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    assert torch.equal(rho, rho2)
+    rng = np.random.default_rng(12)
+    flat = rng.choice(int(np.prod(p.dims)), 100, replace=False)
+    ref = oracle_mod.splat_points(cell9, p.dims, p.pos, p.Z, p.sigma, flat)
+    got = rho.reshape(-1)[torch.tensor(flat, device="cuda")].double().cpu().numpy()
+    err = np.abs(got - ref).max() / float(torch.max(torch.abs(rho)).item())
+    say("  sampled density max-rel %.3e" % err)
+    assert err <= (1e-12 if prec == "fp64" else 2e-6)
+    # a smooth field for the adjoint
+    ix = [np.arange(n) / n for n in p.dims]
+    g = (np.cos(2 * np.pi * ix[0])[:, None, None] + 0.5 * np.sin(4 * np.pi * ix[1])[None, :, None]
+         + 0.25 * np.cos(2 * np.pi * ix[2])[None, None, :]).astype(np.float32 if prec == "fp32" else np.float64)
+    F = plan.splat_adjoint(pos, Z, sig, to_dev(g, plan.dtype)).cpu().numpy()
+    assert plan.device_status() == 0
+    sel = rng.choice(p.natoms, 8, replace=False)
+    ref = oracle_mod.splat_adjoint(cell9, p.pos, p.Z, p.sigma, g.astype(np.float64), sel=sel)
+    err = np.abs(F[sel] - ref).max() / np.abs(ref).max()
+    say("  forces on 8 atoms max-rel %.3e" % err)
+    assert err <= (1e-10 if prec == "fp64" else 1e-5)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_end_to_end_cubic32(H, oracle_mod, prec):
     """32^3 cubic cell, 8 Gaussians: splat, V, E_H, and dL/dR for
