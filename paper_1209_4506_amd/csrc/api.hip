@@ -185,9 +185,31 @@ struct hartree_plan_s {
         graph_exec = nullptr;
         graph = nullptr;
     }
+    // side streams of a batched plan: the launch groups of one pass (problems
+    // with different pass shapes) write disjoint problems, so they run side by
+    // side, forked from and joined back into the caller's stream by events
+    // (under capture: parallel branches of the graph).  Default priority.
+    static constexpr int kSide = 3;
+    hipStream_t side[kSide] = {};
+    hipEvent_t fork_ev = nullptr;
+    hipEvent_t join_ev[kSide] = {};
+    bool side_ready = false;
+    void drop_side()
+    {
+        for (int i = 0; i < kSide; ++i) {
+            if (side[i]) (void)hipStreamDestroy(side[i]);
+            if (join_ev[i]) (void)hipEventDestroy(join_ev[i]);
+            side[i] = nullptr;
+            join_ev[i] = nullptr;
+        }
+        if (fork_ev) (void)hipEventDestroy(fork_ev);
+        fork_ev = nullptr;
+        side_ready = false;
+    }
     ~hartree_plan_s()
     {
         drop_graph();
+        drop_side();
         for (hipEvent_t e : pool) (void)hipEventDestroy(e);
     }
 };
@@ -542,15 +564,50 @@ int kernel_id(PassKind kind)
     }
 }
 
+// The launch groups of one pass.  With side streams (batched plans) the
+// groups are dealt, largest first, to the least-loaded of the caller's stream
+// and the side streams, forked after the work already on `s` and joined back
+// before the pass returns; results do not depend on the dealing (disjoint
+// problems, fixed per-problem sums).
 hipError_t run_group(hartree_plan p, const std::vector<Launch> &groups, PassKind kind, PassArgs a, hipStream_t s)
 {
-    return timed(p, kernel_id(kind), s, [&]() {
-        for (const Launch &l : groups) {
-            a.tl = l.tl;
-            hipError_t e = run_pass(p->fp64, kind, l.plan, l.p_log2, l.pad, l.maxn, l.tl.total, s, a);
-            if (e != hipSuccess) return e;
+    return timed(p, kernel_id(kind), s, [&]() -> hipError_t {
+        const int ng = int(groups.size());
+        const int nside = (ng > 1 && p->side_ready) ? std::min(ng - 1, int(hartree_plan_s::kSide)) : 0;
+        if (nside == 0) {
+            for (const Launch &l : groups) {
+                a.tl = l.tl;
+                hipError_t e = run_pass(p->fp64, kind, l.plan, l.p_log2, l.pad, l.maxn, l.tl.total, s, a);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
         }
-        return hipSuccess;
+        std::vector<int> order(ng);
+        for (int i = 0; i < ng; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return groups[x].tl.total > groups[y].tl.total; });
+        hipStream_t st[hartree_plan_s::kSide + 1] = {s};
+        int64_t load[hartree_plan_s::kSide + 1] = {};
+        for (int k = 0; k < nside; ++k) st[k + 1] = p->side[k];
+        hipError_t e = hipEventRecord(p->fork_ev, s);
+        for (int k = 0; k < nside && e == hipSuccess; ++k) e = hipStreamWaitEvent(p->side[k], p->fork_ev, 0);
+        for (int i = 0; i < ng && e == hipSuccess; ++i) {
+            int best = 0;
+            for (int k = 1; k <= nside; ++k)
+                if (load[k] < load[best]) best = k;
+            const Launch &l = groups[order[i]];
+            load[best] += l.tl.total;
+            a.tl = l.tl;
+            e = run_pass(p->fp64, kind, l.plan, l.p_log2, l.pad, l.maxn, l.tl.total, st[best], a);
+        }
+        // join every side stream that was forked, also after an error, so
+        // that no capture is left with an unjoined branch
+        for (int k = 0; k < nside; ++k) {
+            hipError_t j = hipEventRecord(p->join_ev[k], p->side[k]);
+            if (j == hipSuccess) j = hipStreamWaitEvent(s, p->join_ev[k], 0);
+            if (e == hipSuccess) e = j;
+        }
+        return e;
     });
 }
 
@@ -699,6 +756,18 @@ hartree_status hartree_bind_workspace(hartree_plan plan, void *workspace, size_t
     const unsigned char zero[256] = {};
     e = hipMemcpy(ws + plan->o_zero, zero, sizeof(zero), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "clearing the zero block");
+    if (plan->nprob > 1 && !plan->side_ready) {
+        // side streams for the launch groups of batched passes (on the
+        // device current now, the workspace's); without them the groups run
+        // one after another on the caller's stream
+        bool okay = true;
+        for (int i = 0; i < hartree_plan_s::kSide && okay; ++i)
+            okay = hipStreamCreateWithFlags(&plan->side[i], hipStreamNonBlocking) == hipSuccess &&
+                   hipEventCreateWithFlags(&plan->join_ev[i], hipEventDisableTiming) == hipSuccess;
+        okay = okay && hipEventCreateWithFlags(&plan->fork_ev, hipEventDisableTiming) == hipSuccess;
+        if (okay) plan->side_ready = true;
+        else plan->drop_side();
+    }
     if (plan->splat_ok) {
         // binning keeps its brick counters cleared from one call to the next
         e = hipMemset(ws + plan->o_counts, 0, 4 * size_t(plan->nbricks + 1));
