@@ -313,6 +313,15 @@ __device__ __forceinline__ T kernel_value(const ProbDesc &d, int ma, int mb, int
     return sum / T(na * nb * nc);
 }
 
+// kernel_value out of line: the Nyquist cells of a non-orthorhombic cell are
+// rare, and inlining their alias loop into every store of the last stage
+// would multiply the kernel's code size
+template <typename T>
+__device__ __noinline__ T kernel_value_rare(const ProbDesc &d, int ma, int mb, int mc)
+{
+    return kernel_value<T>(d, ma, mb, mc);
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -325,9 +334,12 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
 // Destination of the last forward stage along a: element m_a of the thread's
 // column is multiplied by K(G)/N on its way into the LDS tile, and (energy)
-// w(m_c) K |X|^2 is accumulated in double.  The column's share of G,
-// m_b b_b + m_c b_c, is formed once per thread; cells where the Nyquist
-// average applies take the general path of kernel_value.
+// w(m_c) K |X|^2 is accumulated in double.  With G = s_a b_a + g, where
+// g = m_b b_b + m_c b_c is the column's share, |G|^2 is the quadratic
+// s_a^2 |b_a|^2 + s_a (2 b_a . g) + |g|^2 whose three coefficients are formed
+// once per thread (for an orthorhombic cell the middle one is exactly 0);
+// cells where the Nyquist average applies take the general path of
+// kernel_value.
 template <typename T>
 struct KernelMultiply {
     static constexpr bool kLds = true;
@@ -341,7 +353,7 @@ struct KernelMultiply {
     double acc;
     int na;
     bool general;     // a Nyquist b or c index of a non-orthorhombic cell
-    T ba[3], gbc[3];  // b_a and m_b b_b + m_c b_c
+    T q2, q1, q0;     // |G|^2 = (q2 s_a + q1) s_a + q0
     __device__ __forceinline__ void init()
     {
         const T *B = nullptr;
@@ -351,20 +363,22 @@ struct KernelMultiply {
         na = d->dims[0];
         general = !d->ortho && (2 * mb == Nb || 2 * mc == Nc);
         const T sb = T((2 * mb < Nb) ? mb : mb - Nb), sc = T(mc);
+        q2 = q1 = q0 = T(0);
         for (int x = 0; x < 3; ++x) {
-            ba[x] = B[x];
-            gbc[x] = sb * B[3 + x] + sc * B[6 + x];
+            const T g = sb * B[3 + x] + sc * B[6 + x];
+            q2 += B[x] * B[x];
+            q1 += T(2) * B[x] * g;
+            q0 += g * g;
         }
     }
     __device__ __forceinline__ void store(int i, Cx<T> v)
     {
         T K;
         if (general || (!d->ortho && 2 * i == na)) {
-            K = kernel_value<T>(*d, i, mb, mc);
+            K = kernel_value_rare<T>(*d, i, mb, mc);
         } else {
             const T sa = T((2 * i < na) ? i : i - na);
-            const T gx = sa * ba[0] + gbc[0], gy = sa * ba[1] + gbc[1], gz = sa * ba[2] + gbc[2];
-            const T g2 = gx * gx + gy * gy + gz * gz;
+            const T g2 = (q2 * sa + q1) * sa + q0;
             K = (g2 > T(0)) ? T(12.566370614359172953850573533118) * recip(g2) : T(0);
         }
         if (energy) acc += wgt * double(K * (v.x * v.x + v.y * v.y));
