@@ -112,7 +112,15 @@ hartree_status hartree_plan_grid_offset(hartree_plan plan, int32_t p, int64_t *o
  * least that many bytes, 256-byte aligned.  Binding uploads the FP64-generated
  * twiddle tables with a synchronous copy; apart from hartree_device_status,
  * hartree_plan_set_config and hartree_plan_tune it is the only call that
- * synchronizes.  Rebinding replaces the previous workspace. */
+ * synchronizes.  Rebinding replaces the previous workspace.  The first binding
+ * of a batched plan (nprob > 1) also creates three internal streams of
+ * default priority on the current device: each transform pass forks its
+ * launch groups (problems with different pass shapes) onto them after the
+ * work already queued on the caller's stream and joins them back before the
+ * pass returns, so calls stay ordered on the caller's stream (under capture
+ * the groups become parallel branches of the graph).  If the streams cannot
+ * be created the groups run on the caller's stream; results are the same
+ * either way.  The plan owns the streams until hartree_plan_destroy. */
 hartree_status hartree_workspace_size(hartree_plan plan, size_t *bytes);
 hartree_status hartree_bind_workspace(hartree_plan plan, void *workspace, size_t bytes);
 
