@@ -388,12 +388,18 @@ struct KernelMultiply {
 
 // mode 0: forward, energy, multiply, inverse.  mode 1: no energy.
 // mode 2: forward and energy only (no potential).
-// pencils along a: column (b, h) of the flattened [Nb][Nh] plane
-template <typename T, int R0, int R1, int R2, int R3>
+// pencils along a: column (b, h) of the flattened [Nb][Nh] plane.
+// CP > 0: a tile of exactly CP pencils with no pitch pad (the host launches
+// it only for that shape), so the tile pitch and the threads per pencil are
+// compile-time constants: LDS offsets become immediates and the per-stage
+// bounds checks fold away.
+template <typename T, int R0, int R1, int R2, int R3, int CP = 0>
 __global__ __launch_bounds__(256) void k_fft_a(PassArgs a)
 {
     constexpr int NT = kPassThreads;
-    const int P = 1 << a.p_log2, TPP = NT >> a.p_log2, PP = P + a.pad;
+    const int P = CP > 0 ? CP : 1 << a.p_log2;
+    const int TPP = NT / P;
+    const int PP = CP > 0 ? CP : P + a.pad;
     const int mode = a.mode;
     const bool energy = mode != 1;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -410,7 +416,7 @@ __global__ __launch_bounds__(256) void k_fft_a(PassArgs a)
     const int tid = threadIdx.x;
     load_twiddles(tw, reinterpret_cast<const Cx<T> *>(a.tw) + d.ax[0].tw_off, n, tid, NT);
     __syncthreads();
-    const int p = tid & (P - 1), tip = tid >> a.p_log2;
+    const int p = tid & (P - 1), tip = CP > 0 ? tid / CP : tid >> a.p_log2;
     const int col = col0 + (p < valid ? p : 0);
     const int mb = int(fdiv(uint32_t(col), d.div_nh));
     const int mc = col - mb * nh;

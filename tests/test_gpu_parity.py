@@ -5,6 +5,8 @@ Tolerances: FP64 V rel-L2 <= 1e-12, E_H rel <= 1e-12; FP32 V rel-L2 <= 5e-6,
 E_H rel <= 1e-6.  The FP32 inputs are rounded to float first and the oracle
 is fed the same rounded values.
 """
+import itertools
+
 import numpy as np
 import pytest
 import torch
@@ -454,9 +456,10 @@ def test_bound_atoms_reuse(H):
 @pytest.mark.parametrize("n", [360, 180])
 def test_every_compiled_plan(H, oracle_mod, prec, n):
     """Every compiled radix plan that factors n, at every tile width the
-    plan accepts, on each axis in turn (the a, b and c passes): the solve and
-    the backward match the oracle.  The tuner may pick any of these, so each
-    is checked, not only the default choice."""
+    plan accepts and pitch pads 0 and 1 (strided axes), on each axis in turn
+    (the a, b and c passes; some tile shapes have kernels of their own): the
+    solve and the backward match the oracle.  The tuner may pick any of
+    these, so each is checked, not only the default choice."""
     cell = CELLS["triclinic"]
     ft = np.float32 if prec == "fp32" else np.float64
     checked = 0
@@ -471,22 +474,21 @@ def test_every_compiled_plan(H, oracle_mod, prec, n):
         V_o, _, e_recip, _ = oracle_mod.poisson(cell.reshape(9), rho.astype(np.float64))
         G_o = oracle_mod.backward(cell.reshape(9), rho.astype(np.float64), grad_v=gv.astype(np.float64), grad_e=0.3)
         rho_d, gv_d = to_dev(rho, plan.dtype), to_dev(gv, plan.dtype)
-        for pid in range(64):
-            for lp in range(7):
-                cfg = base.copy()
-                cfg[0, x] = (pid, lp, 0 if x == 2 else 1)
-                try:
-                    plan.set_config(cfg)
-                except H.HartreeError:
-                    continue
-                say("case compiled plan", prec, dims, "axis", x, "entry", pid, "p_log2", lp)
-                V, E = plan.solve(rho_d)
-                g = plan.backward(grad_v=gv_d, grad_e=torch.tensor([0.3], dtype=torch.float64), rho=rho_d)
-                torch.cuda.synchronize()
-                assert rel_l2(V.double().cpu().numpy(), V_o) <= TOL[prec]["v"]
-                assert abs(float(E[0]) - e_recip) <= TOL[prec]["e"] * abs(e_recip)
-                assert rel_l2(g.double().cpu().numpy(), G_o) <= TOL[prec]["v"]
-                checked += 1
+        for pid, lp, pad in itertools.product(range(64), range(7), (0,) if x == 2 else (0, 1)):
+            cfg = base.copy()
+            cfg[0, x] = (pid, lp, pad)
+            try:
+                plan.set_config(cfg)
+            except H.HartreeError:
+                continue
+            say("case compiled plan", prec, dims, "axis", x, "entry", pid, "p_log2", lp, "pad", pad)
+            V, E = plan.solve(rho_d)
+            g = plan.backward(grad_v=gv_d, grad_e=torch.tensor([0.3], dtype=torch.float64), rho=rho_d)
+            torch.cuda.synchronize()
+            assert rel_l2(V.double().cpu().numpy(), V_o) <= TOL[prec]["v"]
+            assert abs(float(E[0]) - e_recip) <= TOL[prec]["e"] * abs(e_recip)
+            assert rel_l2(g.double().cpu().numpy(), G_o) <= TOL[prec]["v"]
+            checked += 1
     # 360 and 180 each have several compiled plans, radix-6 ones among them
     assert checked >= 12
 
