@@ -133,21 +133,31 @@ struct RealPairOut {
 
 // pencil-major tile pitch: n rounded so that consecutive pencils start in
 // opposite halves of the LDS banks
-__host__ __device__ inline int row_pitch(int n) { return n + ((16 - n % 32) + 32) % 32; }
+__host__ __device__ constexpr int row_pitch(int n) { return n + ((16 - n % 32) + 32) % 32; }
+
+// length of a compiled radix plan (0 for the run-time radix kernel)
+constexpr int plan_length(int r0, int r1, int r2, int r3)
+{
+    return r0 == 0 ? 0 : r0 * (r1 > 0 ? r1 : 1) * (r2 > 0 ? r2 : 1) * (r3 > 0 ? r3 : 1);
+}
 
 // ---------------------------------------------------------------- P1
 // MODE 0: x = rho.  MODE 1 (backward): x = grad_v + grad_e * dV * rho.
 // MODE 2: x = grad_e * dV * rho.
-template <typename T, int MODE, int R0, int R1, int R2, int R3>
+// CP > 0 (passes along c; a compiled plan): tiles of exactly CP pencils
+// (2 CP rows), launched only for that shape, with the pencil length (the
+// plan's) compiled in as well, so tile offsets and loop bounds are constants.
+template <typename T, int MODE, int R0, int R1, int R2, int R3, int CP = 0>
 __global__ __launch_bounds__(256) void k_r2c_mode(PassArgs a)
 {
     constexpr int NT = kPassThreads;
-    const int P = 1 << a.p_log2, TPP = NT >> a.p_log2;
+    constexpr int NF = CP > 0 ? plan_length(R0, R1, R2, R3) : 0;
+    const int P = CP > 0 ? CP : 1 << a.p_log2, TPP = NT / P;
     extern __shared__ __align__(16) unsigned char smem[];
     int prob, tile;
     find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
     const ProbDesc &d = a.desc[prob];
-    const int n = d.dims[2], nh = d.dims[3];
+    const int n = NF > 0 ? NF : d.dims[2], nh = NF > 0 ? NF / 2 + 1 : d.dims[3];
     const int ldp = row_pitch(n);
     const int64_t nrows = int64_t(d.dims[0]) * d.dims[1];
     const int64_t row0 = int64_t(tile) * 2 * P;
@@ -185,7 +195,7 @@ __global__ __launch_bounds__(256) void k_r2c_mode(PassArgs a)
     Cx<T> *dst = reinterpret_cast<Cx<T> *>(a.spec) + d.spec_off + row0 * nh;
     const int totalh = rows * nh;
     for (int e = tid; e < totalh; e += NT) {
-        const int row = int(fdiv(uint32_t(e), d.div_nh));
+        const int row = NF > 0 ? e / nh : int(fdiv(uint32_t(e), d.div_nh));
         const int k = e - row * nh;
         const Cx<T> *z = buf + (row >> 1) * ldp;
         const Cx<T> A = z[k];
@@ -200,16 +210,18 @@ __global__ __launch_bounds__(256) void k_r2c_mode(PassArgs a)
 }
 
 // ---------------------------------------------------------------- P5
-template <typename T, int R0, int R1, int R2, int R3>
+// CP > 0: as for P1
+template <typename T, int R0, int R1, int R2, int R3, int CP = 0>
 __global__ __launch_bounds__(256) void k_c2r(PassArgs a)
 {
     constexpr int NT = kPassThreads;
-    const int P = 1 << a.p_log2, TPP = NT >> a.p_log2;
+    constexpr int NF = CP > 0 ? plan_length(R0, R1, R2, R3) : 0;
+    const int P = CP > 0 ? CP : 1 << a.p_log2, TPP = NT / P;
     extern __shared__ __align__(16) unsigned char smem[];
     int prob, tile;
     find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
     const ProbDesc &d = a.desc[prob];
-    const int n = d.dims[2], nh = d.dims[3];
+    const int n = NF > 0 ? NF : d.dims[2], nh = NF > 0 ? NF / 2 + 1 : d.dims[3];
     const int ldp = row_pitch(n);
     const int64_t nrows = int64_t(d.dims[0]) * d.dims[1];
     const int64_t row0 = int64_t(tile) * 2 * P;
@@ -245,12 +257,16 @@ __global__ __launch_bounds__(256) void k_c2r(PassArgs a)
 
 // ---------------------------------------------------------------- P2 / P4
 // pencils along b: (a, h) for fixed a, P consecutive h per tile; the first
-// stage reads the tile from the spectrum and the last writes it back
-template <typename T, int R0, int R1, int R2, int R3>
+// stage reads the tile from the spectrum and the last writes it back.
+// CP > 0: tiles of exactly CP pencils with no pitch pad, compiled in (as for
+// the a pass).
+template <typename T, int R0, int R1, int R2, int R3, int CP = 0>
 __global__ __launch_bounds__(256) void k_fft_b(PassArgs a)
 {
     constexpr int NT = kPassThreads;
-    const int P = 1 << a.p_log2, TPP = NT >> a.p_log2, PP = P + a.pad;
+    const int P = CP > 0 ? CP : 1 << a.p_log2;
+    const int TPP = NT / P;
+    const int PP = CP > 0 ? CP : P + a.pad;
     extern __shared__ __align__(16) unsigned char smem[];
     int prob, tile;
     find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
@@ -266,7 +282,7 @@ __global__ __launch_bounds__(256) void k_fft_b(PassArgs a)
     const int tid = threadIdx.x;
     load_twiddles(tw, reinterpret_cast<const Cx<T> *>(a.tw) + d.ax[1].tw_off, n, tid, NT);
     __syncthreads();
-    const int p = tid & (P - 1), tip = tid >> a.p_log2;
+    const int p = tid & (P - 1), tip = CP > 0 ? tid / CP : tid >> a.p_log2;
     Cx<T> *g = reinterpret_cast<Cx<T> *>(a.spec) + d.spec_off + int64_t(outer) * n * nh + h0 + (p < valid ? p : 0);
     GlobalPencil<T> gp{g, nh, p < valid, a.inv != 0};
     const LdsPencil<T> lp{buf, PP, p, false};

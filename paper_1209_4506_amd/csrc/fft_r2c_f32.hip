@@ -1,28 +1,37 @@
 // P1 (r2c along c) kernels, FP32: one per radix plan of HARTREE_PLANS plus the run-time
 // radix kernel (one translation unit per pass and precision so the build
-// compiles them in parallel).
+// compiles them in parallel), and per plan a second kernel for the tile of
+// 4 pencils, whose tile shape and pencil length are compiled in.
 #include "fft_passes.hpp"
 
 namespace hartree {
 namespace {
-template <int R0, int R1, int R2, int R3>
+constexpr int kFixedPencils = 4;
+
+template <int R0, int R1, int R2, int R3, int CP>
 hipError_t launch_one(int grid, size_t lds, hipStream_t s, const PassArgs &a)
 {
     // forward: rho.  Backward (mode 1): grad_v + s rho, grad_v alone (no
     // grad_e), or s rho alone (no grad_v); the host never passes neither.
-    if (a.mode == 0 || a.grad_e == nullptr) return launch_pass(k_r2c_mode<float, 0, R0, R1, R2, R3>, grid, lds, s, a);
-    if (a.in != nullptr) return launch_pass(k_r2c_mode<float, 1, R0, R1, R2, R3>, grid, lds, s, a);
-    return launch_pass(k_r2c_mode<float, 2, R0, R1, R2, R3>, grid, lds, s, a);
+    if (a.mode == 0 || a.grad_e == nullptr)
+        return launch_pass(k_r2c_mode<float, 0, R0, R1, R2, R3, CP>, grid, lds, s, a);
+    if (a.in != nullptr) return launch_pass(k_r2c_mode<float, 1, R0, R1, R2, R3, CP>, grid, lds, s, a);
+    return launch_pass(k_r2c_mode<float, 2, R0, R1, R2, R3, CP>, grid, lds, s, a);
 }
-#define HARTREE_ENTRY(R0, R1, R2, R3) &launch_one<R0, R1, R2, R3>,
+#define HARTREE_ENTRY(R0, R1, R2, R3) &launch_one<R0, R1, R2, R3, 0>,
 const PassLaunchFn kTable[] = {HARTREE_PLANS(HARTREE_ENTRY)};
+#undef HARTREE_ENTRY
+#define HARTREE_ENTRY(R0, R1, R2, R3) &launch_one<R0, R1, R2, R3, kFixedPencils>,
+const PassLaunchFn kFixed[] = {HARTREE_PLANS(HARTREE_ENTRY)};
 #undef HARTREE_ENTRY
 }  // namespace
 
 hipError_t run_r2c_f32(int plan, int maxn, int grid, hipStream_t s, const PassArgs &a)
 {
     const size_t lds = pass_lds_bytes<float>(a, maxn);
-    if (plan < 0 || plan >= int(sizeof(kTable) / sizeof(kTable[0]))) return launch_one<0, 0, 0, 0>(grid, lds, s, a);
+    if (plan < 0 || plan >= int(sizeof(kTable) / sizeof(kTable[0])))
+        return launch_one<0, 0, 0, 0, 0>(grid, lds, s, a);
+    if ((1 << a.p_log2) == kFixedPencils && a.pad == 0) return kFixed[plan](grid, lds, s, a);
     return kTable[plan](grid, lds, s, a);
 }
 }  // namespace hartree
