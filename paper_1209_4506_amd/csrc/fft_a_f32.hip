@@ -1,28 +1,33 @@
 // P3 (fused FFT along a) kernels, FP32: one per radix plan of HARTREE_PLANS plus the run-time
 // radix kernel (one translation unit per pass and precision so the build
-// compiles them in parallel), and per plan a second kernel for the tile of
-// 8 pencils with no pitch pad, whose tile shape is compiled in.
+// compiles them in parallel), and per plan kernels for tiles of 4, 8 and 16
+// pencils with no pitch pad, whose tile shape is compiled in.
 #include "fft_passes.hpp"
 
 namespace hartree {
 namespace {
-constexpr int kFixedPencils = 8;
 
 template <int R0, int R1, int R2, int R3>
 hipError_t launch_one(int grid, size_t lds, hipStream_t s, const PassArgs &a)
 {
     return launch_pass(k_fft_a<float, R0, R1, R2, R3>, grid, lds, s, a);
 }
-template <int R0, int R1, int R2, int R3>
+template <int R0, int R1, int R2, int R3, int CP>
 hipError_t launch_fixed(int grid, size_t lds, hipStream_t s, const PassArgs &a)
 {
-    return launch_pass(k_fft_a<float, R0, R1, R2, R3, kFixedPencils>, grid, lds, s, a);
+    return launch_pass(k_fft_a<float, R0, R1, R2, R3, CP>, grid, lds, s, a);
 }
 #define HARTREE_ENTRY(R0, R1, R2, R3) &launch_one<R0, R1, R2, R3>,
 const PassLaunchFn kTable[] = {HARTREE_PLANS(HARTREE_ENTRY)};
 #undef HARTREE_ENTRY
-#define HARTREE_ENTRY(R0, R1, R2, R3) &launch_fixed<R0, R1, R2, R3>,
-const PassLaunchFn kFixed[] = {HARTREE_PLANS(HARTREE_ENTRY)};
+#define HARTREE_ENTRY(R0, R1, R2, R3) &launch_fixed<R0, R1, R2, R3, 4>,
+const PassLaunchFn kFixed4[] = {HARTREE_PLANS(HARTREE_ENTRY)};
+#undef HARTREE_ENTRY
+#define HARTREE_ENTRY(R0, R1, R2, R3) &launch_fixed<R0, R1, R2, R3, 8>,
+const PassLaunchFn kFixed8[] = {HARTREE_PLANS(HARTREE_ENTRY)};
+#undef HARTREE_ENTRY
+#define HARTREE_ENTRY(R0, R1, R2, R3) &launch_fixed<R0, R1, R2, R3, 16>,
+const PassLaunchFn kFixed16[] = {HARTREE_PLANS(HARTREE_ENTRY)};
 #undef HARTREE_ENTRY
 }  // namespace
 
@@ -30,7 +35,9 @@ hipError_t run_a_f32(int plan, int maxn, int grid, hipStream_t s, const PassArgs
 {
     const size_t lds = pass_lds_bytes<float>(a, maxn);
     if (plan < 0 || plan >= int(sizeof(kTable) / sizeof(kTable[0]))) return launch_one<0, 0, 0, 0>(grid, lds, s, a);
-    if ((1 << a.p_log2) == kFixedPencils && a.pad == 0) return kFixed[plan](grid, lds, s, a);
+    if (a.pad == 0 && a.p_log2 == 2) return kFixed4[plan](grid, lds, s, a);
+    if (a.pad == 0 && a.p_log2 == 3) return kFixed8[plan](grid, lds, s, a);
+    if (a.pad == 0 && a.p_log2 == 4) return kFixed16[plan](grid, lds, s, a);
     return kTable[plan](grid, lds, s, a);
 }
 }  // namespace hartree
