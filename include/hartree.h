@@ -113,14 +113,16 @@ hartree_status hartree_plan_grid_offset(hartree_plan plan, int32_t p, int64_t *o
  * twiddle tables with a synchronous copy; apart from hartree_device_status,
  * hartree_plan_set_config and hartree_plan_tune it is the only call that
  * synchronizes.  Rebinding replaces the previous workspace.  The first binding
- * of a batched plan (nprob > 1) also creates three internal streams of
- * default priority on the current device: each transform pass forks its
- * launch groups (problems with different pass shapes) onto them after the
- * work already queued on the caller's stream and joins them back before the
- * pass returns, so calls stay ordered on the caller's stream (under capture
- * the groups become parallel branches of the graph).  If the streams cannot
- * be created the groups run on the caller's stream; results are the same
- * either way.  The plan owns the streams until hartree_plan_destroy. */
+ * also creates three internal streams of default priority on the current
+ * device.  Work forked onto them (the launch groups of a batched plan's
+ * transform passes, i.e. problems with different pass shapes, and the E_H
+ * finalize of hartree_solve, which runs beside the inverse passes) starts
+ * after the work already queued on the caller's stream and is joined back
+ * before the call returns, so calls stay ordered on the caller's stream
+ * (under capture the forked work becomes parallel branches of the graph).
+ * If the streams cannot be created everything runs on the caller's stream;
+ * results are the same either way.  The plan owns the streams until
+ * hartree_plan_destroy. */
 hartree_status hartree_workspace_size(hartree_plan plan, size_t *bytes);
 hartree_status hartree_bind_workspace(hartree_plan plan, void *workspace, size_t bytes);
 
