@@ -1,10 +1,11 @@
 // Mixed-radix Stockham pencil FFT for gfx950.
 //
 // A workgroup transforms P pencils of one axis.  Between stages the pencils
-// live in LDS as buf[i * PP + p] (element i of pencil p, PP = P + 1: the pitch
-// is padded by one so that both a row of P consecutive pencils and a run of
-// consecutive elements of one pencil fall on distinct banks).  Threads are
-// (p, tip) with p fastest, TPP threads per pencil.
+// of a strided axis live in LDS as buf[i * PP + p] (element i of pencil p,
+// PP = P + pad with pad 0..3 chosen per axis, by a bank-conflict model or by
+// the tuner); pencils along the contiguous axis live pencil-major,
+// buf[p * ldp + i].  Threads are (p, tip) with p fastest, TPP threads per
+// pencil.
 //
 // Stage s has radix R and Ns = product of the earlier radices; butterfly
 // j < n/R of every pencil computes

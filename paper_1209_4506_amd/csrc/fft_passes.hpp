@@ -28,7 +28,8 @@ namespace hartree {
 
 // A workgroup has 256 threads: P pencils (P = 1 << p_log2, chosen by the
 // host per launch) with tpp = 256 / P threads each; the LDS tile holds
-// n (P + 1) complex values.
+// n (P + pad) complex values (strided axes) or P row_pitch(n) (axis c), then
+// the axis' n twiddle factors.
 constexpr int kPassThreads = 256;
 
 // 16-byte vectors of reals for the contiguous real-grid rows
