@@ -157,3 +157,37 @@ def test_pass_config_validation(lib):
         assert list(cfg) == vals                                 # rejected choices change nothing
         assert lib.hartree_plan_tune(h, ctypes.c_void_p(1), 3, None) == 5   # no workspace bound
         lib.hartree_plan_destroy(h)
+
+
+def test_compiled_plans_for_360_and_180(lib):
+    """The compiled radix plans accepted for a length are exactly the table
+    entries whose radices multiply to it: for 360 the 9 x 8 x 5 entry and the
+    three radix-6 orders (10 x 6 x 6, 6 x 6 x 10, 6 x 10 x 6), for 180 the
+    9 x 5 x 4 entry and 10 x 6 x 3, 6 x 6 x 5.  Entries are only appended to
+    the table, so these indices are stable (stored tuner choices use them).
+    Host-side validation only (64 KiB of LDS assumed without a device)."""
+    lib.hartree_plan_destroy.argtypes = [ctypes.c_void_p]
+    for fn in ("hartree_plan_get_config", "hartree_plan_set_config"):
+        getattr(lib, fn).restype = ctypes.c_int
+    expect = {360: {20, 36, 37, 38}, 180: {11, 39, 40}}
+    for prec in (0, 1):
+        for n, ids in expect.items():
+            for x in range(3):
+                dims = [12, 10, 14]
+                dims[x] = n
+                rc, h = _create(lib, np.diag([9.0, 10.0, 11.0]), tuple(dims), prec=prec)
+                assert rc == 0
+                cfg = (ctypes.c_int32 * 9)()
+                assert lib.hartree_plan_get_config(h, cfg) == 0
+                base = list(cfg)
+                accepted = set()
+                for pid in range(64):
+                    for lp in range(7):
+                        trial = (ctypes.c_int32 * 9)(*base)
+                        trial[3 * x], trial[3 * x + 1], trial[3 * x + 2] = pid, lp, 0
+                        if lib.hartree_plan_set_config(h, trial) == 0:
+                            accepted.add(pid)
+                            break
+                assert accepted == ids, (prec, n, x, sorted(accepted))
+                lib.hartree_plan_destroy(h)
+
