@@ -458,7 +458,8 @@ def test_every_compiled_plan(H, oracle_mod, prec, n):
     """Every compiled radix plan that factors n, at every tile width the
     plan accepts and pitch pads 0 and 1 (strided axes), on each axis in turn
     (the a, b and c passes; some tile shapes have kernels of their own): the
-    solve and the backward match the oracle.  The tuner may pick any of
+    solve and the backward (with grad_v and grad_e, and grad_e alone) match
+    the oracle.  The tuner may pick any of
     these, so each is checked, not only the default choice."""
     cell = CELLS["triclinic"]
     ft = np.float32 if prec == "fp32" else np.float64
@@ -473,6 +474,7 @@ def test_every_compiled_plan(H, oracle_mod, prec, n):
         gv = inputs.random_grid(dims, 41 + x).astype(ft)
         V_o, _, e_recip, _ = oracle_mod.poisson(cell.reshape(9), rho.astype(np.float64))
         G_o = oracle_mod.backward(cell.reshape(9), rho.astype(np.float64), grad_v=gv.astype(np.float64), grad_e=0.3)
+        G_e = oracle_mod.backward(cell.reshape(9), rho.astype(np.float64), grad_v=None, grad_e=0.3)
         rho_d, gv_d = to_dev(rho, plan.dtype), to_dev(gv, plan.dtype)
         for pid, lp, pad in itertools.product(range(64), range(7), (0,) if x == 2 else (0, 1)):
             cfg = base.copy()
@@ -484,10 +486,12 @@ def test_every_compiled_plan(H, oracle_mod, prec, n):
             say("case compiled plan", prec, dims, "axis", x, "entry", pid, "p_log2", lp, "pad", pad)
             V, E = plan.solve(rho_d)
             g = plan.backward(grad_v=gv_d, grad_e=torch.tensor([0.3], dtype=torch.float64), rho=rho_d)
+            ge = plan.backward(grad_v=None, grad_e=torch.tensor([0.3], dtype=torch.float64), rho=rho_d)
             torch.cuda.synchronize()
             assert rel_l2(V.double().cpu().numpy(), V_o) <= TOL[prec]["v"]
             assert abs(float(E[0]) - e_recip) <= TOL[prec]["e"] * abs(e_recip)
             assert rel_l2(g.double().cpu().numpy(), G_o) <= TOL[prec]["v"]
+            assert rel_l2(ge.double().cpu().numpy(), G_e) <= TOL[prec]["v"]
             checked += 1
     # 360 and 180 each have several compiled plans, radix-6 ones among them
     assert checked >= 12
