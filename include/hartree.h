@@ -310,6 +310,29 @@ hartree_status hartree_plan_tune(hartree_plan plan, void *scratch, int32_t reps,
 hartree_status hartree_atom_partition(int32_t natoms, const double *pos, const double *weights, int32_t nparts,
                                       int32_t *order, int32_t *part, int32_t *part_start);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as hartree_solve (V, and E_H when e_h is not NULL) with no
+ * workspace bound to the plan and no allocation of any kind.  The plan's
+ * problem descriptors, twiddle tables, half spectrum and E_H partials live in
+ * a device array owned by the library, HARTREE_NOALLOC_BYTES (64 MiB) per
+ * GPU, which every GPU the library runs on holds until the process ends; the
+ * first call on a device looks up that device's copy (the current device's,
+ * which must be the stream's).  Each call first rewrites the descriptors and
+ * twiddles (twiddles generated on the device in FP64, so an FP64 plan may
+ * differ from hartree_solve in the last bit of a twiddle) and every
+ * intermediate it reads, so nothing needs clearing between calls.
+ *   rho, v, e_h, stream  as for hartree_solve; everything runs in order on
+ *                        `stream` (no internal side streams).
+ * HARTREE_ERR_WORKSPACE, before anything is enqueued, when the plan needs more
+ * than HARTREE_NOALLOC_BYTES (the message names both sizes): a 240^3 FP32 or
+ * a 180^3 FP64 plan fits, a 256^3 FP32 plan does not.  All calls on one GPU
+ * share the one array: two calls that overlap in time on the same GPU (two
+ * streams, two threads, or a call beside a graph replay that contains one)
+ * race on it and give wrong results; a caller serializes them. */
+#define HARTREE_NOALLOC_BYTES (64u * 1024u * 1024u)
+hartree_status hartree_solve_noalloc(hartree_plan plan, const void *rho, void *v, double *e_h, void *stream);
+
 /* Description of the last error on the calling thread ("" if none). */
 const char *hartree_last_error(void);
 

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -539,16 +540,20 @@ hipError_t timed(hartree_plan p, int id, hipStream_t s, F f)
     return hipSuccess;
 }
 
-PassArgs base_args(hartree_plan p)
+// pass arguments on a workspace laid out as the plan's (the bound one, or
+// the no-allocation entry point's device scratch)
+PassArgs base_args_at(hartree_plan p, unsigned char *ws)
 {
     PassArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.desc = reinterpret_cast<const ProbDesc *>(p->ws + p->o_desc);
-    a.tw = p->ws + p->o_tw;
-    a.spec = p->ws + p->o_spec;
-    a.partials = reinterpret_cast<double *>(p->ws + p->o_parts);
+    a.desc = reinterpret_cast<const ProbDesc *>(ws + p->o_desc);
+    a.tw = ws + p->o_tw;
+    a.spec = ws + p->o_spec;
+    a.partials = reinterpret_cast<double *>(ws + p->o_parts);
     return a;
 }
+
+PassArgs base_args(hartree_plan p) { return base_args_at(p, p->ws); }
 
 int kernel_id(PassKind kind)
 {
@@ -1185,11 +1190,11 @@ void get_config(hartree_plan p, std::vector<int32_t> &cfg)
 }
 
 // enqueue the passes along axis x (both directions) once
-hipError_t run_axis(hartree_plan p, int x, void *scratch, hipStream_t s)
+hipError_t run_axis(hartree_plan p, int x, void *grid, hipStream_t s)
 {
     PassArgs a = base_args(p);
-    a.in = scratch;
-    a.out = scratch;
+    a.in = grid;
+    a.out = grid;
     hipError_t e;
     if (x == 2) {
         if ((e = run_group(p, p->lr2c, PASS_R2C_FWD, a, s)) != hipSuccess) return e;
@@ -1221,11 +1226,11 @@ hartree_status hartree_plan_set_config(hartree_plan plan, const int32_t *cfg)
     return st == HARTREE_OK ? ok() : st;
 }
 
-hartree_status hartree_plan_tune(hartree_plan plan, void *scratch, int32_t reps, void *stream)
+hartree_status hartree_plan_tune(hartree_plan plan, void *grid, int32_t reps, void *stream)
 {
     hartree_status st = check_ws(plan);
     if (st != HARTREE_OK) return st;
-    if (!scratch) return fail(HARTREE_ERR_ARG, "scratch is NULL");
+    if (!grid) return fail(HARTREE_ERR_ARG, "the scratch grid is NULL");
     if (reps < 1 || reps > 1000) return fail(HARTREE_ERR_ARG, "reps must be in [1, 1000]");
     if (plan->capturing || plan->prof) return fail(HARTREE_ERR_ARG, "cannot tune during capture or profiling");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1266,9 +1271,9 @@ hartree_status hartree_plan_tune(hartree_plan plan, void *scratch, int32_t reps,
                         trial[3 * (3 * q + x) + 2] = c.pad;
                     }
                 if (apply_config(plan, trial.data()) != HARTREE_OK) continue;
-                hipError_t e = run_axis(plan, x, scratch, s);  // warm-up (and attribute opt-in)
+                hipError_t e = run_axis(plan, x, grid, s);  // warm-up (and attribute opt-in)
                 if (e == hipSuccess) e = hipEventRecord(ev[0], s);
-                for (int i = 0; i < reps && e == hipSuccess; ++i) e = run_axis(plan, x, scratch, s);
+                for (int i = 0; i < reps && e == hipSuccess; ++i) e = run_axis(plan, x, grid, s);
                 if (e == hipSuccess) e = hipEventRecord(ev[1], s);
                 if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
                 float ms = 0.0f;
@@ -1291,6 +1296,148 @@ hartree_status hartree_plan_tune(hartree_plan plan, void *scratch, int32_t reps,
     hartree_status st2 = apply_config(plan, cfg.data());
     if (result != HARTREE_OK) return result;
     return st2 == HARTREE_OK ? ok() : st2;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------ no-allocation solve
+// The device scratch of hartree_solve_noalloc: one copy of this array per GPU
+// (created with the code object, held until the process ends), laid out like
+// the first part of a plan's workspace (status word, zero block, problem
+// descriptors, twiddles, half spectrum, E_H partials).  Host code never uses
+// the array's name as an address: each GPU's copy is found with
+// hipGetSymbolAddress (noalloc_scratch below), and only that pointer is
+// passed to kernels.
+static __device__ __align__(256) unsigned char scratch[HARTREE_NOALLOC_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of the current device's scratch, looked up once per device
+hipError_t noalloc_scratch(unsigned char **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr || reinterpret_cast<uintptr_t>(ptr) % 256 != 0) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = static_cast<unsigned char *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+// cos and sin of 2 pi t / n, the angle reduced to the first octant in
+// integer arithmetic as on the host (FP64 device cos / sin)
+__device__ void unit_root_dev(int t, int n, double &c, double &s)
+{
+    const int u = 4 * t;  // t < n <= 4096
+    const int q = u / n;
+    int r = u - q * n;
+    bool swap = false;
+    if (2 * r > n) {
+        r = n - r;
+        swap = true;
+    }
+    const double th = 1.5707963267948966192313216916397514 * double(r) / double(n);
+    double cc = cos(th), ss = sin(th);
+    if (swap) {
+        const double tmp = cc;
+        cc = ss;
+        ss = tmp;
+    }
+    switch (q) {
+    case 0: c = cc; s = ss; break;
+    case 1: c = -ss; s = cc; break;
+    case 2: c = -cc; s = -ss; break;
+    default: c = ss; s = -cc; break;
+    }
+}
+
+// One problem's descriptor (thread 0 of block 0) and the twiddle tables of its
+// three axes, W_n^t = exp(-2 pi i t / n) in the plan's precision, into the
+// scratch.  Problems sharing a length write the same values to the same table.
+template <typename T>
+__global__ __launch_bounds__(256) void k_noalloc_setup(ProbDesc d, ProbDesc *desc_out, Cx<T> *tw)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) *desc_out = d;
+    for (int x = 0; x < 3; ++x) {
+        const int n = d.ax[x].n;
+        if (t < n) {
+            double c, s;
+            unit_root_dev(t, n, c, s);
+            tw[d.ax[x].tw_off + t] = Cx<T>{T(c), T(-s)};
+        }
+    }
+}
+
+// the launch groups of one pass, in order on one stream
+hipError_t run_group_serial(hartree_plan p, const std::vector<Launch> &groups, PassKind kind, PassArgs a,
+                            hipStream_t s)
+{
+    for (const Launch &l : groups) {
+        a.tl = l.tl;
+        hipError_t e = run_pass(p->fp64, kind, l.plan, l.p_log2, l.pad, l.maxn, l.tl.total, s, a);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+hartree_status hartree_solve_noalloc(hartree_plan plan, const void *rho, void *v, double *e_h, void *stream)
+{
+    if (!plan) return fail(HARTREE_ERR_ARG, "plan is NULL");
+    if (!rho || !v) return fail(HARTREE_ERR_ARG, "rho or v is NULL");
+    if (rho == v) return fail(HARTREE_ERR_ARG, "v may not alias rho");
+    // the workspace up to the E_H partials: what the solve uses
+    const size_t need = plan->o_qsum;
+    if (need > size_t(HARTREE_NOALLOC_BYTES))
+        return fail(HARTREE_ERR_WORKSPACE,
+                    "the plan needs %zu bytes of scratch; hartree_solve_noalloc holds %zu (HARTREE_NOALLOC_BYTES): "
+                    "use hartree_solve with a bound workspace",
+                    need, size_t(HARTREE_NOALLOC_BYTES));
+    unsigned char *ws = nullptr;
+    hipError_t e = noalloc_scratch(&ws);
+    if (e != hipSuccess) return hip_fail(e, "locating the device scratch");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int maxn = 1;
+    for (const ProbDesc &d : plan->desc)
+        for (int x = 0; x < 3; ++x) maxn = std::max(maxn, d.ax[x].n);
+    const int blocks = (maxn + 255) / 256;
+    for (int q = 0; q < plan->nprob; ++q) {
+        ProbDesc *dst = reinterpret_cast<ProbDesc *>(ws + plan->o_desc) + q;
+        if (plan->fp64)
+            hipLaunchKernelGGL(k_noalloc_setup<double>, dim3(blocks), dim3(256), 0, s, plan->desc[q], dst,
+                               reinterpret_cast<Cx<double> *>(ws + plan->o_tw));
+        else
+            hipLaunchKernelGGL(k_noalloc_setup<float>, dim3(blocks), dim3(256), 0, s, plan->desc[q], dst,
+                               reinterpret_cast<Cx<float> *>(ws + plan->o_tw));
+        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "writing the plan into the device scratch");
+    }
+    PassArgs a = base_args_at(plan, ws);
+    a.in = rho;
+    a.out = v;
+    if ((e = run_group_serial(plan, plan->lr2c, PASS_R2C_FWD, a, s)) != hipSuccess) return hip_fail(e, "P1");
+    if ((e = run_group_serial(plan, plan->lb, PASS_B_FWD, a, s)) != hipSuccess) return hip_fail(e, "P2");
+    if ((e = run_group_serial(plan, plan->la, e_h ? PASS_A_FULL : PASS_A_NOENERGY, a, s)) != hipSuccess)
+        return hip_fail(e, "P3");
+    if (e_h && (e = run_finalize(a.desc, a.partials, e_h, plan->nprob, s)) != hipSuccess)
+        return hip_fail(e, "E_H finalize");
+    if ((e = run_group_serial(plan, plan->lb, PASS_B_INV, a, s)) != hipSuccess) return hip_fail(e, "P4");
+    if ((e = run_group_serial(plan, plan->lr2c, PASS_C2R, a, s)) != hipSuccess) return hip_fail(e, "P5");
+    return ok();
 }
 
 hartree_status hartree_atom_partition(int32_t natoms, const double *pos, const double *weights, int32_t nparts,

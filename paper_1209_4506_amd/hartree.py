@@ -78,6 +78,7 @@ def _load():
         "hartree_plan_tune": [vp, vp, i32, vp],
         "hartree_atom_partition": [i32, P(d), P(d), i32, P(i32), P(i32), P(i32)],
         "hartree_atoms_pairs": [vp, P(i64), vp],
+        "hartree_solve_noalloc": [vp, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -99,7 +100,10 @@ EXPORTED = ["hartree_plan_create", "hartree_plan_create_batched", "hartree_plan_
             "hartree_device_status", "hartree_atoms_bind", "hartree_splat_bound", "hartree_splat_adjoint_bound",
             "hartree_profile_begin", "hartree_profile_end", "hartree_graph_begin", "hartree_graph_end",
             "hartree_graph_launch", "hartree_plan_get_config", "hartree_plan_set_config", "hartree_plan_tune",
-            "hartree_atom_partition", "hartree_atoms_pairs", "hartree_last_error"]
+            "hartree_atom_partition", "hartree_atoms_pairs", "hartree_solve_noalloc", "hartree_last_error"]
+
+# device scratch of hartree_solve_noalloc (HARTREE_NOALLOC_BYTES)
+NOALLOC_BYTES = 64 * 1024 * 1024
 
 # hartree_kernel_id order
 KERNELS = ["r2c", "r2c_bwd", "fft_b", "fft_a", "fft_a_bwd", "fft_a_eonly", "fft_b_inv", "c2r", "finalize",
@@ -256,6 +260,15 @@ class Plan:
         v = self.empty_grid() if v is None else self._grid(v, "v")
         e_h = torch.empty(self.nprob, dtype=torch.float64, device=self.device) if e_h is None else e_h
         _check(LIB.hartree_solve(self._h, _ptr(rho), _ptr(v), _ptr(e_h), stream or _stream(self.device)))
+        return v, e_h
+
+    def solve_noalloc(self, rho, v, e_h=None, stream=None):
+        """hartree_solve_noalloc: V (and E_H into ``e_h`` if given) with the
+        library's own device scratch; the plan needs no workspace.  ``v`` and
+        ``e_h`` are preallocated by the caller."""
+        self._grid(rho, "rho")
+        self._grid(v, "v")
+        _check(LIB.hartree_solve_noalloc(self._h, _ptr(rho), _ptr(v), _ptr(e_h), stream or _stream(self.device)))
         return v, e_h
 
     def potential(self, rho, v=None, stream=None):

@@ -76,6 +76,25 @@ def test_plan_validation(lib):
     lib.hartree_plan_destroy(h)
 
 
+def test_noalloc_size_limit(lib):
+    """hartree_solve_noalloc refuses a plan larger than its device scratch
+    (HARTREE_NOALLOC_BYTES) with HARTREE_ERR_WORKSPACE before any device call;
+    argument errors come first."""
+    vp = ctypes.c_void_p
+    lib.hartree_solve_noalloc.argtypes = [vp, vp, vp, vp, vp]
+    lib.hartree_last_error.restype = ctypes.c_char_p
+    rc, h = _create(lib, np.eye(3) * 20.0, (256, 256, 256))
+    assert rc == 0
+    assert lib.hartree_solve_noalloc(h, vp(16), vp(32), None, None) == 5
+    msg = lib.hartree_last_error()
+    assert b"HARTREE_NOALLOC_BYTES" in msg and b"67108864" in msg
+    assert lib.hartree_solve_noalloc(h, None, vp(32), None, None) == 1
+    assert lib.hartree_solve_noalloc(h, vp(16), vp(16), None, None) == 1
+    assert lib.hartree_solve_noalloc(None, vp(16), vp(32), None, None) == 1
+    lib.hartree_plan_destroy.argtypes = [vp]
+    lib.hartree_plan_destroy(h)
+
+
 def test_batched_plan_offsets(lib):
     from paper_1209_4506_amd import inputs
 
