@@ -277,6 +277,24 @@ int oracle_kernel(const double cell[9], const int dims[3], double *K)
     return 0;
 }
 
+/* Compensated (Kahan-Babuska / Neumaier) summation: s carries the running
+ * sum, c the rounding error lost from it, so that the energies of 10^9-point
+ * grids keep their value to a few units of the last place instead of the
+ * ~sqrt(n) ulps a plain running sum loses. */
+typedef struct {
+    double s, c;
+} csum_t;
+
+static void csum_add(csum_t *a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x))
+        a->c += (a->s - t) + x;
+    else
+        a->c += (x - t) + a->s;
+    a->s = t;
+}
+
 /* out = P in, with P = F^{-1} K F on real grids.  Also returns, when the
  * pointers are non-null, sum_m K |F in|^2 and the largest |Im| seen in the
  * inverse transform (exactly zero in exact arithmetic). */
@@ -291,18 +309,27 @@ static int apply_P(const double cell[9], const int dims[3], const double *in, do
     fft_axis(a, dims, 2, -1);
     fft_axis(a, dims, 1, -1);
     fft_axis(a, dims, 0, -1);
-    double acc = 0.0;
-    #pragma omp parallel for schedule(static) reduction(+ : acc)
-    for (int i = 0; i < dims[0]; ++i)
+    /* sum_m K |X|^2: one compensated sum per a-plane, then over the planes in
+     * order (the same value for any thread count) */
+    double *plane = (double *)calloc((size_t)dims[0], sizeof(double));
+    #pragma omp parallel for schedule(static)
+    for (int i = 0; i < dims[0]; ++i) {
+        csum_t ps = {0.0, 0.0};
         for (int j = 0; j < dims[1]; ++j)
             for (int k = 0; k < dims[2]; ++k) {
                 int m[3] = {i, j, k};
                 size_t idx = ((size_t)i * dims[1] + j) * dims[2] + k;
                 double K = kernel_at(B, dims, m);
                 double re = creal(a[idx]), im = cimag(a[idx]);
-                acc += K * (re * re + im * im);
+                csum_add(&ps, K * (re * re + im * im));
                 a[idx] *= K;
             }
+        plane[i] = ps.s + ps.c;
+    }
+    csum_t tot = {0.0, 0.0};
+    for (int i = 0; i < dims[0]; ++i) csum_add(&tot, plane[i]);
+    free(plane);
+    double acc = tot.s + tot.c;
     fft_axis(a, dims, 0, +1);
     fft_axis(a, dims, 1, +1);
     fft_axis(a, dims, 2, +1);
@@ -330,10 +357,10 @@ int oracle_poisson(const double cell[9], const int dims[3], const double *rho, d
     if (rc) return rc;
     double n = (double)dims[0] * dims[1] * dims[2];
     double dv = omega / n;
-    double s = 0.0;
+    csum_t cs = {0.0, 0.0};
     size_t nn = (size_t)n;
-    for (size_t i = 0; i < nn; ++i) s += rho[i] * V[i];
-    if (eh_real) *eh_real = 0.5 * dv * s;
+    for (size_t i = 0; i < nn; ++i) csum_add(&cs, rho[i] * V[i]);
+    if (eh_real) *eh_real = 0.5 * dv * (cs.s + cs.c);
     if (eh_recip) *eh_recip = omega / (2.0 * n * n) * kx2;
     if (max_imag) *max_imag = mi;
     return 0;
