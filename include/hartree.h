@@ -73,7 +73,8 @@ typedef enum {
 
 /* Optional plan settings; zero fields take the defaults in brackets. */
 typedef struct {
-    double cutoff_sigmas; /* Gaussian truncation radius in units of sigma [8 for FP64, 6 for FP32] */
+    double cutoff_sigmas; /* Gaussian truncation radius in units of sigma [FP32: 6; FP64: 8 when every
+                             cell is diagonal (per-axis box), 9 otherwise (sphere)] */
     double max_sigma;     /* largest sigma the splat workspace is sized for, Bohr [1.0] */
     int32_t max_atoms;    /* largest atom count per splat call [65536] */
     int32_t reserved[7];  /* must be zero */

@@ -21,7 +21,7 @@ Five named configurations (seed = 1209 + index):
 4. ``cubic1024``     cubic a = 150 Bohr, 1024^3 grid, 32768 uniform atoms.
 
 and, on grids with a factor 7 at the paper's own grid spacing (0.2568 Bohr,
-Sec. 5.2.7: 420 x 420 x 210 points for 16,384 diamond atoms):
+Sec. 5.2.6: 420 x 420 x 210 points for 16,384 diamond atoms):
 
 5. ``diamond16384``  16x16x8 conventional diamond cells (16,384 atoms),
                      107.85 x 107.85 x 53.93 Bohr, 420 x 420 x 210 grid.
@@ -135,8 +135,11 @@ def cubic1024(seed: int = SEED_BASE + 4) -> Problem:
     rng = np.random.default_rng(seed)
     L = 150.0
     n = 32768
-    return Problem("cubic1024", _cubic(L), (1024, 1024, 1024), rng.random((n, 3)) * L,
-                   np.full(n, 4.0), np.full(n, 0.8), seed)
+    p = Problem("cubic1024", _cubic(L), (1024, 1024, 1024), rng.random((n, 3)) * L,
+                np.full(n, 4.0), np.full(n, 0.8), seed)
+    # the 16 atoms whose forces are checked against the oracle adjoint
+    p.extra["fd_atoms"] = np.random.default_rng(seed + 7).choice(n, 16, replace=False)
+    return p
 
 
 CONFIGS = {0: cubic32, 1: diamond180, 2: diamond360, 3: batched24, 4: cubic1024, 5: diamond16384}

@@ -7,9 +7,12 @@ benchmark times (FP32 plan, max_atoms = the atom count).
   oracle solve of the same (upcast) density; Hartree forces against central
   finite differences of FP64 energies on 16 seeded atoms, and against the
   oracle adjoint for those atoms.
-* 1024^3 cubic cell (32768 atoms): the density at sampled points against the
-  oracle; properties that hold at any size (neutrality, the real-space and
-  reciprocal-space E_H agree, FP32 agrees with FP64).
+* 1024^3 cubic cell (32768 atoms): FP32 and FP64 steps; FP32 against FP64
+  element by element (density, V, E_H, every force); the density at sampled
+  points against the oracle; V and E_H of both against the oracle solve of the
+  FP64 density, and the forces of 16 seeded atoms against the oracle adjoint;
+  properties that hold at any size (neutrality, the real-space and
+  reciprocal-space E_H agree, the forces sum to zero).
 * the 24-problem batched workload: every problem against the oracle.
 """
 import numpy as np
@@ -72,7 +75,7 @@ def test_diamond180_against_oracle(H, oracle_mod):
     dv = abs(np.linalg.det(p.cell)) / p.npoints
     sel = np.arange(0, p.natoms, 8)
     F_o = oracle_mod.splat_adjoint(cell9, p.pos, p.Z, p.sigma, dv * V_o, sel=sel)
-    for prec, tv, te, tr, tf in (("fp64", 1e-12, 1e-12, 1e-12, 1e-10), ("fp32", 5e-6, 1e-6, 2e-6, 1e-4)):
+    for prec, tv, te, tr, tf in (("fp64", 1e-12, 1e-12, 1e-13, 1e-10), ("fp32", 5e-6, 1e-6, 1e-6, 1e-5)):
         say("case diamond180", prec)
         _, rho, V, E, F = run_step(H, p, prec)
         er = float(np.abs(rho.double().cpu().numpy() - rho_o).max() / np.abs(rho_o).max())
@@ -101,7 +104,7 @@ def test_diamond360_density_sampled(oracle_mod, diamond360):
     e32 = np.abs(sample(rho32, flat) - ref).max() / scale
     e64 = np.abs(sample(rho64, flat) - ref).max() / scale
     say("  fp32 %.2e  fp64 %.2e" % (e32, e64))
-    assert e32 <= 2e-6 and e64 <= 1e-12
+    assert e32 <= 1e-6 and e64 <= 1e-13
 
 
 def test_diamond360_potential_energy(oracle_mod, diamond360):
@@ -146,8 +149,8 @@ def test_diamond360_forces(H, oracle_mod, diamond360):
     say("  fp64 adjoint vs FD max %.2e Ha/Bohr; fp32 vs fp64 max %.2e" % (np.abs(g64 - fd).max(),
                                                                           np.abs(g32 - g64).max()))
     assert np.abs(g64 - fd).max() <= 1e-5
-    assert np.abs(g32 - g64).max() <= 1e-4
-    assert rel_l2(F32.cpu().numpy(), F64.cpu().numpy()) <= 1e-4
+    assert np.abs(g32 - g64).max() <= 1e-5
+    assert rel_l2(F32.cpu().numpy(), F64.cpu().numpy()) <= 1e-5
     dv = plan64.dv()[0]
     ref = oracle_mod.splat_adjoint(p.cell.reshape(9), p.pos, p.Z, p.sigma, dv * V64.cpu().numpy(), sel=atoms)
     err = np.abs(g64 - ref).max() / np.abs(ref).max()
@@ -155,24 +158,97 @@ def test_diamond360_forces(H, oracle_mod, diamond360):
     assert err <= 1e-10
 
 
-def test_cubic1024_properties(H, oracle_mod):
+@pytest.fixture(scope="module")
+def cubic1024(H):
+    """One FP32 and one FP64 step (splat, solve, backward of E_H, adjoint) of
+    the 1024^3 workload, kept on the GPU for the tests below."""
     p = inputs.cubic1024()
-    say("case cubic1024 fp32")
-    plan, rho, V, E, F = run_step(H, p, "fp32")
-    dv = plan.dv()[0]
+    say("case cubic1024 fp32 and fp64 steps")
+    out32 = run_step(H, p, "fp32")
+    out64 = run_step(H, p, "fp64")
+    yield p, out32, out64
+    del out32, out64
+    torch.cuda.empty_cache()
+
+
+def gpu_rel_l2(a, b):
+    """rel-L2 of a against b, in FP64 on the GPU (no host copies of the grids)."""
+    d = a.double() - b.double()
+    return float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(b.double()))
+
+
+def test_cubic1024_fp32_vs_fp64(cubic1024):
+    """FP32 end to end against FP64 end to end, element by element: the FP64
+    path is pinned to the oracle at 1e-12 (below, and on every other size)."""
+    p, (_, rho32, V32, E32, F32), (_, rho64, V64, E64, F64) = cubic1024
+    say("case cubic1024 fp32 vs fp64")
+    er = float(torch.max(torch.abs(rho32.double() - rho64)) / torch.max(torch.abs(rho64)))
+    ev = gpu_rel_l2(V32, V64)
+    ee = abs(float(E32[0]) - float(E64[0])) / float(E64[0])
+    ef = float(torch.max(torch.abs(F32 - F64)) / torch.max(torch.abs(F64)))
+    say("  rho max-rel %.2e  V rel-L2 %.2e  E_H rel %.2e  forces max-rel %.2e" % (er, ev, ee, ef))
+    assert er <= 1e-6 and ev <= 5e-6 and ee <= 1e-6 and ef <= 1e-5
+
+
+def test_cubic1024_density_sampled(oracle_mod, cubic1024):
+    p, (_, rho32, *_), (_, rho64, *_) = cubic1024
+    say("case cubic1024 sampled density")
     flat = np.random.default_rng(6).choice(p.npoints, 64, replace=False)
     ref = oracle_mod.splat_points(p.cell.reshape(9), p.dims, p.pos, p.Z, p.sigma, flat)
-    scale = float(torch.max(torch.abs(rho)).item())
-    er = np.abs(sample(rho, flat) - ref).max() / scale
+    scale = float(torch.max(torch.abs(rho64)).item())
+    e32 = np.abs(sample(rho32, flat) - ref).max() / scale
+    e64 = np.abs(sample(rho64, flat) - ref).max() / scale
+    say("  fp32 %.2e  fp64 %.2e" % (e32, e64))
+    assert e32 <= 1e-6 and e64 <= 1e-13
+
+
+def test_cubic1024_properties(cubic1024):
+    """Properties that hold at any size: neutrality, the real-space and
+    reciprocal-space forms of E_H agree, the forces sum to zero (up to the
+    grid's aliasing)."""
+    p, (plan, rho, V, E, F), _ = cubic1024
+    say("case cubic1024 properties (fp32)")
+    dv = plan.dv()[0]
     neutral = abs(float(rho.double().sum()) * dv) / float(np.sum(p.Z))
     e_real = 0.5 * dv * float((rho.double() * V.double()).sum())
     ep = abs(e_real - float(E[0])) / float(E[0])
     fsum = float(np.abs(F.cpu().numpy().sum(0)).max() / np.abs(F.cpu().numpy()).max())
-    say("  rho sampled %.2e  neutrality %.2e  E_H real vs reciprocal %.2e  sum of forces %.2e" % (er, neutral, ep,
-                                                                                                  fsum))
-    assert er <= 2e-6 and neutral <= 1e-5 and ep <= 1e-5 and fsum <= 2e-3
-    del plan, rho, V, F
-    torch.cuda.empty_cache()
+    say("  neutrality %.2e  E_H real vs reciprocal %.2e  sum of forces %.2e" % (neutral, ep, fsum))
+    assert neutral <= 1e-5 and ep <= 1e-5 and fsum <= 2e-3
+
+
+@pytest.mark.timeout(900)
+def test_cubic1024_against_oracle(oracle_mod, cubic1024):
+    """V and E_H of both paths against the oracle solve of the FP64 density
+    (1024^3 in FP64 on the host: about 35 GB and a minute or two of the host's
+    cores), and the forces of 16 seeded atoms against the oracle adjoint of
+    the oracle potential."""
+    import psutil
+
+    if psutil.virtual_memory().available < 48 * 2**30:
+        pytest.skip("the 1024^3 oracle solve needs about 35 GB of free host memory")
+    p, (_, rho32, V32, E32, F32), (plan64, rho64, V64, E64, F64) = cubic1024
+    say("case cubic1024 oracle solve of the fp64 density")
+    cell9 = p.cell.reshape(9)
+    V_o, _, eg, _ = oracle_mod.poisson(cell9, rho64.cpu().numpy())
+    Vd = torch.from_numpy(V_o).to("cuda")
+    ev64 = gpu_rel_l2(V64, Vd)
+    ev32 = gpu_rel_l2(V32, Vd)
+    ee64 = abs(float(E64[0]) - eg) / eg
+    ee32 = abs(float(E32[0]) - eg) / eg
+    del Vd
+    atoms = p.extra["fd_atoms"]
+    dv = plan64.dv()[0]
+    V_o *= dv
+    F_o = oracle_mod.splat_adjoint(cell9, p.pos, p.Z, p.sigma, V_o, sel=atoms)
+    del V_o
+    fs = np.abs(F_o).max()
+    ef64 = np.abs(F64.cpu().numpy()[atoms] - F_o).max() / fs
+    ef32 = np.abs(F32.cpu().numpy()[atoms] - F_o).max() / fs
+    say("  fp64: V %.2e  E_H %.2e  forces %.2e" % (ev64, ee64, ef64))
+    say("  fp32: V %.2e  E_H %.2e  forces %.2e" % (ev32, ee32, ef32))
+    assert ev64 <= 1e-12 and ee64 <= 1e-12 and ef64 <= 1e-10
+    assert ev32 <= 5e-6 and ee32 <= 1e-6 and ef32 <= 1e-5
 
 
 def test_diamond16384_radix7(H, oracle_mod):
@@ -196,7 +272,7 @@ def test_diamond16384_radix7(H, oracle_mod):
     F_o = oracle_mod.splat_adjoint(cell9, p.pos, p.Z, p.sigma, dv * V_o, sel=atoms)
     ef = np.abs(F.cpu().numpy()[atoms] - F_o).max() / np.abs(F_o).max()
     say("  rho sampled %.2e  V %.2e  E_H %.2e  forces %.2e" % (er, ev, ee, ef))
-    assert er <= 2e-6 and ev <= 5e-6 and ee <= 1e-6 and ef <= 1e-4
+    assert er <= 1e-6 and ev <= 5e-6 and ee <= 1e-6 and ef <= 1e-5
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
@@ -216,7 +292,7 @@ def test_diamond_fcc_general_cell(H, oracle_mod, prec):
     ee = abs(float(E[0]) - E_o) / E_o
     ef = float(np.abs(F.cpu().numpy()[atoms] - F_o).max() / np.abs(F_o).max())
     say("  rho %.2e  V %.2e  E_H %.2e  forces %.2e" % (er, ev, ee, ef))
-    tol = dict(fp64=(1e-12, 1e-12, 1e-12, 1e-10), fp32=(2e-6, 5e-6, 1e-6, 1e-4))[prec]
+    tol = dict(fp64=(1e-13, 1e-12, 1e-12, 1e-10), fp32=(1e-6, 5e-6, 1e-6, 1e-5))[prec]
     assert er <= tol[0] and ev <= tol[1] and ee <= tol[2] and ef <= tol[3]
 
 
@@ -252,5 +328,5 @@ def test_batched24_against_oracle(H, oracle_mod):
         ef = np.abs(F_h[a0:a0 + q.natoms] - F_o).max() / np.abs(F_o).max()
         say("  problem %2d dims %s atoms %3d: rho %.1e V %.1e E_H %.1e forces %.1e" % (i, q.dims, q.natoms, er, ev,
                                                                                         ee, ef))
-        assert er <= 2e-6 and ev <= 5e-6 and ee <= 1e-6 and ef <= 1e-4
+        assert er <= 1e-6 and ev <= 5e-6 and ee <= 1e-6 and ef <= 1e-5
         a0 += q.natoms

@@ -1,9 +1,11 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle.
 
 Every test prints the case it is about to run before touching the GPU.
-Tolerances: FP64 V rel-L2 <= 1e-12, E_H rel <= 1e-12; FP32 V rel-L2 <= 5e-6,
-E_H rel <= 1e-6.  The FP32 inputs are rounded to float first and the oracle
-is fed the same rounded values.
+Tolerances: FP64 V rel-L2 <= 1e-12, E_H rel <= 1e-12, density max-rel <= 1e-13
+(of the largest value), forces max-rel <= 1e-10; FP32 V rel-L2 <= 5e-6, E_H
+rel <= 1e-6, density max-rel <= 1e-6, forces max-rel <= 1e-5.  The FP32
+inputs are rounded to float first and the oracle is fed the same rounded
+values.
 """
 import itertools
 
@@ -129,7 +131,7 @@ def test_splat_parity(H, oracle_mod, prec, case):
     e1 = np.abs(rho - ref).max() / scale
     e2 = np.abs(rho_nb - ref_nb).max() / scale
     say("  rho max-rel %.3e (background) %.3e (none)" % (e1, e2))
-    tol = 1e-12 if prec == "fp64" else 2e-6
+    tol = 1e-13 if prec == "fp64" else 1e-6
     assert e1 <= tol and e2 <= tol
 
 
@@ -174,7 +176,7 @@ def test_many_atoms_one_problem(H, oracle_mod, prec):
     got = rho.reshape(-1)[torch.tensor(flat, device="cuda")].double().cpu().numpy()
     err = np.abs(got - ref).max() / float(torch.max(torch.abs(rho)).item())
     say("  sampled density max-rel %.3e" % err)
-    assert err <= (1e-12 if prec == "fp64" else 2e-6)
+    assert err <= (1e-13 if prec == "fp64" else 1e-6)
     # a smooth field for the adjoint
     ix = [np.arange(n) / n for n in p.dims]
     g = (np.cos(2 * np.pi * ix[0])[:, None, None] + 0.5 * np.sin(4 * np.pi * ix[1])[None, :, None]
@@ -213,7 +215,7 @@ def test_end_to_end_cubic32(H, oracle_mod, prec):
     ef = np.abs(pos.grad.cpu().numpy() - gp_o).max() / np.abs(gp_o).max()
     say("  V %.3e  E_H %.3e  grad %.3e" % (ev, ee, ef))
     assert ev <= TOL[prec]["v"] and ee <= TOL[prec]["e"]
-    assert ef <= (1e-10 if prec == "fp64" else 1e-4)
+    assert ef <= (1e-10 if prec == "fp64" else 1e-5)
 
 
 def test_bitwise_reproducible(H):
@@ -262,7 +264,7 @@ def test_atom_order_equivariance(H, prec, mode):
     er = np.abs(rho1 - rho0).max() / np.abs(rho0).max()
     ef = np.abs(back - f0).max() / np.abs(f0).max()
     say("  rho max-rel %.3e  grad max-rel %.3e" % (er, ef))
-    assert er <= (1e-13 if prec == "fp64" else 2e-6)
+    assert er <= (1e-13 if prec == "fp64" else 1e-6)
     assert ef <= (1e-11 if prec == "fp64" else 1e-5)
 
 
@@ -291,7 +293,7 @@ def test_workspace_contents_do_not_matter(H, oracle_mod, prec, fill):
         assert plan.device_status() == 0
         outs.append([rho.cpu(), V.cpu(), E.cpu(), f.cpu()])
         ref = oracle_splat_cache(oracle_mod, p)
-        assert np.abs(rho.double().cpu().numpy() - ref).max() / np.abs(ref).max() <= (1e-12 if prec == "fp64" else 2e-6)
+        assert np.abs(rho.double().cpu().numpy() - ref).max() / np.abs(ref).max() <= (1e-13 if prec == "fp64" else 1e-6)
     key = (prec,)
     if key in _WS_REF:
         for a, b in zip(sum(_WS_REF[key], []), sum(outs, [])):
@@ -380,7 +382,7 @@ def test_periodic_images_of_atoms(H, prec, case):
     er = np.abs(r1 - r0).max() / np.abs(r0).max()
     ef = np.abs(f1 - f0).max() / np.abs(f0).max()
     say("  rho max-rel %.3e  grad max-rel %.3e" % (er, ef))
-    assert er <= (1e-12 if prec == "fp64" else 2e-6)
+    assert er <= (1e-13 if prec == "fp64" else 1e-6)
     assert ef <= (1e-10 if prec == "fp64" else 1e-5)
 
 
