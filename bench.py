@@ -3,24 +3,28 @@
 
 One step (one "solve") is the whole hot path on one batch of synthetic input:
   bin        atoms into bricks (once, shared by splat and adjoint)
-  splat      rho = sum of 4096 Gaussians (Z = 4, sigma = 0.8 Bohr) - Q/Omega
+  splat      rho = sum of the Gaussians - Q/Omega
   solve      V = P rho, E_H                         (P1 .. P5 + E_H finalize)
   backward   grad_rho = P (c dV + 1 * dV * rho)     (loss L = E_H + <c, V> dV)
   adjoint    dL/dR for every atom
 All inputs are resident in HBM before the timed region starts.
 
-Prints one JSON line.  `value` is the rate of K steps replayed as one
-captured HIP graph each (the replayed outputs are checked bit for bit against
-an eager step); `eager` is the rate of the same K steps launched kernel by
-kernel with every kernel group bracketed by HIP events, which give the
-per-kernel timings and the roofline of the dominant kernel.  Also: the same
-step with an FP64 plan, eager (the "plain FP64" comparison), and the CPU
-oracle timed on a bounded sample of the same workload.  --eager skips the
-graph region and reports the eager rate as `value`.
+Prints one JSON line.  `value` is the rate of K steps of the 360^3 workload
+replayed as one captured HIP graph each (the replayed outputs are checked bit
+for bit against an eager step).  Beside it, per workload:
+  eager       the same K steps launched kernel by kernel, every kernel group
+              bracketed by HIP events (per-kernel times, the rooflines);
+  replay_ms   min / median / mean of single replays, each timed with HIP
+              events, over at least one second of replays;
+  fp64_plain  the same step with an FP64 plan, eager (the comparison point);
+and the same record for the 24-problem batched workload and the 1024^3
+workload under `workloads`.  The CPU oracle is timed on a bounded sample of
+the 360^3 workload.  --eager reports the eager rate as `value`.
 """
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -33,6 +37,7 @@ PEAK_MFMA_F32_TFLOPS = 157.3  # MI355X dense FP32 matrix-core peak
 PEAK_MFMA_F16_TFLOPS = 2500.0  # MI355X dense FP16 matrix-core peak
 BRICK_POINTS_F32 = 16 * 16 * 32  # points of one FP32 splat brick
 METRIC = "Hartree solves/sec & HBM GB/s, 360^3 FP32 fwd+bwd vs FP64 plain"
+WORKLOADS = ("diamond360", "batched24", "cubic1024")
 
 
 def parse():
@@ -44,15 +49,16 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default pass shapes (skip hartree_plan_tune)")
     ap.add_argument("--tune-cache", default=None,
-                    help="JSON file of tuned pass shapes: applied when it holds this plan, else written after tuning")
+                    help="JSON file of tuned pass shapes: applied when it holds a plan, else written after tuning")
     ap.add_argument("--eager", action="store_true",
                     help="time eager launches only (no HIP graph replay region; value is then the eager rate)")
     ap.add_argument("--cpu-atoms", type=int, default=4096, help="atoms in the CPU-oracle sample (all of them by default)")
-    ap.add_argument("--workload", choices=("diamond360", "batched24"), default="diamond360",
-                    help="the headline 360^3 problem, or 24 uneven orthorhombic problems in one batched plan "
-                         "(solves/s then counts problems)")
+    ap.add_argument("--workload", choices=WORKLOADS, default="diamond360",
+                    help="the workload `value` is quoted on (the headline is diamond360)")
+    ap.add_argument("--only", action="store_true",
+                    help="run the --workload alone (no other workloads: for profiler runs)")
     ap.add_argument("--atom-order", choices=("given", "shuffled", "bisection"), default="given",
-                    help="atom order handed to the library: as generated (lattice order), a random "
+                    help="atom order handed to the library (diamond360): as generated (lattice order), a random "
                          "permutation, or the recursive-bisection order of hartree_atom_partition")
     ap.add_argument("--atom-parts", type=int, default=64, help="parts of the bisection order")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
@@ -122,9 +128,16 @@ class Step:
         self.pos = torch.tensor(np.concatenate([q.pos for q in probs]), device=dev)
         self.Z = torch.tensor(np.concatenate([q.Z for q in probs]), device=dev)
         self.sig = torch.tensor(np.concatenate([q.sigma for q in probs]), device=dev)
+        # the loss weights c ~ N(0, 1) times dV, drawn on the device (a seeded
+        # torch generator: a host draw of a 1024^3 grid takes tens of seconds)
         dvs = p.dv()
-        c = np.concatenate([inputs.random_grid(q.dims, 1209 + i).reshape(-1) * dvs[i] for i, q in enumerate(probs)])
-        self.gv = torch.tensor(c, device=dev).to(p.dtype).reshape(p.empty_grid().shape).contiguous()
+        self.gv = p.empty_grid()
+        gen = torch.Generator(device=dev)
+        for i, q in enumerate(probs):
+            gen.manual_seed(1209 + i)
+            part = self.gv.reshape(-1)[p.offsets[i]:p.offsets[i + 1]]
+            part.normal_(generator=gen)
+            part.mul_(dvs[i])
         self.ge = torch.ones(len(probs), dtype=torch.float64, device=dev)
         self.rho = p.empty_grid()
         self.V = p.empty_grid()
@@ -161,7 +174,9 @@ class Step:
 
     def timed_graph(self, steps, warmup):
         """The same step captured once as a HIP graph and replayed; the
-        replayed outputs are checked bit for bit against an eager step."""
+        replayed outputs are checked bit for bit against an eager step.
+        Returns (seconds for `steps` replays, bit-identical, per-replay
+        milliseconds from HIP events over at least one second)."""
         torch = self.torch
         self()
         torch.cuda.synchronize()
@@ -179,7 +194,40 @@ class Step:
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         same = all(torch.equal(a, b) for a, b in zip(self.outputs(), ref))
-        return dt, same
+        # single replays bracketed by events on the replay stream (torch's current)
+        n = max(steps, int(math.ceil(1.0 / max(dt / steps, 1e-6))))
+        n = min(n, 20000)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * n)]
+        for i in range(n):
+            ev[2 * i].record()
+            self.plan.replay()
+            ev[2 * i + 1].record()
+        torch.cuda.synchronize()
+        per = sorted(ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(n))
+        stats = {"min": per[0], "median": per[n // 2], "mean": sum(per) / n, "max": per[-1], "replays": n}
+        return dt, same, stats
+
+
+def window_points(probs, cutoff):
+    """The method's splat work: sum over atoms of the product over the three
+    axes of the grid points inside the atom's truncation window (at most the
+    axis length), i.e. the (atom, grid point) pairs of the density sum."""
+    import numpy as np
+
+    total = 0
+    for q in probs:
+        L = np.diag(q.cell)
+        w = np.ones(q.natoms)
+        for x in range(3):
+            n = q.dims[x]
+            h = L[x] / n
+            X = np.mod(q.pos[:, x], L[x])
+            rc = cutoff * q.sigma
+            lo = np.ceil((X - rc) / h)
+            hi = np.floor((X + rc) / h)
+            w *= np.minimum(hi - lo + 1, n)
+        total += int(w.sum())
+    return total
 
 
 def kernel_bytes(name, probs, s):
@@ -207,54 +255,50 @@ def kernel_bytes(name, probs, s):
     return total
 
 
-def kernel_flops(name, pairs):
-    """Algorithmic matrix-core flops of one launch of the splat or adjoint:
-    per (atom, brick) pair one multiply-add per brick point (splat: the
-    density; adjoint: two, the factor and its displacement-weighted form)."""
-    per = {"splat": 2, "adjoint": 4}.get(name)
-    return None if per is None else per * BRICK_POINTS_F32 * pairs
+# The splat and adjoint count the method's own work: per (atom, window
+# point) one multiply-add for the density (2 flops) and two for the adjoint
+# (the factor and its displacement-weighted form, 4 flops).  The kernels
+# execute more: whole 16 x 16 x 32 bricks per (atom, brick) pair, the adjoint
+# as three 16-bit split products per FP32 product.
+FLOPS_PER_POINT = {"splat": 2, "adjoint": 4}
+EXEC_MULT = {"splat": 1, "adjoint": 3}
 
 
-# the adjoint forms each FP32 product from three 16-bit products of split
-# operands: its matrix cores execute three times the algorithmic flops, at
-# the FP16 peak
-MFMA_EXEC = {"splat": (1, PEAK_MFMA_F32_TFLOPS), "adjoint": (3, PEAK_MFMA_F16_TFLOPS)}
-
-
-def roofline_of(name, probs, s, pairs, avg_ms, precision="fp32"):
+def roofline_of(name, probs, s, wpoints, pairs, avg_ms, traffic_file=None):
     """Roofline entry of one kernel group from its average launch time: the
-    matrix-core kernels (splat, adjoint) against the FP32 MFMA peak, the
-    grid passes against HBM."""
-    fl = kernel_flops(name, pairs)
+    splat and adjoint against the FP32 matrix-core peak (method flops), the
+    grid passes against HBM (algorithmic bytes)."""
     by = kernel_bytes(name, probs, s)
-    if fl is not None:
-        mult, peak = MFMA_EXEC[name]
-        alg = fl / (avg_ms * 1e-3) / 1e12
-        ach = mult * alg
-        return {"bound": "mfma", "kernel": name, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": traffic_for(name, precision),
-                "flops_per_launch": mult * fl, "algorithmic_flops_per_launch": fl,
-                "fp32_equivalent_tflops": alg, "fp32_equivalent_frac": alg / PEAK_MFMA_F32_TFLOPS,
-                "atom_brick_pairs": pairs, "bytes_per_launch": by,
-                "hbm_gbs": by / (avg_ms * 1e-3) / 1e9, "avg_launch_us": 1000.0 * avg_ms}
+    if name in FLOPS_PER_POINT:
+        fl = FLOPS_PER_POINT[name] * wpoints
+        ach = fl / (avg_ms * 1e-3) / 1e12
+        dense = FLOPS_PER_POINT[name] * BRICK_POINTS_F32 * pairs
+        return {"bound": "mfma", "kernel": name, "achieved": ach, "peak": PEAK_MFMA_F32_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_MFMA_F32_TFLOPS, "traffic": traffic_for(traffic_file, name),
+                "method_flops_per_launch": fl, "window_points": wpoints,
+                "brick_dense_flops_per_launch": dense, "atom_brick_pairs": pairs,
+                "executed_mfma_flops_per_launch": EXEC_MULT[name] * dense,
+                "bytes_per_launch": by, "hbm_gbs": by / (avg_ms * 1e-3) / 1e9, "avg_launch_us": 1000.0 * avg_ms}
     if by is None:
         return None
     ach = by / (avg_ms * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": name, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": ach / PEAK_HBM_GBS, "traffic": traffic_for(name, precision), "bytes_per_launch": by,
+            "frac": ach / PEAK_HBM_GBS, "traffic": traffic_for(traffic_file, name), "bytes_per_launch": by,
             "avg_launch_us": 1000.0 * avg_ms}
 
 
-def traffic_for(kernel, precision):
+def traffic_for(path, kernel):
     """Counter-measured HBM bytes per launch, if taken on the current sources."""
-    f = os.path.join(ROOT, "profiles", "traffic_diamond360.json")
+    if path is None:
+        return None
+    f = os.path.join(ROOT, "profiles", path)
     if not os.path.exists(f):
         return None
     with open(f) as fh:
         t = json.load(fh)
     if t.get("source_hash") != source_hash():
         return None
-    return t.get("kernels", {}).get(precision, {}).get(kernel)
+    return t.get("kernels", {}).get("fp32", {}).get(kernel)
 
 
 def cpu_baseline(prob, natoms_sample, inputs):
@@ -291,6 +335,103 @@ def cpu_baseline(prob, natoms_sample, inputs):
     }
 
 
+def describe(name, probs):
+    if name == "diamond360":
+        return ("diamond360: 8x8x8 diamond supercell, a = 53.93 Bohr, 4096 Gaussian atoms (Z = 4, sigma = 0.8 Bohr, "
+                "N(0, 0.05) displacements, seed 1211), 360^3 grid, FP32 transforms with FP64 E_H and force "
+                "reductions, splat + solve + backward + adjoint per step"), {"grid": list(probs[0].dims),
+                                                                            "atoms": probs[0].natoms}
+    if name == "cubic1024":
+        return ("cubic1024: cubic cell a = 150 Bohr, 32768 uniform Gaussian atoms (Z = 4, sigma = 0.8 Bohr, seed "
+                "1213), 1024^3 grid, FP32 transforms with FP64 E_H and force reductions, splat + solve + backward + "
+                "adjoint per step"), {"grid": list(probs[0].dims), "atoms": probs[0].natoms}
+    return ("batched24: 24 orthorhombic cells (edges U[8, 40] Bohr, each grid dimension from {48, 60, 72, 90, 120, "
+            "150, 180, 240}, 16-512 atoms with Z in {1, 4, 6} and sigma U[0.6, 1.0]) in one batched plan, FP32 "
+            "transforms with FP64 reductions, splat + solve + backward + adjoint of all 24 per step; solves count "
+            "problems"), {"problems": len(probs), "points": int(sum(q.npoints for q in probs)),
+                          "atoms": int(sum(q.natoms for q in probs))}
+
+
+def problems(name, inputs, args, H):
+    if name == "diamond360":
+        prob, part_ms = reorder_atoms(inputs.diamond360(), args.atom_order, args.atom_parts, H)
+        return [prob], part_ms
+    if name == "cubic1024":
+        return [inputs.cubic1024()], None
+    return inputs.batched24(), None
+
+
+def run_workload(name, args, torch, H, inputs, steps, warmup, fp64_steps):
+    """One workload's record: graph-replayed rate, eager per-kernel times and
+    rooflines, single-replay statistics, and the FP64 plain step."""
+    probs, part_ms = problems(name, inputs, args, H)
+    nprob = len(probs)
+    desc, wconf = describe(name, probs)
+    step = Step(probs, "fp32", torch, H, inputs, tune=not args.no_tune, cache=args.tune_cache)
+    assert step.plan.device_status() == 0
+    dt_eager, prof = step.timed(steps, warmup, profile=True)
+    assert step.plan.device_status() == 0, "device status bits set"
+    eager = {"value": nprob * steps / dt_eager, "unit": "solves/s", "ms_per_step": 1000.0 * dt_eager / steps}
+    stats = None
+    if args.eager:
+        dt = dt_eager
+        mode = "eager launches, per-kernel HIP events"
+    else:
+        dt, same, stats = step.timed_graph(steps, warmup)
+        assert same, "graph replay differs from the eager step"
+        assert step.plan.device_status() == 0, "device status bits set"
+        mode = "HIP graph replay of the whole step (outputs bit-identical to the eager step)"
+    ms = 1000.0 * dt / steps
+    s = 4
+    n = sum(q.npoints for q in probs)
+    model_bytes = 23 * s * n
+    pairs = step.plan.atoms_pairs()
+    wpts = window_points(probs, 6.0)
+    tfile = "traffic_%s.json" % name
+    rooflines = {k: roofline_of(k, probs, s, wpts, pairs, v[0] / v[1], tfile) for k, v in prof.items()}
+    rooflines = {k: v for k, v in rooflines.items() if v is not None}
+    dom = max(rooflines, key=lambda k: prof[k][0])
+    per_kernel = {k: {"avg_us": round(1000.0 * v[0] / v[1], 2), "launches": v[1],
+                      "share": round(v[0] / sum(x[0] for x in prof.values()), 4)} for k, v in prof.items()}
+    rec = {
+        "value": nprob * steps / dt,
+        "unit": "solves/s",
+        "ms_per_step": ms,
+        "steps": steps,
+        "timing": mode,
+        "config": dict({"workload": desc}, **wconf, precision="fp32"),
+        "hbm_gbs_model": model_bytes / (ms * 1e-3) / 1e9,
+        "hbm_frac_model": model_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+        "roofline": rooflines[dom],
+        "kernel_rooflines": {k: {"bound": v["bound"], "achieved": round(v["achieved"], 2), "unit": v["unit"],
+                                 "frac": round(v["frac"], 4)} for k, v in rooflines.items()},
+        "kernels": per_kernel,
+        "pass_config": step.config.reshape(-1).tolist() if nprob == 1 else "per problem (see tune cache)",
+        "eager": eager,
+    }
+    if stats is not None:
+        rec["replay_ms"] = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in stats.items()}
+        rec["value_at_median_replay"] = nprob / (stats["median"] * 1e-3)
+    if part_ms is not None:
+        rec["atom_order"] = {"mode": args.atom_order,
+                             "parts": args.atom_parts if args.atom_order == "bisection" else None,
+                             "host_ms": part_ms}
+    del step
+    torch.cuda.empty_cache()
+    if not args.no_fp64:
+        step64 = Step(probs, "fp64", torch, H, inputs, tune=not args.no_tune, cache=args.tune_cache)
+        dt64, prof64 = step64.timed(fp64_steps, 2, profile=True)
+        assert step64.plan.device_status() == 0, "device status bits set"
+        rec["fp64_plain"] = {"value": nprob * fp64_steps / dt64, "unit": "solves/s",
+                             "ms_per_step": 1000.0 * dt64 / fp64_steps, "steps": fp64_steps,
+                             "hbm_gbs_model": 23 * 8 * n / (dt64 / fp64_steps) / 1e9,
+                             "kernels": {k: round(1000.0 * v[0] / v[1], 2) for k, v in prof64.items()}}
+        rec["speedup_vs_fp64_plain"] = rec["value"] / rec["fp64_plain"]["value"]
+        del step64
+        torch.cuda.empty_cache()
+    return rec, probs
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -306,88 +447,39 @@ def main():
     import paper_1209_4506_amd.hartree as H
     from paper_1209_4506_amd import inputs
 
-    if args.workload == "diamond360":
-        prob, part_ms = reorder_atoms(inputs.diamond360(), args.atom_order, args.atom_parts, H)
-        probs = [prob]
-        workload = ("diamond360: 8x8x8 diamond supercell, a = 53.93 Bohr, 4096 Gaussian atoms (Z = 4, sigma = 0.8 "
-                    "Bohr, N(0, 0.05) displacements, seed 1211), 360^3 grid, FP32 transforms with FP64 E_H and "
-                    "force reductions, splat + solve + backward + adjoint per step")
-        wconf = {"grid": list(prob.dims), "atoms": prob.natoms}
-    else:
-        probs, part_ms = inputs.batched24(), None
-        workload = ("batched24: 24 orthorhombic cells (edges U[8, 40] Bohr, each grid dimension from {48, 60, 72, "
-                    "90, 120, 150, 180, 240}, 16-512 atoms with Z in {1, 4, 6} and sigma U[0.6, 1.0]) in one "
-                    "batched plan, FP32 transforms with FP64 reductions, splat + solve + backward + adjoint of all "
-                    "24 per step; solves count problems")
-        wconf = {"problems": len(probs), "points": int(sum(q.npoints for q in probs)),
-                 "atoms": int(sum(q.natoms for q in probs))}
-    nprob = len(probs)
-    step = Step(probs, "fp32", torch, H, inputs, tune=not args.no_tune, cache=args.tune_cache)
-    assert step.plan.device_status() == 0
-    # eager region: every kernel group bracketed by HIP events (the roofline)
-    dt_eager, prof = step.timed(args.steps, args.warmup, profile=True)
-    assert step.plan.device_status() == 0, "device status bits set"
-    eager = {"value": nprob * args.steps / dt_eager, "unit": "solves/s", "ms_per_step": 1000.0 * dt_eager / args.steps}
-    if args.eager:
-        dt = dt_eager
-        mode = "eager launches, per-kernel HIP events"
-    else:
-        # the headline region: the same step replayed as one HIP graph
-        dt, same = step.timed_graph(args.steps, args.warmup)
-        assert same, "graph replay differs from the eager step"
-        assert step.plan.device_status() == 0, "device status bits set"
-        mode = "HIP graph replay of the whole step (outputs bit-identical to the eager step)"
-    ms = 1000.0 * dt / args.steps
-    s = 4
-    n = sum(q.npoints for q in probs)
-    model_bytes = 23 * s * n
-    # dominant kernel group by time
-    groups = {k: v for k, v in prof.items()}
-    pairs = step.plan.atoms_pairs()
-    rooflines = {k: roofline_of(k, probs, s, pairs, v[0] / v[1]) for k, v in groups.items()}
-    rooflines = {k: v for k, v in rooflines.items() if v is not None}
-    dom = max(rooflines, key=lambda k: groups[k][0])
-    per_kernel = {k: {"avg_us": round(1000.0 * v[0] / v[1], 2), "launches": v[1],
-                      "share": round(v[0] / sum(x[0] for x in groups.values()), 4)} for k, v in groups.items()}
+    head, probs = run_workload(args.workload, args, torch, H, inputs, args.steps, args.warmup,
+                               max(3, args.steps // 4))
     out = {
         "metric": METRIC,
-        "value": nprob * args.steps / dt,
+        "value": head["value"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": dict({"workload": workload}, **wconf, precision="fp32"),
-        "hbm_gbs_model": model_bytes / (ms * 1e-3) / 1e9,
-        "roofline": rooflines[dom],
-        "kernel_rooflines": {k: {"bound": v["bound"], "achieved": round(v["achieved"], 2), "unit": v["unit"],
-                                 "frac": round(v["frac"], 4)} for k, v in rooflines.items()},
-        "kernels": per_kernel,
-        "pass_config": step.config.reshape(-1).tolist(),
-        "source_hash": source_hash(),
+        "config": head["config"],
+        "roofline": head["roofline"],
     }
-    out["timing"] = mode
-    out["eager"] = eager
-    if args.atom_order != "given":
-        out["atom_order"] = {"mode": args.atom_order, "parts": args.atom_parts if args.atom_order == "bisection" else None,
-                             "host_ms": part_ms}
-    if not args.no_fp64:
-        del step
-        torch.cuda.empty_cache()
-        step64 = Step(probs, "fp64", torch, H, inputs, tune=not args.no_tune, cache=args.tune_cache)
-        k64 = max(3, args.steps // 4)
-        dt64, prof64 = step64.timed(k64, 2, profile=True)
-        out["fp64_plain"] = {"value": nprob * k64 / dt64, "unit": "solves/s", "ms_per_step": 1000.0 * dt64 / k64,
-                             "steps": k64, "hbm_gbs_model": 23 * 8 * n / (dt64 / k64) / 1e9,
-                             "kernels": {k: round(1000.0 * v[0] / v[1], 2) for k, v in prof64.items()}}
-        out["speedup_vs_fp64_plain"] = out["value"] / out["fp64_plain"]["value"]
-        del step64
-        torch.cuda.empty_cache()
+    for k in ("hbm_gbs_model", "hbm_frac_model", "replay_ms", "value_at_median_replay", "timing", "eager",
+              "kernel_rooflines", "kernels", "pass_config", "fp64_plain", "speedup_vs_fp64_plain", "atom_order"):
+        if k in head:
+            out[k] = head[k]
+    out["source_hash"] = source_hash()
+    if not args.only:
+        others = {}
+        for name in WORKLOADS:
+            if name == args.workload:
+                continue
+            # the 1024^3 step takes tens of milliseconds: fewer steps keep the run short
+            k = args.steps if name != "cubic1024" else max(5, args.steps // 5)
+            rec, _ = run_workload(name, args, torch, H, inputs, k, min(args.warmup, 3), 3)
+            others[name] = rec
+        out["workloads"] = others
     if not args.no_cpu_baseline and args.workload == "diamond360":
         out["cpu_baseline"] = cpu_baseline(probs[0], args.cpu_atoms, inputs)
     line = json.dumps(out)
