@@ -131,15 +131,6 @@ def _opts(cutoff_sigmas=0.0, max_sigma=0.0, max_atoms=0):
     return o
 
 
-def weights_from_times(etime):
-    """Load-balancing weights of Eq. (19): each atom's processing time over the
-    longest one."""
-    t = np.asarray(etime, dtype=np.float64)
-    if t.size == 0:
-        return t.copy()
-    return t / t.max()
-
-
 def atom_partition(pos, nparts, weights=None):
     """hartree_atom_partition on host arrays (Sec. 3.1).
 
