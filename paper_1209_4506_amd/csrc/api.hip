@@ -120,6 +120,7 @@ struct Launch {
     int p_log2;  // pencils per workgroup, log2
     int pad;     // LDS pitch pad of strided tiles
     int maxn;    // longest pencil in the launch (sizes the LDS tile)
+    int64_t col_stride;  // largest pencil stride (elements) of the strided passes
     TileList tl;
 };
 
@@ -225,7 +226,7 @@ bool is_smooth(int n)
     return n == 1;
 }
 
-void add_launch(std::vector<Launch> &v, int plan, int p_log2, int pad, int n, int prob, int tiles)
+void add_launch(std::vector<Launch> &v, int plan, int p_log2, int pad, int n, int64_t col_stride, int prob, int tiles)
 {
     for (auto &l : v) {
         if (l.plan == plan && l.p_log2 == p_log2 && l.pad == pad && l.tl.count < kMaxProb) {
@@ -234,6 +235,7 @@ void add_launch(std::vector<Launch> &v, int plan, int p_log2, int pad, int n, in
             l.tl.count++;
             l.tl.total += tiles;
             if (n > l.maxn) l.maxn = n;
+            if (col_stride > l.col_stride) l.col_stride = col_stride;
             return;
         }
     }
@@ -243,6 +245,7 @@ void add_launch(std::vector<Launch> &v, int plan, int p_log2, int pad, int n, in
     l.p_log2 = p_log2;
     l.pad = pad;
     l.maxn = n;
+    l.col_stride = col_stride;
     l.tl.count = 1;
     l.tl.prob[0] = prob;
     l.tl.start[0] = 0;
@@ -267,9 +270,9 @@ void rebuild_launches(hartree_plan p)
         const int64_t t1 = (rows + 2 * pc - 1) / (2 * pc);
         const int64_t t2 = int64_t(d.dims[0]) * ((d.dims[3] + pb - 1) / pb);
         const int64_t t3 = (int64_t(d.dims[1]) * d.dims[3] + pa - 1) / pa;
-        add_launch(p->lr2c, c[2].plan, c[2].p_log2, c[2].pad, d.dims[2], q, int(t1));
-        add_launch(p->lb, c[1].plan, c[1].p_log2, c[1].pad, d.dims[1], q, int(t2));
-        add_launch(p->la, c[0].plan, c[0].p_log2, c[0].pad, d.dims[0], q, int(t3));
+        add_launch(p->lr2c, c[2].plan, c[2].p_log2, c[2].pad, d.dims[2], 0, q, int(t1));
+        add_launch(p->lb, c[1].plan, c[1].p_log2, c[1].pad, d.dims[1], d.dims[3], q, int(t2));
+        add_launch(p->la, c[0].plan, c[0].p_log2, c[0].pad, d.dims[0], int64_t(d.dims[1]) * d.dims[3], q, int(t3));
         d.part_off = p->nparts;
         d.nparts = int(t3);
         p->nparts += int(t3);
@@ -593,6 +596,7 @@ hipError_t run_group(hartree_plan p, const std::vector<Launch> &groups, PassKind
         if (nside == 0) {
             for (const Launch &l : groups) {
                 a.tl = l.tl;
+                a.col_stride = l.col_stride;
                 hipError_t e = run_pass(p->fp64, kind, l.plan, l.p_log2, l.pad, l.maxn, l.tl.total, s, a);
                 if (e != hipSuccess) return e;
             }
@@ -614,6 +618,7 @@ hipError_t run_group(hartree_plan p, const std::vector<Launch> &groups, PassKind
             const Launch &l = groups[order[i]];
             load[best] += l.tl.total;
             a.tl = l.tl;
+            a.col_stride = l.col_stride;
             e = run_pass(p->fp64, kind, l.plan, l.p_log2, l.pad, l.maxn, l.tl.total, st[best], a);
         }
         // join every side stream that was forked, also after an error, so
@@ -1397,6 +1402,7 @@ hipError_t run_group_serial(hartree_plan p, const std::vector<Launch> &groups, P
 {
     for (const Launch &l : groups) {
         a.tl = l.tl;
+        a.col_stride = l.col_stride;
         hipError_t e = run_pass(p->fp64, kind, l.plan, l.p_log2, l.pad, l.maxn, l.tl.total, s, a);
         if (e != hipSuccess) return e;
     }

@@ -35,9 +35,12 @@ hipError_t run_a_f32(int plan, int maxn, int grid, hipStream_t s, const PassArgs
 {
     const size_t lds = pass_lds_bytes<float>(a, maxn);
     if (plan < 0 || plan >= int(sizeof(kTable) / sizeof(kTable[0]))) return launch_one<0, 0, 0, 0>(grid, lds, s, a);
-    if (a.pad == 0 && a.p_log2 == 2) return kFixed4[plan](grid, lds, s, a);
-    if (a.pad == 0 && a.p_log2 == 3) return kFixed8[plan](grid, lds, s, a);
-    if (a.pad == 0 && a.p_log2 == 4) return kFixed16[plan](grid, lds, s, a);
+    // the compiled tiles address their pencils with 32-bit lane offsets
+    if (a.pad == 0 && lane_offsets_fit<float>(a)) {
+        if (a.p_log2 == 2) return kFixed4[plan](grid, lds, s, a);
+        if (a.p_log2 == 3) return kFixed8[plan](grid, lds, s, a);
+        if (a.p_log2 == 4) return kFixed16[plan](grid, lds, s, a);
+    }
     return kTable[plan](grid, lds, s, a);
 }
 }  // namespace hartree

@@ -252,6 +252,9 @@ struct LdsPencil {
         if (cj) v.y = -v.y;
         buf[i * pp + p] = v;
     }
+    // element u + t, u uniform across the wavefront (see GlobalPencil)
+    __device__ __forceinline__ Cx<T> load_at(int u, int t) const { return load(u + t); }
+    __device__ __forceinline__ void store_at(int u, int t, Cx<T> v) const { store(u + t, v); }
 };
 
 // element i of the thread's pencil in a pencil-major LDS tile
@@ -273,29 +276,46 @@ struct LdsRow {
         if (cj) v.y = -v.y;
         buf[p * ldp + i] = v;
     }
+    __device__ __forceinline__ Cx<T> load_at(int u, int t) const { return load(u + t); }
+    __device__ __forceinline__ void store_at(int u, int t, Cx<T> v) const { store(u + t, v); }
 };
 
-// element i of a strided pencil in global memory.  A pencil beyond the tile
-// edge (valid false) points at a valid pencil of the tile: it loads real
-// data, is transformed like the others, and stores nothing.  Offsets within
-// one problem's spectrum fit 32 bits (the host limits its size).
-template <typename T>
+// Element u + tip of the thread's strided pencil in global memory, where the
+// stage loops pass u (the part of the index that is the same for every lane
+// of a wavefront) and tip separately: the uniform part moves a base pointer
+// in scalar registers, and each lane adds its fixed offset lane = tip *
+// stride + its pencil's column, so an access costs no vector arithmetic.
+// L32: lane * sizeof(Cx<T>) fits 32 bits (the host launches such kernels
+// only then), and the lane offset is a 32-bit byte offset.  A pencil beyond
+// the tile edge (valid false) points at a valid pencil of the tile: it loads
+// real data, is transformed like the others, and stores nothing.
+template <typename T, bool L32>
 struct GlobalPencil {
     static constexpr bool kLds = false;
-    Cx<T> *ptr;
-    int stride;
+    Cx<T> *base;  // element 0 of the tile's first pencil (wavefront-uniform)
+    int stride;   // elements between consecutive points of a pencil
+    int lane;     // tip * stride + column of this thread's pencil (elements)
     bool valid;
     bool cj;
-    __device__ __forceinline__ Cx<T> load(int i) const
+    __device__ __forceinline__ Cx<T> *at(int u) const
     {
-        Cx<T> v = ptr[i * stride];
+        Cx<T> *row = base + int64_t(u) * stride;
+        if constexpr (L32)
+            return reinterpret_cast<Cx<T> *>(reinterpret_cast<char *>(row) +
+                                              uint32_t(lane) * uint32_t(sizeof(Cx<T>)));
+        else
+            return row + lane;
+    }
+    __device__ __forceinline__ Cx<T> load_at(int u, int) const
+    {
+        Cx<T> v = *at(u);
         if (cj) v.y = -v.y;
         return v;
     }
-    __device__ __forceinline__ void store(int i, Cx<T> v) const
+    __device__ __forceinline__ void store_at(int u, int, Cx<T> v) const
     {
         if (cj) v.y = -v.y;
-        if (valid) ptr[i * stride] = v;
+        if (valid) *at(u) = v;
     }
 };
 
@@ -323,7 +343,7 @@ __device__ __forceinline__ void stage(const Src &src, Dst &dst, const Cx<T> *tw,
         const int j = tip + m * tpp;
         if (j < nb) {
 #pragma unroll
-            for (int q = 0; q < R; ++q) v[m][q] = src.load(j + q * nb);
+            for (int q = 0; q < R; ++q) v[m][q] = src.load_at(m * tpp + q * nb, tip);
         }
     }
     if (SYNC) __syncthreads();
@@ -341,9 +361,16 @@ __device__ __forceinline__ void stage(const Src &src, Dst &dst, const Cx<T> *tw,
                 for (int q = 1; q < R; ++q) v[m][q] = cmul(v[m][q], tw[q * tstep]);
             }
             butterfly<T, R, false>(v[m]);
-            const int base = jd * ns * R + k;
+            if constexpr (Dst::kLds) {
+                const int base = jd * ns * R + k;
 #pragma unroll
-            for (int q = 0; q < R; ++q) dst.store(base + q * ns, v[m][q]);
+                for (int q = 0; q < R; ++q) dst.store(base + q * ns, v[m][q]);
+            } else {
+                // only the last stage writes global memory: ns = n / R,
+                // so jd = 0 and k = j
+#pragma unroll
+                for (int q = 0; q < R; ++q) dst.store_at(m * tpp + q * ns, tip, v[m][q]);
+            }
         }
     }
 }
@@ -360,7 +387,7 @@ __device__ __forceinline__ void stage_ct(const Src &src, Dst &dst, const Cx<T> *
         const int j = tip + m * tpp;
         if (j < NB) {
 #pragma unroll
-            for (int q = 0; q < R; ++q) v[m][q] = src.load(j + q * NB);
+            for (int q = 0; q < R; ++q) v[m][q] = src.load_at(m * tpp + q * NB, tip);
         }
     }
     if (SYNC) __syncthreads();
@@ -377,9 +404,15 @@ __device__ __forceinline__ void stage_ct(const Src &src, Dst &dst, const Cx<T> *
                 for (int q = 1; q < R; ++q) v[m][q] = cmul(v[m][q], tw[q * tstep]);
             }
             butterfly<T, R, false>(v[m]);
-            const int base = jd * (NS * R) + k;
+            if constexpr (Dst::kLds) {
+                const int base = jd * (NS * R) + k;
 #pragma unroll
-            for (int q = 0; q < R; ++q) dst.store(base + q * NS, v[m][q]);
+                for (int q = 0; q < R; ++q) dst.store(base + q * NS, v[m][q]);
+            } else {
+                // the last stage (NS = N / R): jd = 0, k = j
+#pragma unroll
+                for (int q = 0; q < R; ++q) dst.store_at(m * tpp + q * NS, tip, v[m][q]);
+            }
         }
     }
 }
@@ -425,7 +458,7 @@ __device__ __forceinline__ void fft_pencils(const Src &src, Dst &dst, const L &l
     stage_any<T, true, Src::kLds>(ap.radix[0], src, l, tw, n, ap.twstride[0], ap.ns[0], tip, tpp);
     __syncthreads();
     if (S == 1) {
-        for (int i = tip; i < n; i += tpp) dst.store(i, l.load(i));
+        for (int u = 0; u + tip < n; u += tpp) dst.store_at(u, tip, l.load(u + tip));
         return;
     }
     for (int s = 1; s + 1 < S; ++s) {
@@ -456,7 +489,7 @@ __device__ __forceinline__ void fft_static(const Src &src, Dst &dst, const L &ld
     stage_ct<T, R0, stage_maxb<T>(R0), true, Src::kLds, N / R0, 1, 1>(src, l, tw, tip, tpp);
     __syncthreads();
     if constexpr (S == 1) {
-        for (int i = tip; i < N; i += tpp) dst.store(i, l.load(i));
+        for (int u = 0; u + tip < N; u += tpp) dst.store_at(u, tip, l.load(u + tip));
     } else if constexpr (S == 2) {
         stage_ct<T, Q1, stage_maxb<T>(Q1), false, Dst::kLds, N / Q1, NS1, N / (NS1 * Q1)>(l, dst, tw, tip, tpp);
     } else {

@@ -88,6 +88,20 @@ struct RealPairIn {
             return Cx<T>{w0 * ld(r0 + i) + s0 * ld(h0 + i), w1 * ld(r1 + i) + s1 * ld(h1 + i)};
         else return Cx<T>{s0 * ld(h0 + i), s1 * ld(h1 + i)};
     }
+    // element u + t, u uniform: where the rows are the same for the whole
+    // wavefront (a pencil per wavefront) the row pointers plus u stay in
+    // scalar registers and t becomes a fixed 32-bit byte offset
+    static __device__ __forceinline__ T ldu(const T *row, int u, int t)
+    {
+        return ld(reinterpret_cast<const T *>(reinterpret_cast<const char *>(row + u) + uint32_t(t) * uint32_t(sizeof(T))));
+    }
+    __device__ __forceinline__ Cx<T> load_at(int u, int t) const
+    {
+        if constexpr (MODE == 0) return Cx<T>{w0 * ldu(r0, u, t), w1 * ldu(r1, u, t)};
+        else if constexpr (MODE == 1)
+            return Cx<T>{w0 * ldu(r0, u, t) + s0 * ldu(h0, u, t), w1 * ldu(r1, u, t) + s1 * ldu(h1, u, t)};
+        else return Cx<T>{s0 * ldu(h0, u, t), s1 * ldu(h1, u, t)};
+    }
 };
 
 // P5 input: Z[i] = X[i] + i Y[i] from the half-spectrum rows of X and Y,
@@ -116,6 +130,7 @@ struct HermitianPairIn {
         }
         return Cx<T>{xe.x - xo.y, -(xe.y + xo.x)};
     }
+    __device__ __forceinline__ Cx<T> load_at(int u, int t) const { return load(u + t); }
 };
 
 // P5 output: the conjugate of the last stage's value is x + i y for the
@@ -129,6 +144,13 @@ struct RealPairOut {
     {
         if (v0) __builtin_nontemporal_store(v.x, o0 + i);
         if (v1) __builtin_nontemporal_store(-v.y, o1 + i);
+    }
+    // element u + t, u uniform (see RealPairIn::load_at)
+    __device__ __forceinline__ void store_at(int u, int t, Cx<T> v) const
+    {
+        const uint32_t off = uint32_t(t) * uint32_t(sizeof(T));
+        if (v0) __builtin_nontemporal_store(v.x, reinterpret_cast<T *>(reinterpret_cast<char *>(o0 + u) + off));
+        if (v1) __builtin_nontemporal_store(-v.y, reinterpret_cast<T *>(reinterpret_cast<char *>(o1 + u) + off));
     }
 };
 
@@ -169,7 +191,10 @@ __global__ __launch_bounds__(256) void k_r2c_mode(PassArgs a)
     load_twiddles(tw, reinterpret_cast<const Cx<T> *>(a.tw) + d.ax[2].tw_off, n, tid, NT);
     __syncthreads();
 
-    const int q = tid / TPP, tip = tid - q * TPP;
+    // with 64 or more threads per pencil a wavefront holds one pencil: its
+    // index is uniform and the row pointers stay in scalar registers
+    const int q = (CP > 0 && NT / CP >= 64) ? __builtin_amdgcn_readfirstlane(tid / TPP) : tid / TPP;
+    const int tip = tid & (TPP - 1);  // TPP is a power of two
     const bool v0 = 2 * q < rows, v1 = 2 * q + 1 < rows;
     const int64_t g_even = d.grid_off + (row0 + (v0 ? 2 * q : 0)) * n;
     const int64_t g_odd = d.grid_off + (row0 + (v1 ? 2 * q + 1 : 0)) * n;
@@ -233,7 +258,8 @@ __global__ __launch_bounds__(256) void k_c2r(PassArgs a)
     load_twiddles(tw, reinterpret_cast<const Cx<T> *>(a.tw) + d.ax[2].tw_off, n, tid, NT);
     __syncthreads();
 
-    const int q = tid / TPP, tip = tid - q * TPP;
+    const int q = (CP > 0 && NT / CP >= 64) ? __builtin_amdgcn_readfirstlane(tid / TPP) : tid / TPP;
+    const int tip = tid & (TPP - 1);  // TPP is a power of two
     const bool v0 = 2 * q < rows, v1 = 2 * q + 1 < rows;
     const Cx<T> *spec = reinterpret_cast<const Cx<T> *>(a.spec) + d.spec_off + row0 * nh;
     HermitianPairIn<T> in;
@@ -284,8 +310,8 @@ __global__ __launch_bounds__(256) void k_fft_b(PassArgs a)
     load_twiddles(tw, reinterpret_cast<const Cx<T> *>(a.tw) + d.ax[1].tw_off, n, tid, NT);
     __syncthreads();
     const int p = tid & (P - 1), tip = CP > 0 ? tid / CP : tid >> a.p_log2;
-    Cx<T> *g = reinterpret_cast<Cx<T> *>(a.spec) + d.spec_off + int64_t(outer) * n * nh + h0 + (p < valid ? p : 0);
-    GlobalPencil<T> gp{g, nh, p < valid, a.inv != 0};
+    Cx<T> *g = reinterpret_cast<Cx<T> *>(a.spec) + d.spec_off + int64_t(outer) * n * nh + h0;
+    GlobalPencil<T, (CP > 0)> gp{g, nh, tip * nh + (p < valid ? p : 0), p < valid, a.inv != 0};
     const LdsPencil<T> lp{buf, PP, p, false};
     fft_any<T, R0, R1, R2, R3>(gp, gp, lp, tw, d.ax[1], tip, TPP);
 }
@@ -364,11 +390,12 @@ struct KernelMultiply {
     int pp, p;
     const ProbDesc *d;
     int mb, mc;
-    bool energy;
+    bool energy;      // wavefront-uniform: accumulate the E_H partial
     T invn;
-    double wgt;
+    double wgt;       // w(m_c), and 0 for a pencil beyond the tile edge
     double acc;
     int na;
+    bool ortho;       // wavefront-uniform: a diagonal cell (no Nyquist average, q1 = 0)
     bool general;     // a Nyquist b or c index of a non-orthorhombic cell
     T q2, q1, q0;     // |G|^2 = (q2 s_a + q1) s_a + q0
     __device__ __forceinline__ void init()
@@ -378,7 +405,8 @@ struct KernelMultiply {
         else B = reinterpret_cast<const T *>(d->B);
         const int Nb = d->dims[1], Nc = d->dims[2];
         na = d->dims[0];
-        general = !d->ortho && (2 * mb == Nb || 2 * mc == Nc);
+        ortho = d->ortho != 0;
+        general = !ortho && (2 * mb == Nb || 2 * mc == Nc);
         const T sb = T((2 * mb < Nb) ? mb : mb - Nb), sc = T(mc);
         q2 = q1 = q0 = T(0);
         for (int x = 0; x < 3; ++x) {
@@ -391,7 +419,13 @@ struct KernelMultiply {
     __device__ __forceinline__ void store(int i, Cx<T> v)
     {
         T K;
-        if (general || (!d->ortho && 2 * i == na)) {
+        if (ortho) {
+            // a diagonal cell: b_a is orthogonal to b_b and b_c, so q1 = 0
+            // and no index needs the Nyquist average
+            const T sa = T((2 * i < na) ? i : i - na);
+            const T g2 = q2 * sa * sa + q0;
+            K = (g2 > T(0)) ? T(12.566370614359172953850573533118) * recip(g2) : T(0);
+        } else if (general || 2 * i == na) {
             K = kernel_value_rare<T>(*d, i, mb, mc);
         } else {
             const T sa = T((2 * i < na) ? i : i - na);
@@ -401,6 +435,7 @@ struct KernelMultiply {
         if (energy) acc += wgt * double(K * (v.x * v.x + v.y * v.y));
         buf[i * pp + p] = cscale(v, K * invn);
     }
+    __device__ __forceinline__ void store_at(int u, int t, Cx<T> v) { store(u + t, v); }
 };
 
 // mode 0: forward, energy, multiply, inverse.  mode 1: no energy.
@@ -437,15 +472,16 @@ __global__ __launch_bounds__(256) void k_fft_a(PassArgs a)
     const int col = col0 + (p < valid ? p : 0);
     const int mb = int(fdiv(uint32_t(col), d.div_nh));
     const int mc = col - mb * nh;
-    Cx<T> *g = reinterpret_cast<Cx<T> *>(a.spec) + d.spec_off + col;
-    GlobalPencil<T> gp{g, ncol, p < valid, false};
+    Cx<T> *g = reinterpret_cast<Cx<T> *>(a.spec) + d.spec_off + col0;
+    const int lane = tip * ncol + (p < valid ? p : 0);
+    GlobalPencil<T, (CP > 0)> gp{g, ncol, lane, p < valid, false};
     const LdsPencil<T> lp{buf, PP, p, false};
-    KernelMultiply<T> km{buf, PP, p, &d, mb, mc, energy && p < valid, T(d.inv_n),
-                         (mc == 0 || 2 * mc == Nc) ? 1.0 : 2.0, 0.0};
+    KernelMultiply<T> km{buf, PP, p, &d, mb, mc, energy, T(d.inv_n),
+                         p < valid ? ((mc == 0 || 2 * mc == Nc) ? 1.0 : 2.0) : 0.0, 0.0};
     km.init();
     if (d.ax[0].nstages == 0) {
         // length-1 axis: the multiply alone
-        if (tip == 0) km.store(0, gp.load(0));
+        if (tip == 0) km.store(0, gp.load_at(0, 0));
     } else {
         fft_any<T, R0, R1, R2, R3>(gp, km, lp, tw, d.ax[0], tip, TPP);
     }
@@ -463,9 +499,9 @@ __global__ __launch_bounds__(256) void k_fft_a(PassArgs a)
     if (mode == 2) return;
     // inverse along a: conjugate on the way in and on the way out
     const LdsPencil<T> lpc{buf, PP, p, true};
-    GlobalPencil<T> gpc{g, ncol, p < valid, true};
+    GlobalPencil<T, (CP > 0)> gpc{g, ncol, lane, p < valid, true};
     if (d.ax[0].nstages == 0) {
-        if (tip == 0) gp.store(0, lp.load(0));
+        if (tip == 0) gp.store_at(0, 0, lp.load(0));
     } else {
         fft_any<T, R0, R1, R2, R3>(lpc, gpc, lp, tw, d.ax[0], tip, TPP);
     }
@@ -498,6 +534,16 @@ static hipError_t launch_pass(F kern, int grid, size_t lds, hipStream_t s, const
     }
     hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, s, a);
     return hipGetLastError();
+}
+
+// Strided tiles of compiled width keep each thread's offset from the tile's
+// first pencil, tip * stride + column, as a 32-bit byte offset: true when that
+// fits for every problem of the launch (the largest stride, tpp - 1 tips).
+template <typename T>
+inline bool lane_offsets_fit(const PassArgs &a)
+{
+    const int64_t P = int64_t(1) << a.p_log2, tpp = kPassThreads / P;
+    return ((tpp - 1) * a.col_stride + P) * int64_t(sizeof(Cx<T>)) < (int64_t(1) << 32);
 }
 
 // A launcher runs plan < 0 through the run-time radix kernel and otherwise

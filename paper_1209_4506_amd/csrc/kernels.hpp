@@ -37,6 +37,7 @@ struct PassArgs {
     int32_t inv;           // P2/P4: 1 for the inverse transform
     int32_t p_log2;        // pencils per workgroup, log2
     int32_t pad;           // strided tiles (P2-P4): LDS pitch P + pad complex values per pencil element
+    int64_t col_stride;    // strided passes: the largest pencil stride (elements) of the launch's problems
     TileList tl;
 };
 

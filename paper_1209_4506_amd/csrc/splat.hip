@@ -202,12 +202,14 @@ __global__ __launch_bounds__(256) void k_brick_visit(SplatArgs a)
     }
 }
 
-// exclusive scan of counts[0..n) into offsets[0..n] by one workgroup:
-// thread t owns a contiguous run of entries, sums it, the workgroup scans
-// the run sums, and each thread writes its run (clamped to the capacity).
-// The same workgroup first sums each problem's charges Q = sum Z in a
-// fixed order (for the background Q / Omega).
+// exclusive scan of counts[0..n) into offsets[0..n] by one workgroup, in
+// chunks of kScanThreads * kScanPer entries: thread t loads the kScanPer
+// consecutive counts at t * kScanPer of the chunk (four 16-byte loads), the
+// workgroup scans the per-thread sums, and each thread writes its run
+// (clamped to the capacity).  The same workgroup first sums each problem's
+// charges Q = sum Z in a fixed order (for the background Q / Omega).
 constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 16;
 
 __global__ __launch_bounds__(kScanThreads) void k_scan(SplatArgs a)
 {
@@ -230,30 +232,55 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(SplatArgs a)
         __syncthreads();
     }
     const int64_t n = a.nbricks_total;
-    const int64_t per = (n + kScanThreads - 1) / kScanThreads;
-    const int64_t e0 = t * per, e1 = (e0 + per) < n ? (e0 + per) : n;
-    int64_t s = 0;
-    for (int64_t e = e0; e < e1; ++e) s += a.counts[e];
-    // inclusive scan of the run sums within the wavefront, then across them
-    int64_t x = s;
+    constexpr int64_t CH = int64_t(kScanThreads) * kScanPer;
+    int64_t carry = 0;  // total of the chunks before this one (the same in every thread)
+    for (int64_t c0 = 0; c0 < n; c0 += CH) {
+        const int64_t e0 = c0 + int64_t(t) * kScanPer;
+        int v[kScanPer];
+        if (e0 + kScanPer <= n) {
+            // the counts array is 256-byte aligned and e0 a multiple of 16
+            const int4 *src = reinterpret_cast<const int4 *>(a.counts + e0);
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int64_t y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
+            for (int k = 0; k < kScanPer / 4; ++k) {
+                const int4 x = src[k];
+                v[4 * k] = x.x;
+                v[4 * k + 1] = x.y;
+                v[4 * k + 2] = x.z;
+                v[4 * k + 3] = x.w;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kScanPer; ++k) v[k] = e0 + k < n ? a.counts[e0 + k] : 0;
+        }
+        int64_t s = 0;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) s += v[k];
+        // inclusive scan of the thread sums within the wavefront, then across them
+        int64_t x = s;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int64_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wtot[w] = x;
+        __syncthreads();
+        int64_t before = 0, chunk = 0;
+        for (int k = 0; k < NW; ++k) {
+            if (k < w) before += wtot[k];
+            chunk += wtot[k];
+        }
+        int64_t run = carry + before + x - s;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            if (e0 + k < n) a.offsets[e0 + k] = int32_t(run < a.capacity ? run : a.capacity);
+            run += v[k];
+        }
+        carry += chunk;
+        __syncthreads();  // wtot is rewritten by the next chunk
     }
-    if (lane == 63) wtot[w] = x;
-    __syncthreads();
-    int64_t before = 0;
-    for (int k = 0; k < w; ++k) before += wtot[k];
-    int64_t run = before + x - s;
-    for (int64_t e = e0; e < e1; ++e) {
-        a.offsets[e] = int32_t(run < a.capacity ? run : a.capacity);
-        run += a.counts[e];
-    }
-    if (t == kScanThreads - 1) {
-        const int64_t total = before + x;
-        a.offsets[n] = int32_t(total < a.capacity ? total : a.capacity);
-        if (total > a.capacity) atomicOr(&a.status->bits, 0x4u);
+    if (t == 0) {
+        a.offsets[n] = int32_t(carry < a.capacity ? carry : a.capacity);
+        if (carry > a.capacity) atomicOr(&a.status->bits, 0x4u);
     }
 }
 
@@ -293,20 +320,31 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a, int rank_words)
         while (prob + 1 < a.nprob && b >= a.desc[prob + 1].brick_off) ++prob;
     const int a0 = a.atom_off[prob];
     const int span = a.atom_off[prob + 1] - a0;
-    const bool bitmap = rank_words > 0;
+    // ranks from the bitmap cost about span / 32 word operations per
+    // wavefront plus a scan; counting smaller entries costs cnt per lane:
+    // short lists over wide spans (many atoms per problem, few per brick)
+    // are ranked by counting
+    const int nw = (span + 31) >> 5;
+    const bool bitmap = rank_words > 0 && !(cnt <= kSortLds && cnt <= nw / 32 + 16);
     uint32_t *bm = rank_lds + w * 2 * rank_words, *pre = bm + rank_words;
-    const bool in_lds = cnt <= kSortLds;
+    const bool in_lds = !bitmap && cnt <= kSortLds;
+    // the barriers are reached by every wavefront whatever its brick's method
+    if (bitmap)
+        for (int i = lane; i < nw; i += 64) bm[i] = 0u;
+    __syncthreads();
     if (bitmap) {
-        for (int i = lane; i < rank_words; i += 64) bm[i] = 0u;
-        __syncthreads();
         for (int e = lane; e < cnt; e += 64) {
             const int r = a.list[off + e] - a0;
             if (unsigned(r) < unsigned(span)) atomicOr(&bm[r >> 5], 1u << (r & 31));
         }
-        __syncthreads();
+    } else if (in_lds) {
+        for (int e = lane; e < cnt; e += 64) lst[w][e] = a.list[off + e];
+    }
+    __syncthreads();
+    if (bitmap) {
         // exclusive prefix of the words' bit counts: lane l takes a run of
         // consecutive words, a wavefront scan orders the runs
-        const int nw = (span + 31) >> 5, wpl = (nw + 63) >> 6;
+        const int wpl = (nw + 63) >> 6;
         const int w0 = lane * wpl < nw ? lane * wpl : nw, w1 = w0 + wpl < nw ? w0 + wpl : nw;
         int c = 0;
         for (int i = w0; i < w1; ++i) c += __popc(bm[i]);
@@ -321,8 +359,6 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a, int rank_words)
             pre[i] = uint32_t(run);
             run += __popc(bm[i]);
         }
-    } else if (in_lds) {
-        for (int e = lane; e < cnt; e += 64) lst[w][e] = a.list[off + e];
     }
     __syncthreads();
     if (cnt == 0) return;
