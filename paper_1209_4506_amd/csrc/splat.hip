@@ -217,19 +217,34 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(SplatArgs a)
     __shared__ int64_t wtot[NW];
     __shared__ double qw[NW];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    for (int p = 0; p < a.nprob; ++p) {
-        double q = 0.0;
-        for (int i = a.atom_off[p] + t; i < a.atom_off[p + 1]; i += kScanThreads) q += a.Z[i];
+    if (a.nprob <= 4) {
+        // few problems: the whole workgroup sums each problem's charges,
+        // thread t the atoms t, t + kScanThreads, ..., then fixed butterflies
+        for (int p = 0; p < a.nprob; ++p) {
+            double q = 0.0;
+            for (int i = a.atom_off[p] + t; i < a.atom_off[p + 1]; i += kScanThreads) q += a.Z[i];
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) q += __shfl_xor(q, off, 64);
-        if (lane == 0) qw[w] = q;
-        __syncthreads();
-        if (t == 0) {
-            double tot = 0.0;
-            for (int k = 0; k < NW; ++k) tot += qw[k];
-            a.qsum[p] = tot;
+            for (int off = 32; off >= 1; off >>= 1) q += __shfl_xor(q, off, 64);
+            if (lane == 0) qw[w] = q;
+            __syncthreads();
+            if (t == 0) {
+                double tot = 0.0;
+                for (int k = 0; k < NW; ++k) tot += qw[k];
+                a.qsum[p] = tot;
+            }
+            __syncthreads();
         }
-        __syncthreads();
+    } else {
+        // many problems: wavefront w sums the charges of problems w, w + NW,
+        // ...: lane l the atoms l, l + 64, ... of the problem, then a fixed
+        // butterfly (no workgroup barrier per problem)
+        for (int p = w; p < a.nprob; p += NW) {
+            double q = 0.0;
+            for (int i = a.atom_off[p] + lane; i < a.atom_off[p + 1]; i += 64) q += a.Z[i];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) q += __shfl_xor(q, off, 64);
+            if (lane == 0) a.qsum[p] = q;
+        }
     }
     const int64_t n = a.nbricks_total;
     constexpr int64_t CH = int64_t(kScanThreads) * kScanPer;
