@@ -345,25 +345,17 @@ __device__ __forceinline__ void adjoint_factors(AdjBuf &buf, const StagedG *recs
     }
 }
 
-// One group's products and fold.  Lane l holds S[row][n] for column
-// n = l % 32 (function f = n / 16 of atom n % 16) and 16 rows of each of its
-// two tiles: row r of tile u is local i = 4 wave + 2 u + r / 8 and
-// j = 8 ((r / 4) % 2) + 4 half + r % 4, so the eight j values (and their gy,
-// gdy) are the same for both tiles and both halves r / 8.  Writes the lane's
-// two partial components to red[n][0 .. 1].
-__device__ __forceinline__ void adjoint_group(const AdjBuf &buf, const half8 (&ah)[2][2], const half8 (&al)[2][2],
-                                              const float (&unscale)[2], int wave, int lane, float (*red)[2])
+// One group's products and fold, split in two so that the caller can
+// evaluate the next group's factors while the products run on the matrix
+// cores.  Lane l holds S[row][n] for column n = l % 32 (function f = n / 16
+// of atom n % 16) and 16 rows of each of its two tiles: row r of tile u is
+// local i = 4 wave + 2 u + r / 8 and j = 8 ((r / 4) % 2) + 4 half + r % 4, so
+// the eight j values (and their gy, gdy) are the same for both tiles and
+// both halves r / 8.
+__device__ __forceinline__ void adjoint_products(const AdjBuf &buf, const half8 (&ah)[2][2], const half8 (&al)[2][2],
+                                                 int lane, floatx16 (&acc)[2])
 {
     const int half = lane >> 5, n = lane & 31;
-    const int f = n >> 4, sl = n & 15;
-    float yv[8], dyv[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const int j = mfma_row(r, lane) & 15;
-        yv[r] = buf.gxy[sl][kMI + j];
-        dyv[r] = buf.gdxy[sl][kMI + j];
-    }
-    float ax = 0.0f, ay = 0.0f;  // f = 0: (x, y) components; f = 1: z in ax
     // B operand: column n at points 16 kap + 8 half + e, e = 0 .. 7, in the
     // same K slots as the A operand's grad_rho
     half8 bh[2], bl[2];
@@ -372,40 +364,59 @@ __device__ __forceinline__ void adjoint_group(const AdjBuf &buf, const half8 (&a
         bh[kap] = *reinterpret_cast<const half8 *>(&buf.bhi[n][16 * kap + 8 * half]);
         bl[kap] = *reinterpret_cast<const half8 *>(&buf.blo[n][16 * kap + 8 * half]);
     }
+    // the two tiles' product chains interleaved (each tile's own order is
+    // fixed): (hi + lo)(hi' + lo') without lo lo', the small terms first
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        floatx16 acc;
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-        // (hi + lo)(hi' + lo') without lo lo': the small terms first
+        for (int r = 0; r < 16; ++r) acc[u][r] = 0.0f;
 #pragma unroll
-        for (int kap = 0; kap < 2; ++kap) {
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(al[u][kap], bh[kap], acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[u][kap], bl[kap], acc, 0, 0, 0);
+    for (int kap = 0; kap < 2; ++kap)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al[u][kap], bh[kap], acc[u], 0, 0, 0);
+            acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[u][kap], bl[kap], acc[u], 0, 0, 0);
         }
 #pragma unroll
-        for (int kap = 0; kap < 2; ++kap)
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[u][kap], bh[kap], acc, 0, 0, 0);
+    for (int kap = 0; kap < 2; ++kap)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[u][kap], bh[kap], acc[u], 0, 0, 0);
+}
+
+// The fold of the products with the transverse factors; writes the lane's
+// two partial components to red[n][0 .. 1]: ax, the x component (f = 0) or
+// the z component (f = 1), and ay, the y component (f = 0; f = 1 lanes
+// compute a value nobody reads, which keeps the fold free of branches).
+// The x coefficient of row i is gdx (f = 0) or gx (f = 1), that of ay gx.
+__device__ __forceinline__ void adjoint_fold(const AdjBuf &buf, const floatx16 (&acc)[2], const float (&unscale)[2],
+                                             int wave, int lane, float (*red)[2])
+{
+    const int n = lane & 31;
+    const int f = n >> 4, sl = n & 15;
+    float yv[8], dyv[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int j = mfma_row(r, lane) & 15;
+        yv[r] = buf.gxy[sl][kMI + j];
+        dyv[r] = buf.gdxy[sl][kMI + j];
+    }
+    float ax = 0.0f, ay = 0.0f;
+    const float *cx = f == 0 ? buf.gdxy[sl] : buf.gxy[sl];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int i = 4 * wave + 2 * u + h;
             float sy = 0.0f, sdy = 0.0f;
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
-                sy += yv[r] * acc[8 * h + r];
-                sdy += dyv[r] * acc[8 * h + r];
+                sy += yv[r] * acc[u][8 * h + r];
+                sdy += dyv[r] * acc[u][8 * h + r];
             }
             // the fold is linear in the products: undo the operand scales here
-            sy *= unscale[u];
-            sdy *= unscale[u];
-            if (f == 0) {
-                ax += buf.gdxy[sl][i] * sy;
-                ay += buf.gxy[sl][i] * sdy;
-            } else {
-                ax += buf.gxy[sl][i] * sy;
-            }
+            ax += cx[i] * (sy * unscale[u]);
+            ay += buf.gxy[sl][i] * (sdy * unscale[u]);
         }
-    }
     red[n][0] = ax;
     red[n][1] = ay;
 }
@@ -597,9 +608,11 @@ __global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(3))) 
         if (blk == 0) split_grad(g0, g1, ah, al, unscale, a.b_exp);
         for (int gi = 0; gi < ngroup; ++gi) {
             if (gi > 0) adjoint_reduce(a, red[(gi - 1) & 1], recs, (gi - 1) * kAdjGroup, nb, t);
+            floatx16 acc[2];
+            adjoint_products(buf[gi & 1], ah, al, lane, acc);
             if (gi + 1 < ngroup)
                 adjoint_factors<WIDE>(buf[(gi + 1) & 1], recs, la, (gi + 1) * kAdjGroup, nb, wave, lane, bscale);
-            adjoint_group(buf[gi & 1], ah, al, unscale, wave, lane, red[gi & 1][wave][half]);
+            adjoint_fold(buf[gi & 1], acc, unscale, wave, lane, red[gi & 1][wave][half]);
             __syncthreads();
         }
         adjoint_reduce(a, red[(ngroup - 1) & 1], recs, (ngroup - 1) * kAdjGroup, nb, t);
