@@ -500,7 +500,7 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
     p->o_tw = take(cx * (p->twiddles.size() / 2));
     p->o_spec = take(cx * size_t(p->spec_count));
     p->o_parts = take(8 * size_t(p->max_parts + 1));
-    p->o_qsum = take(8 * size_t(nprob));
+    p->o_qsum = take(16 * size_t(nprob));  // per problem: the charge Q, then the largest atom weight
     if (p->splat_ok) {
         p->o_info = take(sizeof(AtomInfo) * size_t(p->max_atoms));
         p->o_counts = take(4 * size_t(p->nbricks + 1));

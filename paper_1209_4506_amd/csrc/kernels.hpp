@@ -90,7 +90,7 @@ struct SplatArgs {
     int32_t grad_rows_vec4; // every problem's grad_rho rows start 16-byte aligned with Nc % 4 == 0
     const float *zeros;     // 64 zero floats in the workspace (never written by kernels)
     double *grad_pos;       // adjoint output
-    double *qsum;           // nprob: total charge per problem
+    double *qsum;           // 2 nprob: total charge per problem, then the largest atom weight per problem
     void *tab;              // per-atom 1-D factor tables: max_atoms x 3 x wcap pairs (g, gd) of the precision
     int32_t wcap;           // table row length
 };

@@ -207,30 +207,59 @@ __global__ __launch_bounds__(256) void k_brick_visit(SplatArgs a)
 // consecutive counts at t * kScanPer of the chunk (four 16-byte loads), the
 // workgroup scans the per-thread sums, and each thread writes its run
 // (clamped to the capacity).  The same workgroup first sums each problem's
-// charges Q = sum Z in a fixed order (for the background Q / Omega).
+// charges Q = sum Z in a fixed order (for the background Q / Omega) and
+// takes the largest weight |Z| (2 pi sigma^2)^(-3/2) of its valid atoms (the
+// FP32 splat scales its 16-bit operands by it).
 constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 16;
+
+// the weight |Z| (2 pi sigma^2)^(-3/2) of a valid atom in float (a bound
+// for scaling: clamped to the float range), 0 for an invalid one
+__device__ __forceinline__ float weight_bound(const SplatArgs &a, int i)
+{
+    const double s = a.sigma[i], z = a.Z[i];
+    if (!(isfinite(z) && s > 0.0 && s <= a.max_sigma)) return 0.0f;
+    const float s2 = 6.2831855f * float(s) * float(s);
+    const float wv = fabsf(float(z)) / (s2 * sqrtf(s2));
+    return wv < 3.0e38f ? wv : 3.0e38f;
+}
 
 __global__ __launch_bounds__(kScanThreads) void k_scan(SplatArgs a)
 {
     constexpr int NW = kScanThreads / 64;
     __shared__ int64_t wtot[NW];
     __shared__ double qw[NW];
+    __shared__ float ww[NW];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     if (a.nprob <= 4) {
         // few problems: the whole workgroup sums each problem's charges,
         // thread t the atoms t, t + kScanThreads, ..., then fixed butterflies
         for (int p = 0; p < a.nprob; ++p) {
             double q = 0.0;
-            for (int i = a.atom_off[p] + t; i < a.atom_off[p + 1]; i += kScanThreads) q += a.Z[i];
+            float wm = 0.0f;
+            for (int i = a.atom_off[p] + t; i < a.atom_off[p + 1]; i += kScanThreads) {
+                q += a.Z[i];
+                wm = fmaxf(wm, weight_bound(a, i));
+            }
 #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) q += __shfl_xor(q, off, 64);
-            if (lane == 0) qw[w] = q;
+            for (int off = 32; off >= 1; off >>= 1) {
+                q += __shfl_xor(q, off, 64);
+                wm = fmaxf(wm, __shfl_xor(wm, off, 64));
+            }
+            if (lane == 0) {
+                qw[w] = q;
+                ww[w] = wm;
+            }
             __syncthreads();
             if (t == 0) {
                 double tot = 0.0;
-                for (int k = 0; k < NW; ++k) tot += qw[k];
+                float wmax = 0.0f;
+                for (int k = 0; k < NW; ++k) {
+                    tot += qw[k];
+                    wmax = fmaxf(wmax, ww[k]);
+                }
                 a.qsum[p] = tot;
+                a.qsum[a.nprob + p] = wmax;
             }
             __syncthreads();
         }
@@ -240,10 +269,20 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(SplatArgs a)
         // butterfly (no workgroup barrier per problem)
         for (int p = w; p < a.nprob; p += NW) {
             double q = 0.0;
-            for (int i = a.atom_off[p] + lane; i < a.atom_off[p + 1]; i += 64) q += a.Z[i];
+            float wm = 0.0f;
+            for (int i = a.atom_off[p] + lane; i < a.atom_off[p + 1]; i += 64) {
+                q += a.Z[i];
+                wm = fmaxf(wm, weight_bound(a, i));
+            }
 #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) q += __shfl_xor(q, off, 64);
-            if (lane == 0) a.qsum[p] = q;
+            for (int off = 32; off >= 1; off >>= 1) {
+                q += __shfl_xor(q, off, 64);
+                wm = fmaxf(wm, __shfl_xor(wm, off, 64));
+            }
+            if (lane == 0) {
+                a.qsum[p] = q;
+                a.qsum[a.nprob + p] = wm;
+            }
         }
     }
     const int64_t n = a.nbricks_total;

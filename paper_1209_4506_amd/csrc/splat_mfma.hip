@@ -1,6 +1,6 @@
-// FP32 splat and splat adjoint on the matrix cores: the splat with FP32
-// products (v_mfma_f32_32x32x2f32), the adjoint with 16-bit split products
-// (v_mfma_f32_32x32x16_f16, three per FP32-accurate product).
+// FP32 splat and splat adjoint on the matrix cores, both with 16-bit split
+// products (three per FP32-accurate product): the splat with
+// v_mfma_f32_32x32x8f16, the adjoint with v_mfma_f32_32x32x16_f16.
 //
 // A brick is 16 x 16 columns (i, j) by 32 points along c.  Inside it both
 // operations are dense contractions over the brick's atom list:
@@ -16,23 +16,28 @@
 // columns (c = 16 i + j) form 8 row tiles of 32; wavefront w owns tiles 2w
 // and 2w + 1, i.e. local i = 4w, 4w + 1 and 4w + 2, 4w + 3.
 //
-// Operand layout of v_mfma_f32_32x32x2f32 (C = A B + C, A 32x2, B 2x32):
-// lane l supplies A[l % 32][l / 32] and B[l / 32][l % 32]; after the call
-// lane l holds C[i][l % 32] for i = 8 (r / 4) + 4 (l / 32) + r % 4 in its
-// accumulator element r = 0 .. 15.  v_mfma_f32_32x32x16_f16 has the same C
-// layout, with 8 K slots per lane: element e of lane l is K slot
-// 8 (l / 32) + e of both A (row l % 32) and B (column l % 32).  Which
-// reduction index sits in which K slot is free as long as A and B agree:
-// the splat puts atom 2 m + l / 32 in slot l / 32 of step m; the adjoint
-// puts point k = 16 kap + 8 (l / 32) + e in slot e of its product kap, so
-// that each lane's grad_rho values are two runs of 8 points of one column,
-// loaded once into registers.
+// A 16-bit split writes an FP32 value x (scaled into the 16-bit range by a
+// power of two) as hi + lo, hi = fp16(x), lo = fp16(x - hi): 22 significant
+// bits.  A product of two split values is hi hi' + hi lo' + lo hi' (the
+// dropped lo lo' is 2^-22 of it), each exact in the FP32 accumulation.
+//
+// Operand layout of v_mfma_f32_32x32x8f16 (C = A B + C, A 32x8, B 8x32):
+// element e of lane l is K slot 4 (l / 32) + e of both A (row l % 32) and B
+// (column l % 32); after the call lane l holds C[i][l % 32] for
+// i = 8 (r / 4) + 4 (l / 32) + r % 4 in its accumulator element r = 0 .. 15.
+// v_mfma_f32_32x32x16_f16 has the same C layout, with 8 K slots per lane
+// (slot 8 (l / 32) + e).  Which reduction index sits in which K slot is free
+// as long as A and B agree: the splat puts atom 4 (l / 32) + e of a step in
+// slot e; the adjoint puts point k = 16 kap + 8 (l / 32) + e in slot e of its
+// product kap, so that each lane's grad_rho values are two runs of 8 points
+// of one column, loaded once into registers.
 #include "splat_common.hpp"
 
 namespace hartree {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int mfma_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
@@ -150,25 +155,34 @@ __device__ __forceinline__ void more_images(const LaneAxis &la, const StagedG *a
     }
 }
 
-// LDS pitch of a staged atom's factor row (64 entries): the z entries of
-// atoms 2m and 2m + 1, read by the two lane halves together, fall in
-// different halves of the 64 banks
-constexpr int kFacPitch = 96;
-
-// Splat pipeline step: kSub atoms (kSub / 2 matrix products per tile).
-// While the products of step c run on the matrix cores, the wavefronts
-// evaluate the factors of step c + 1 into the other LDS buffer, so the
-// vector work fills the matrix cores' shadow.
+// Splat pipeline step: kSub atoms, one K = 8 product set per tile.  While
+// the products of step c run on the matrix cores, the wavefronts evaluate
+// the factors of step c + 1 into the other LDS buffer, so the vector work
+// fills the matrix cores' shadow.
 constexpr int kSub = 8;
 static_assert(kSub % 4 == 0 && kStage % kSub == 0, "pipeline step");
 
-// factors of staged atoms s0 .. s0 + kSub - 1 into dst (zeros past nb):
-// row s: W gx (entries 0 .. 15), gy (16 .. 31), gz (32 .. 63).  WIDE: some
-// window may hold several images of a point (otherwise the first image is
-// the only one, and the step stays one straight-line block)
+// One step's factors, entry-major so that a lane reads its four atoms of one
+// entry as one 16-byte (8-byte) vector: fxy[q][s] = 2^ea W gx (q < 16) or gy
+// (16 <= q < 32) of staged atom s of the step, zhi / zlo[k][s] the two halves
+// of the 16-bit split of 2^eb gz(k).
+struct SplatBuf {
+    float fxy[kMI + kMJ][kSub];
+    _Float16 zhi[kMK][kSub], zlo[kMK][kSub];
+};
+
+__device__ __forceinline__ void split16(float x, _Float16 &hi, _Float16 &lo)
+{
+    hi = _Float16(x);
+    lo = _Float16(x - float(hi));
+}
+
+// factors of staged atoms s0 .. s0 + kSub - 1 into buf (zeros past nb).
+// WIDE: some window may hold several images of a point (otherwise the first
+// image is the only one, and the step stays one straight-line block)
 template <bool WIDE>
-__device__ __forceinline__ void splat_factors(float (*dst)[kFacPitch], const StagedG *recs, const LaneAxis &la,
-                                              int s0, int nb, int wave, int lane)
+__device__ __forceinline__ void splat_factors(SplatBuf &buf, const StagedG *recs, const LaneAxis &la, int s0, int nb,
+                                              int wave, int lane, float ascale, float bscale)
 {
     constexpr int R = kSub / 4;  // atoms per wavefront
     float v[R], wv[R];
@@ -191,29 +205,89 @@ __device__ __forceinline__ void splat_factors(float (*dst)[kFacPitch], const Sta
             }
         }
     }
+    if (lane < kMI + kMJ) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) dst[wave + 4 * r][lane] = la.x == 0 ? v[r] * wv[r] : v[r];
-}
-
-// products of one step: atom 2 m + kk of the step in K slot kk
-__device__ __forceinline__ void splat_products(const float (*f)[kFacPitch], int kk, int col, int i0, int jj,
-                                               floatx16 &acc0, floatx16 &acc1)
-{
+        for (int r = 0; r < R; ++r) buf.fxy[lane][wave + 4 * r] = la.x == 0 ? v[r] * wv[r] * ascale : v[r];
+    } else {
+        const int k = lane - kMI - kMJ;
 #pragma unroll
-    for (int m = 0; m < kSub / 2; ++m) {
-        const int s = 2 * m + kk;
-        const float y = f[s][kMI + jj];
-        const float bv = f[s][kMI + kMJ + col];
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(f[s][i0] * y, bv, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(f[s][i0 + 2] * y, bv, acc1, 0, 0, 0);
+        for (int r = 0; r < R; ++r) split16(v[r] * bscale, buf.zhi[k][wave + 4 * r], buf.zlo[k][wave + 4 * r]);
     }
 }
 
+// the 16-bit split of the products x[e] y[e]: hi = fp16(p) of the FP32
+// product p, lo = fp16(x y - hi) with the residual exact (one fma).  p is
+// pinned in a register first: otherwise the compiler may form hi once as
+// fp16(p) and once as fp16(x y) (one rounding, by a mixed-precision fma),
+// and the two differ near rounding midpoints, which would leave an error of
+// one 16-bit ulp.
+__device__ __forceinline__ void split_products(const float4 &x, const float4 &y, half4 &hi, half4 &lo)
+{
+    const float xs[4] = {x.x, x.y, x.z, x.w}, ys[4] = {y.x, y.y, y.z, y.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        float p = xs[e] * ys[e];
+        asm("" : "+v"(p));
+        const _Float16 h = _Float16(p);
+        hi[e] = h;
+        lo[e] = _Float16(fmaf(xs[e], ys[e], -float(h)));
+    }
+}
+
+// products of one step: atom 4 kk + e of the step in K slot e of lane half
+// kk.  (hi + lo)(hi' + lo') without lo lo', the small terms first; the two
+// tiles' chains interleaved.
+__device__ __forceinline__ void splat_products(const SplatBuf &buf, int kk, int col, int i0, int jj, floatx16 &acc0,
+                                               floatx16 &acc1)
+{
+    const float4 y = *reinterpret_cast<const float4 *>(&buf.fxy[kMI + jj][4 * kk]);
+    const float4 x0 = *reinterpret_cast<const float4 *>(&buf.fxy[i0][4 * kk]);
+    const float4 x1 = *reinterpret_cast<const float4 *>(&buf.fxy[i0 + 2][4 * kk]);
+    const half4 bh = *reinterpret_cast<const half4 *>(&buf.zhi[col][4 * kk]);
+    const half4 bl = *reinterpret_cast<const half4 *>(&buf.zlo[col][4 * kk]);
+    half4 ah0, al0, ah1, al1;
+    split_products(x0, y, ah0, al0);
+    split_products(x1, y, ah1, al1);
+    acc0 = __builtin_amdgcn_mfma_f32_32x32x8f16(al0, bh, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_32x32x8f16(al1, bh, acc1, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_32x32x8f16(ah0, bl, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_32x32x8f16(ah1, bl, acc1, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_32x32x8f16(ah0, bh, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_32x32x8f16(ah1, bh, acc1, 0, 0, 0);
+}
+
+// Operand scales of the splat (uniform over a brick): the row operand
+// 2^ea W gx gy and the column operand 2^eb gz stay below 2^13, inside the
+// 16-bit range with room to spare, whatever the atoms' weights (W <= the
+// problem's largest weight wmax from the binning).  A factor is one Gaussian
+// (<= 1) unless the window is wider than the cell; then the periodic sum
+// over images is at most 1 + sqrt(2 pi) sigma / L.  The exponents are
+// clamped to +-60 (weights below 2^-47 lose relative precision).
+__device__ __forceinline__ void splat_scales(const SplatArgs &a, const ProbDesc &d, int prob, int &ea, int &eb)
+{
+    double g[3] = {1.0, 1.0, 1.0};
+    if (a.wide)
+        for (int x = 0; x < 3; ++x) g[x] = 1.0 + 2.5066282746310002 * a.max_sigma / d.L[x];
+    const double wb = a.qsum[a.nprob + prob] * g[0] * g[1];
+    int e = 0;
+    ea = 0;
+    if (wb > 0.0 && wb < 1.0e300) {
+        frexp(wb, &e);  // wb < 2^e
+        ea = 13 - e;
+    }
+    ea = ea < -60 ? -60 : (ea > 60 ? 60 : ea);
+    frexp(g[2], &e);
+    eb = 13 - e;
+    eb = eb < -60 ? -60 : eb;
+}
+
+// six workgroups per CU (80 registers): measured a little faster than the
+// compiler's choice of five
 template <bool WIDE>
-__global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
+__global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_splat_mfma(SplatArgs a)
 {
     __shared__ StagedG recs[kStage];
-    __shared__ float fac[2][kSub][kFacPitch];  // double buffer of pipeline steps
+    __shared__ SplatBuf fac[2];  // double buffer of pipeline steps
     const int64_t b = brick_of_block();
     const int prob = brick_prob(a, b);
     const ProbDesc &d = a.desc[prob];
@@ -227,14 +301,19 @@ __global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
     // i = 4 wave + 2 u + col / 16 and j = col % 16, for u = 0, 1
     const int i0 = 4 * wave + (col >> 4), jj = col & 15;
     const LaneAxis la = lane_axis(d, p, lane);
+    int ea, eb;
+    splat_scales(a, d, prob, ea, eb);
+    const float ascale = __builtin_ldexpf(1.0f, ea), bscale = __builtin_ldexpf(1.0f, eb);
+    const float unscale = __builtin_ldexpf(1.0f, -ea - eb);
 
-    // the accumulators start at the background -Q / Omega
+    // the accumulators start at the background -Q / Omega (scaled like the products)
     const float bg = a.subtract_background ? float(a.qsum[prob] / (d.L[0] * d.L[1] * d.L[2])) : 0.0f;
+    const float bgs = -bg * (ascale * bscale);
     floatx16 acc0, acc1;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        acc0[r] = -bg;
-        acc1[r] = -bg;
+        acc0[r] = bgs;
+        acc1[r] = bgs;
     }
 
     for (int blk = 0; blk < cnt; blk += kStage) {
@@ -242,10 +321,10 @@ __global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
         stage_g(recs, a, off, blk, nb, t);
         __syncthreads();
         const int nsub = (nb + kSub - 1) / kSub;
-        splat_factors<WIDE>(fac[0], recs, la, 0, nb, wave, lane);
+        splat_factors<WIDE>(fac[0], recs, la, 0, nb, wave, lane, ascale, bscale);
         __syncthreads();
         for (int c = 0; c + 1 < nsub; ++c) {
-            splat_factors<WIDE>(fac[(c + 1) & 1], recs, la, (c + 1) * kSub, nb, wave, lane);
+            splat_factors<WIDE>(fac[(c + 1) & 1], recs, la, (c + 1) * kSub, nb, wave, lane, ascale, bscale);
             splat_products(fac[c & 1], kk, col, i0, jj, acc0, acc1);
             __syncthreads();
         }
@@ -265,8 +344,8 @@ __global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
         for (int r = 0; r < 16; ++r) {
             const int c8 = 8 * (r >> 2) + (r & 3);  // mfma_row without the lane's 4 kk (never crosses a 16-row line)
             float *row = base + ((c8 >> 4) * sa + (c8 & 15) * sb);
-            row[loff] = acc0[r];
-            row[2 * sa + loff] = acc1[r];
+            row[loff] = acc0[r] * unscale;
+            row[2 * sa + loff] = acc1[r] * unscale;
         }
         return;
     }
@@ -278,8 +357,8 @@ __global__ __launch_bounds__(kMThreads) void k_splat_mfma(SplatArgs a)
         const int j = p.b1 * kMJ + (c & 15);
         const int ia = p.b0 * kMI + 4 * wave + (c >> 4);
         if (j < d.dims[1]) {
-            if (ia < d.dims[0]) out[(int64_t(ia) * d.dims[1] + j) * d.dims[2] + k] = acc0[r];
-            if (ia + 2 < d.dims[0]) out[(int64_t(ia + 2) * d.dims[1] + j) * d.dims[2] + k] = acc1[r];
+            if (ia < d.dims[0]) out[(int64_t(ia) * d.dims[1] + j) * d.dims[2] + k] = acc0[r] * unscale;
+            if (ia + 2 < d.dims[0]) out[(int64_t(ia + 2) * d.dims[1] + j) * d.dims[2] + k] = acc1[r] * unscale;
         }
     }
 }
@@ -296,12 +375,6 @@ struct AdjBuf {
     float gxy[kAdjGroup][kMI + kMJ + 1], gdxy[kAdjGroup][kMI + kMJ + 1];
     _Float16 bhi[2 * kAdjGroup][kBPitch], blo[2 * kAdjGroup][kBPitch];
 };
-
-__device__ __forceinline__ void split16(float x, _Float16 &hi, _Float16 &lo)
-{
-    hi = _Float16(x);
-    lo = _Float16(x - float(hi));
-}
 
 // factors of staged atoms s0 .. s0 + kAdjGroup - 1 into buf (zeros past nb)
 template <bool WIDE>
