@@ -206,8 +206,7 @@ hartree_status hartree_profile_end(hartree_plan plan, double *total_ms, int64_t 
 
 /* Atom binning shared by a splat and its adjoint.  hartree_splat and
  * hartree_splat_adjoint each bin their atoms into bricks of the grid (sorted
- * per-brick lists with per-slot atom records (FP32) or per-atom 1-D factor
- * tables (FP64) in the workspace) before
+ * per-brick lists with per-slot atom records in the workspace) before
  * their main kernels.  When both run on the same atoms -- a forward splat and
  * the backward pass of the same positions -- the binning can be done once:
  *   hartree_atoms_bind  bins the atoms (same arguments as hartree_splat) and

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhartree.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["api.hip", "fft_host.hip", "splat.hip", "splat_mfma.hip", "splat_general.hip", "partition.cpp"] + ["fft_%s_%s.hip" % (k, t) for k in ("a", "b", "r2c", "c2r") for t in ("f32", "f64")]
+SOURCES = ["api.hip", "fft_host.hip", "splat.hip", "splat_mfma.hip", "splat_mfma64.hip", "splat_general.hip", "partition.cpp"] + ["fft_%s_%s.hip" % (k, t) for k in ("a", "b", "r2c", "c2r") for t in ("f32", "f64")]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -41,7 +41,7 @@ def _hipcc() -> str:
 # per-source extra flags: the matrix-core kernels keep their accumulators in
 # ordinary vector registers (no copies out of the accumulation registers
 # before the vector code that folds the products)
-EXTRA_FLAGS = {"splat_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+EXTRA_FLAGS = {"splat_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"], "splat_mfma64.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _compile(src: str) -> str:

@@ -154,10 +154,9 @@ struct hartree_plan_s {
     int64_t max_parts = 0;  // E_H partial slots at one pencil per workgroup
     // workspace layout
     size_t o_status = 0, o_desc = 0, o_tw = 0, o_spec = 0, o_parts = 0, o_qsum = 0, o_info = 0, o_counts = 0,
-           o_offsets = 0, o_cursor = 0, o_list = 0, o_lists = 0, o_bpart = 0, o_slot = 0, o_tab = 0, o_rec = 0, o_zero = 0,
+           o_offsets = 0, o_cursor = 0, o_list = 0, o_lists = 0, o_bpart = 0, o_slot = 0, o_rec = 0, o_zero = 0,
            ws_size = 0;
     int32_t cap_pa = 0;
-    int32_t wcap = 0;  // per-atom factor table row length
     bool wide = false;  // some truncation window can hold two images of one grid point
     unsigned char *ws = nullptr;
     // profiling: events bracketing each kernel group
@@ -319,7 +318,6 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
     p->splat_ok = true;
     int64_t grid = 0, spec = 0, bricks = 0;
     int64_t cap_per_atom = 0;
-    int64_t wcap = 1;
     for (int q = 0; q < nprob; ++q) {
         const double *A = cells + 9 * q;
         const int32_t *N = dims + 3 * q;
@@ -447,7 +445,10 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
         }
         p->max_parts += int64_t(N[1]) * d.dims[3];
         // splat bricks
-        const int bsz[3] = {p->fp64 ? kBI : kMI, p->fp64 ? kBJ : kMJ, p->fp64 ? kBK : kMK};
+        // (FP64 plans with a non-diagonal cell keep the smaller bricks of the
+        // point-by-point kernels)
+        const bool small = p->fp64 && any_general;
+        const int bsz[3] = {small ? kBI : kMI, small ? kBJ : kMJ, small ? kBK : kMK};
         int64_t per_atom = 1;
         for (int x = 0; x < 3; ++x) {
             d.bsz[x] = bsz[x];
@@ -464,8 +465,6 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
                 const int64_t bnd = int64_t(std::ceil((w - 1.0) / bsz[x])) + 2;
                 if (bnd < nbx) nbx = bnd;
             }
-            // factor table row: one entry per point of the touched bricks
-            if (nbx * bsz[x] > wcap) wcap = nbx * bsz[x];
             per_atom *= nbx;
         }
         d.brick_off = bricks;
@@ -479,7 +478,6 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
     p->nbricks = p->splat_ok ? bricks : 0;
     p->capacity = p->splat_ok ? int64_t(p->max_atoms) * cap_per_atom : 0;
     p->cap_pa = int32_t(cap_per_atom);
-    p->wcap = int32_t(wcap);
     if (p->capacity > int64_t(INT32_MAX)) {
         const int64_t cap = p->capacity;
         delete p;
@@ -510,8 +508,7 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
         p->o_lists = take(4 * size_t(p->capacity));
         p->o_bpart = take(24 * size_t(p->capacity));
         p->o_slot = take(4 * size_t(p->capacity));
-        if (!p->fp64 && !p->general) p->o_rec = take(sizeof(SlotAtom) * size_t(p->capacity));
-        if (p->fp64 && !p->general) p->o_tab = take(16 * size_t(p->max_atoms) * 3 * size_t(p->wcap));
+        if (!p->general) p->o_rec = take((p->fp64 ? sizeof(SlotAtom64) : sizeof(SlotAtom)) * size_t(p->capacity));
     }
     p->ws_size = o;
     *out = p;
@@ -660,6 +657,7 @@ SplatArgs splat_args(hartree_plan p, int32_t natoms, const double *pos, const do
     a.bpart = reinterpret_cast<double *>(p->ws + p->o_bpart);
     a.slot_of = reinterpret_cast<int32_t *>(p->ws + p->o_slot);
     a.rec = (p->fp64 || p->general) ? nullptr : reinterpret_cast<SlotAtom *>(p->ws + p->o_rec);
+    a.rec64 = (!p->fp64 || p->general) ? nullptr : reinterpret_cast<SlotAtom64 *>(p->ws + p->o_rec);
     a.general = p->general ? 1 : 0;
     a.wide = p->wide ? 1 : 0;
     // |g|, |gd| of a c-axis factor stay below 4 max(1, max_sigma) (a few
@@ -677,8 +675,6 @@ SplatArgs splat_args(hartree_plan p, int32_t natoms, const double *pos, const do
     }
     a.zeros = reinterpret_cast<const float *>(p->ws + p->o_zero);
     a.cap_pa = p->cap_pa;
-    a.tab = p->ws + p->o_tab;
-    a.wcap = p->wcap;
     a.capacity = p->capacity;
     a.nbricks_total = p->nbricks;
     a.status = reinterpret_cast<DeviceStatus *>(p->ws + p->o_status);
@@ -947,12 +943,13 @@ hartree_status hartree_splat_adjoint_bound(hartree_plan plan, uint64_t token, co
     if (!grad_rho || (a.natoms > 0 && !grad_pos)) return fail(HARTREE_ERR_ARG, "grad_rho or grad_pos is NULL");
     a.grad_rho = grad_rho;
     a.grad_pos = grad_pos;
-    // float4 row loads when every problem's rows are whole, aligned vectors
-    a.grad_rows_vec4 = 0;
-    if (!plan->fp64 && reinterpret_cast<uintptr_t>(grad_rho) % 16 == 0) {
-        a.grad_rows_vec4 = 1;
+    // 16-byte row loads when every problem's rows are whole, aligned vectors
+    a.grad_rows_vec16 = 0;
+    if (reinterpret_cast<uintptr_t>(grad_rho) % 16 == 0) {
+        const int per = plan->fp64 ? 2 : 4;  // elements per 16-byte vector
+        a.grad_rows_vec16 = 1;
         for (const ProbDesc &d : plan->desc)
-            if (d.dims[2] % 4 != 0 || d.grid_off % 4 != 0) a.grad_rows_vec4 = 0;
+            if (d.dims[2] % per != 0 || d.grid_off % per != 0) a.grad_rows_vec16 = 0;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = timed(plan, HARTREE_K_ADJOINT, s, [&]() { return run_adjoint(a, s); });

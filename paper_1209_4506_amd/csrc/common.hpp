@@ -78,12 +78,11 @@ struct ProbDesc {
     int32_t pad3;
 };
 
-// Splat bricks, one workgroup each: BI x BJ x BK grid points for the FP64
-// (vector-unit) kernels, MI x MJ x MK for the FP32 (matrix-core) kernels.
+// Splat bricks, one workgroup each: MI x MJ x MK grid points for the
+// matrix-core kernels (diagonal cells), BI x BJ x BK for the FP64
+// point-by-point kernels of any other cell.
 constexpr int kBI = 8, kBJ = 8, kBK = 32;
 constexpr int kMI = 16, kMJ = 16, kMK = 32;
-constexpr int kBrickThreads = 256;   // 64 columns x 4 k-strips
-constexpr int kStrip = kBK / 4;      // points per thread along k
 
 // Per-atom data prepared on the device before binning.
 struct AtomInfo {
@@ -114,6 +113,20 @@ struct SlotAtom {
     float w;        // Z (2 pi sigma^2)^(-3/2)
     int32_t atom;   // the atom's index ...
     int32_t touch;  // ... and this brick's place in its enumeration of touched bricks
+};
+
+// The same for the FP64 splat kernels, in double precision: the unwrapped
+// offset r has grid index lo + r and displacement (lo + r) h - X.
+struct SlotAtom64 {
+    double X[3];     // the wrapped position per axis
+    double inv2s2;   // 1 / (2 sigma^2): the 1-D factor is exp(-d^2 inv2s2)
+    double w;        // Z (2 pi sigma^2)^(-3/2)
+    int32_t lo[3];   // window start per axis (unwrapped grid index)
+    int32_t r0[3];   // offset of the brick's first point from the window start, mod n
+    int32_t wl[3];   // window width in points; 0 for an atom that touches nothing
+    int32_t atom;    // the atom's index ...
+    int32_t touch;   // ... and this brick's place in its enumeration of touched bricks
+    int32_t pad;
 };
 
 struct DeviceStatus {

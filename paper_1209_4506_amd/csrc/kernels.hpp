@@ -73,8 +73,9 @@ struct SplatArgs {
     int32_t *list_sorted;   // capacity
     int32_t *slot_of;       // max_atoms x cap_pa: sorted-list slot of each (atom, touched brick)
     SlotAtom *rec;          // capacity (FP32 plans): the sorted lists' atoms relative to their brick
+    SlotAtom64 *rec64;      // capacity (FP64 plans): the same in double precision
     double *bpart;          // capacity x 3 (adjoint partials): per list slot, or per (atom, touched brick)
-                            // (atom * cap_pa + touch) where the per-slot records exist (rec != nullptr)
+                            // (atom * cap_pa + touch) where the per-slot records exist (rec or rec64)
     int64_t capacity;
     int32_t cap_pa;         // most bricks one atom can touch
     int64_t nbricks_total;
@@ -87,12 +88,10 @@ struct SplatArgs {
     int32_t b_exp;          // FP32 adjoint: the c-axis factors enter the 16-bit products scaled by 2^b_exp
     void *rho;              // splat output grid
     const void *grad_rho;   // adjoint input grid
-    int32_t grad_rows_vec4; // every problem's grad_rho rows start 16-byte aligned with Nc % 4 == 0
+    int32_t grad_rows_vec16;  // every problem's grad_rho rows are whole 16-byte vectors from a 16-byte aligned start
     const float *zeros;     // 64 zero floats in the workspace (never written by kernels)
     double *grad_pos;       // adjoint output
     double *qsum;           // 2 nprob: total charge per problem, then the largest atom weight per problem
-    void *tab;              // per-atom 1-D factor tables: max_atoms x 3 x wcap pairs (g, gd) of the precision
-    int32_t wcap;           // table row length
 };
 
 hipError_t run_bin(const SplatArgs &a, hipStream_t s);
@@ -101,6 +100,8 @@ hipError_t run_adjoint(const SplatArgs &a, hipStream_t s);
 hipError_t run_adjoint_final(const SplatArgs &a, hipStream_t s);
 hipError_t run_gather_mfma(const SplatArgs &a, hipStream_t s);
 hipError_t run_adjoint_mfma(const SplatArgs &a, hipStream_t s);
+hipError_t run_gather_mfma64(const SplatArgs &a, hipStream_t s);
+hipError_t run_adjoint_mfma64(const SplatArgs &a, hipStream_t s);
 hipError_t run_gather_general(const SplatArgs &a, hipStream_t s);
 hipError_t run_adjoint_general(const SplatArgs &a, hipStream_t s);
 

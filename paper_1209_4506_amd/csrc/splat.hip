@@ -2,10 +2,10 @@
 //
 // The density of each atom is a product of three 1-D periodic Gaussians in
 // an orthorhombic cell, so every contribution factorizes into per-axis
-// tables.  The grid is cut into bricks of 8 x 8 x 32 points in FP64 and
-// 16 x 16 x 32 in FP32 (the analogue of
-// the paper's structure A / structure C idea, Sec. 3.2.2: the points touched
-// by one atom's sphere, and a box around a group of atoms); each brick is one
+// factors.  The grid is cut into bricks of 16 x 16 x 32 points (8 x 8 x 32 in
+// FP64 plans with a non-diagonal cell; the analogue of the paper's
+// structure A / structure C idea, Sec. 3.2.2: the points touched by one
+// atom's sphere, and a box around a group of atoms); each brick is one
 // workgroup that gathers the atoms whose truncation window overlaps it.
 //
 // Binning is deterministic: every atom adds itself to the bricks its window
@@ -91,44 +91,6 @@ __device__ __forceinline__ AtomInfo atom_prep(const SplatArgs &a, int atom, bool
     in.w = z * pow(6.283185307179586476925286766559 * s * s, -1.5);
     in.inv2s2 = 1.0 / (2.0 * s * s);
     return in;
-}
-
-// Per-atom 1-D factor tables (see splat_common.hpp): one thread per
-// (atom, axis, entry).  The displacement is formed in double and the
-// exponential evaluated in the working precision.
-template <typename T>
-__global__ __launch_bounds__(256) void k_atom_tables(SplatArgs a)
-{
-    const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    const int64_t rowlen = a.wcap;
-    if (e >= int64_t(a.natoms) * 3 * rowlen) return;
-    const int t = int(e % rowlen);
-    const int x = int((e / rowlen) % 3);
-    const int atom = int(e / (3 * rowlen));
-    const AtomInfo in = a.info[atom];
-    const ProbDesc &d = a.desc[in.prob];
-    const int n = d.dims[x], bsz = d.bsz[x];
-    const int lo = in.lo[x], hi = in.hi[x];
-    int st, ct;
-    axis_bricks(lo, hi, n, bsz, d.nbricks[x], st, ct);
-    const int u = t / bsz;
-    if (u >= ct) return;  // never read
-    int sb = st + u;
-    if (sb >= d.nbricks[x]) sb -= d.nbricks[x];
-    const int ig = sb * bsz + (t - u * bsz);
-    const double h = d.L[x] / n;
-    T g = T(0), gd = T(0);
-    if (ig < n) {
-        // every unwrapped index congruent to ig inside the window
-        for (int ip = lo + wrapi(ig - lo, n); ip <= hi; ip += n) {
-            const double dd = double(ip) * h - in.X[x];
-            const T dt = T(dd);
-            const T ev = expT<T>(-dt * dt * T(in.inv2s2));
-            g += ev;
-            gd += ev * dt;
-        }
-    }
-    reinterpret_cast<Cx<T> *>(a.tab)[e] = Cx<T>{g, gd};
 }
 
 // Bricks touched by one atom, enumerated t = 0 .. ntouch-1 in a fixed order:
@@ -437,7 +399,26 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a, int rank_words)
         const int ti = touch_index(t, d, b - d.brick_off);
         // with records, the adjoint writes its partials under (atom, touch)
         // directly; otherwise the slot map leads the reduction to them
-        if (!a.rec) a.slot_of[int64_t(v) * a.cap_pa + ti] = int32_t(off + rank);
+        if (!a.rec && !a.rec64) a.slot_of[int64_t(v) * a.cap_pa + ti] = int32_t(off + rank);
+        if (a.rec64) {
+            // the atom relative to this brick, for the FP64 splat kernels
+            const int64_t lb = b - d.brick_off;
+            const int bc[3] = {int(lb / (int64_t(d.nbricks[2]) * d.nbricks[1])),
+                               int((lb / d.nbricks[2]) % d.nbricks[1]), int(lb % d.nbricks[2])};
+            SlotAtom64 r;
+            for (int x = 0; x < 3; ++x) {
+                r.X[x] = in.X[x];
+                r.lo[x] = in.lo[x];
+                r.r0[x] = wrapi(bc[x] * d.bsz[x] - in.lo[x], d.dims[x]);
+                r.wl[x] = in.hi[x] >= in.lo[x] ? in.hi[x] - in.lo[x] + 1 : 0;
+            }
+            r.inv2s2 = in.inv2s2;
+            r.w = in.w;
+            r.atom = v;
+            r.touch = ti;
+            r.pad = 0;
+            a.rec64[off + rank] = r;
+        }
         if (a.rec) {
             // the atom relative to this brick, for the FP32 splat kernels
             const int64_t lb = b - d.brick_off;
@@ -462,192 +443,6 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a, int rank_words)
     }
 }
 
-// Factor entries of the staged atoms 0 .. nc-1 over one brick, from the
-// per-atom tables: kBI entries along a (times the weight W when WEIGHT), kBJ
-// along b and kBK along c, and the displacement-weighted entries too when D.
-// Every thread issues all its table loads before it stores any entry, so the
-// loads are in flight together.
-template <typename T, bool D, bool WEIGHT>
-__device__ __forceinline__ void fill_factors(const SplatArgs &a, const StagedAtom *atoms, int nc, int nb0, int nb1,
-                                             int nb2, int bi, int bj, int bk, T (*gx)[kBI], T (*gdx)[kBI],
-                                             T (*gy)[kBJ], T (*gdy)[kBJ], T (*gz)[kBK], T (*gdz)[kBK], int t)
-{
-    constexpr int E = kBI + kBJ + kBK;
-    constexpr int R = (kChunk * E + kBrickThreads - 1) / kBrickThreads;
-    static_assert(kBI == kBJ, "a and b share one brick edge");
-    Cx<T> v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int e = t + r * kBrickThreads;
-        const bool ok = e < nc * E;
-        const int s = ok ? e / E : 0;
-        const int q = ok ? e - s * E : 0;
-        const int x = q < kBI ? 0 : (q < kBI + kBJ ? 1 : 2);
-        const int qq = q - (x == 0 ? 0 : (x == 1 ? kBI : kBI + kBJ));
-        const int nb = x == 0 ? nb0 : (x == 1 ? nb1 : nb2);
-        const int bx = x == 0 ? bi : (x == 1 ? bj : bk);
-        v[r] = table_factor<T>(a, nb, x == 2 ? kBK : kBI, bx, qq, atoms[s], x, ok);
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int e = t + r * kBrickThreads;
-        if (e < nc * E) {
-            const int s = e / E, q = e - s * E;
-            if (q < kBI) {
-                gx[s][q] = WEIGHT ? v[r].x * T(atoms[s].w) : v[r].x;
-                if (D) gdx[s][q] = v[r].y;
-            } else if (q < kBI + kBJ) {
-                gy[s][q - kBI] = v[r].x;
-                if (D) gdy[s][q - kBI] = v[r].y;
-            } else {
-                gz[s][q - kBI - kBJ] = v[r].x;
-                if (D) gdz[s][q - kBI - kBJ] = v[r].y;
-            }
-        }
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBrickThreads) void k_splat_gather(SplatArgs a, const double *qsum)
-{
-    __shared__ StagedAtom atoms[kChunk];
-    __shared__ T gx[kChunk][kBI], gy[kChunk][kBJ];
-    __shared__ __align__(16) T gz[kChunk][kBK];
-    const int64_t b = blockIdx.x;
-    const int prob = brick_prob(a, b);
-    const ProbDesc &d = a.desc[prob];
-    const int lb = int(b - d.brick_off);  // bricks of one problem fit 32 bits
-    const int bk = lb % d.nbricks[2];
-    const int bij = lb / d.nbricks[2];
-    const int bj = bij % d.nbricks[1];
-    const int bi = bij / d.nbricks[1];
-    const int nb0 = d.nbricks[0], nb1 = d.nbricks[1], nb2 = d.nbricks[2];
-    const int t = threadIdx.x;
-    const int ci = (t & 63) >> 3, cj = t & 7, strip = t >> 6;
-    const int i = bi * kBI + ci, j = bj * kBJ + cj, k0 = bk * kBK + strip * kStrip;
-    const int64_t off = a.offsets[b];
-    const int cnt = int(a.offsets[b + 1] - off);
-
-    T acc[kStrip];
-#pragma unroll
-    for (int r = 0; r < kStrip; ++r) acc[r] = T(0);
-
-    for (int c0 = 0; c0 < cnt; c0 += kChunk) {
-        const int nc = (cnt - c0) < kChunk ? (cnt - c0) : kChunk;
-        // tables: per atom 8 + 8 + 32 entries
-        stage_atoms(atoms, a, d, off, c0, nc, t);
-        __syncthreads();
-        fill_factors<T, false, true>(a, atoms, nc, nb0, nb1, nb2, bi, bj, bk, gx, nullptr, gy, nullptr, gz, nullptr,
-                                     t);
-        __syncthreads();
-        for (int s = 0; s < nc; ++s) {
-            const T c = gx[s][ci] * gy[s][cj];
-#pragma unroll
-            for (int r = 0; r < kStrip; ++r) acc[r] += c * gz[s][strip * kStrip + r];
-        }
-        __syncthreads();
-    }
-    if (i >= d.dims[0] || j >= d.dims[1]) return;
-    const T bg = a.subtract_background ? T(qsum[prob] / (d.L[0] * d.L[1] * d.L[2])) : T(0);
-    T *out = reinterpret_cast<T *>(a.rho) + d.grid_off + (int64_t(i) * d.dims[1] + j) * d.dims[2];
-#pragma unroll
-    for (int r = 0; r < kStrip; ++r)
-        if (k0 + r < d.dims[2]) out[k0 + r] = acc[r] - bg;
-}
-
-// Adjoint on the vector units (FP64), per brick of 8 x 8 columns by 32
-// points, as two contractions with no cross-lane reductions:
-//   A  thread = column c (its 32 grad_rho values in registers) for atoms
-//      s = wave, wave + 4, ...:  S0[c][s] = sum_k g[c][k] gz_s(k) and
-//      S1[c][s] = sum_k g[c][k] gdz_s(k) (gz, gdz broadcast from LDS);
-//   B  thread = (atom s, component x):  F_x = sum_i X_i sum_j Y_j S[(i, j)][s]
-//      with (X, Y, S) = (gdx, gy, S0), (gx, gdy, S0), (gx, gy, S1),
-//      written as the atom's partial for this brick.
-template <typename T>
-__global__ __launch_bounds__(kBrickThreads) void k_splat_adjoint(SplatArgs a)
-{
-    constexpr int NC = kBI * kBJ;   // columns per brick
-    constexpr int GP = kBK + 1;     // grad_rho tile pitch
-    constexpr int SP = kChunk + 1;  // S pitch
-    static_assert(NC == 64 && kBrickThreads == 4 * NC, "one column per lane, four wavefronts");
-    __shared__ StagedAtom atoms[kChunk];
-    __shared__ T gx[kChunk][kBI], gdx[kChunk][kBI], gy[kChunk][kBJ], gdy[kChunk][kBJ];
-    __shared__ __align__(16) T gz[kChunk][kBK];
-    __shared__ __align__(16) T gdz[kChunk][kBK];
-    __shared__ T tile[NC * (GP > SP ? GP : SP)];  // the grad_rho tile, then S0
-    __shared__ T s1t[NC * SP];
-    const int64_t b = blockIdx.x;
-    const int prob = brick_prob(a, b);
-    const ProbDesc &d = a.desc[prob];
-    const int lb = int(b - d.brick_off);  // bricks of one problem fit 32 bits
-    const int bk = lb % d.nbricks[2];
-    const int bij = lb / d.nbricks[2];
-    const int bj = bij % d.nbricks[1];
-    const int bi = bij / d.nbricks[1];
-    const int nb0 = d.nbricks[0], nb1 = d.nbricks[1], nb2 = d.nbricks[2];
-    const int t = threadIdx.x;
-    const int c = t & 63, w = t >> 6;
-    const int64_t off = a.offsets[b];
-    const int cnt = int(a.offsets[b + 1] - off);
-    if (cnt == 0) return;
-
-    // grad_rho tile (zero outside the grid): consecutive threads read
-    // consecutive points of a column
-    {
-        const T *src = reinterpret_cast<const T *>(a.grad_rho) + d.grid_off;
-        for (int e = t; e < NC * kBK; e += kBrickThreads) {
-            const int cc = e / kBK, k = e - cc * kBK;
-            const int i = bi * kBI + (cc >> 3), j = bj * kBJ + (cc & 7), kk = bk * kBK + k;
-            const bool in = i < d.dims[0] && j < d.dims[1] && kk < d.dims[2];
-            tile[cc * GP + k] = in ? src[(int64_t(i) * d.dims[1] + j) * d.dims[2] + kk] : T(0);
-        }
-    }
-    __syncthreads();
-    T g[kBK];
-#pragma unroll
-    for (int k = 0; k < kBK; ++k) g[k] = tile[c * GP + k];
-    __syncthreads();  // the tile's space now holds S0
-    T *s0t = tile;
-
-    for (int c0 = 0; c0 < cnt; c0 += kChunk) {
-        const int nc = (cnt - c0) < kChunk ? (cnt - c0) : kChunk;
-        stage_atoms(atoms, a, d, off, c0, nc, t);
-        __syncthreads();
-        fill_factors<T, true, false>(a, atoms, nc, nb0, nb1, nb2, bi, bj, bk, gx, gdx, gy, gdy, gz, gdz, t);
-        __syncthreads();
-        // A: contraction along k
-        for (int s = w; s < nc; s += 4) {
-            T a0 = T(0), a1 = T(0);
-#pragma unroll
-            for (int k = 0; k < kBK; ++k) {
-                a0 += g[k] * gz[s][k];
-                a1 += g[k] * gdz[s][k];
-            }
-            s0t[c * SP + s] = a0;
-            s1t[c * SP + s] = a1;
-        }
-        __syncthreads();
-        // B: the transverse factors, per (atom, component)
-        if (t < 3 * nc) {
-            const int s = t / 3, x = t - 3 * s;
-            const T *X = x == 0 ? gdx[s] : gx[s];
-            const T *Y = x == 1 ? gdy[s] : gy[s];
-            const T *S = (x == 2 ? s1t : s0t) + s;
-            T f = T(0);
-#pragma unroll
-            for (int i = 0; i < kBI; ++i) {
-                T inner = T(0);
-#pragma unroll
-                for (int j = 0; j < kBJ; ++j) inner += Y[j] * S[(i * kBJ + j) * SP];
-                f += X[i] * inner;
-            }
-            const int64_t slot = off + c0 + s;
-            if (slot < a.capacity) a.bpart[slot * 3 + x] = double(f);
-        }
-        __syncthreads();
-    }
-}
-
 // one wavefront per atom: lanes sum its per-brick partials (slots from the
 // sort) in a fixed order, then a fixed butterfly combines the lanes
 __global__ __launch_bounds__(256) void k_adjoint_final(SplatArgs a)
@@ -660,7 +455,7 @@ __global__ __launch_bounds__(256) void k_adjoint_final(SplatArgs a)
     const Touch t = atom_touch(in, d);
     const int nt = t.ntouch();
     double f0 = 0.0, f1 = 0.0, f2 = 0.0;
-    if (a.rec) {
+    if (a.rec || a.rec64) {
         // partials stored per (atom, touched brick): one contiguous row
         const double *row = a.bpart + int64_t(atom) * a.cap_pa * 3;
         for (int i = lane; i < nt; i += 64) {
@@ -701,14 +496,8 @@ hipError_t run_bin(const SplatArgs &a, hipStream_t s)
 {
     const int64_t nbt = a.nbricks_total;
     const int nw = int((a.natoms + 3) / 4);  // one wavefront per atom
-    if (a.natoms > 0) {
-        // FP64 kernels read per-atom factor tables; the FP32 matrix-core
-        // kernels evaluate the factors themselves
-        const int nt = int((int64_t(a.natoms) * 3 * a.wcap + 255) / 256);
-        // the count pass prepares the atoms (AtomInfo): it runs first
-        hipLaunchKernelGGL(k_brick_visit<0>, dim3(nw), dim3(256), 0, s, a);
-        if (a.fp64 && !a.general) hipLaunchKernelGGL(k_atom_tables<double>, dim3(nt), dim3(256), 0, s, a);
-    }
+    // the count pass prepares the atoms (AtomInfo): it runs first
+    if (a.natoms > 0) hipLaunchKernelGGL(k_brick_visit<0>, dim3(nw), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, a);
     if (a.natoms > 0) hipLaunchKernelGGL(k_brick_visit<1>, dim3(nw), dim3(256), 0, s, a);
     int span = 0;
@@ -720,21 +509,19 @@ hipError_t run_bin(const SplatArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-// FP32 runs on the matrix cores (splat_mfma.hip); FP64 on the vector units
+// diagonal cells run on the matrix cores (splat_mfma.hip: FP32,
+// splat_mfma64.hip: FP64); any other cell evaluates the Gaussians point by
+// point (splat_general.hip)
 hipError_t run_gather(const SplatArgs &a, hipStream_t s)
 {
     if (a.general) return run_gather_general(a, s);
-    if (!a.fp64) return run_gather_mfma(a, s);
-    hipLaunchKernelGGL(k_splat_gather<double>, dim3(int(a.nbricks_total)), dim3(kBrickThreads), 0, s, a, a.qsum);
-    return hipGetLastError();
+    return a.fp64 ? run_gather_mfma64(a, s) : run_gather_mfma(a, s);
 }
 
 hipError_t run_adjoint(const SplatArgs &a, hipStream_t s)
 {
     if (a.general) return run_adjoint_general(a, s);
-    if (!a.fp64) return run_adjoint_mfma(a, s);
-    hipLaunchKernelGGL(k_splat_adjoint<double>, dim3(int(a.nbricks_total)), dim3(kBrickThreads), 0, s, a);
-    return hipGetLastError();
+    return a.fp64 ? run_adjoint_mfma64(a, s) : run_adjoint_mfma(a, s);
 }
 
 hipError_t run_adjoint_final(const SplatArgs &a, hipStream_t s)

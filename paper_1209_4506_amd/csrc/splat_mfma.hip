@@ -41,31 +41,11 @@ typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int mfma_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
-// brick index with consecutive bricks (which share cache lines at their
-// edges along c) kept on one XCD
-__device__ __forceinline__ int64_t brick_of_block() { return xcd_remap(blockIdx.x, gridDim.x); }
-
 constexpr int kMThreads = 256;   // four wavefronts per brick
 constexpr int kAdjGroup = 16;    // atoms per MFMA column tile: 16 atoms x (g, gd)
 constexpr int kStage = 128;      // atom records staged at once (whole lists, almost always)
 static_assert(kStage % kAdjGroup == 0 && kStage <= kMThreads, "record staging");
 constexpr int kRow = kMI + kMJ + kMK;  // table entries one atom needs in one brick
-
-// A brick's position (brick index per axis), kept in registers
-struct BrickPos {
-    int b0, b1, b2;
-};
-
-__device__ __forceinline__ BrickPos brick_pos(const ProbDesc &d, int64_t b)
-{
-    const int lb = int(b - d.brick_off);  // bricks of one problem fit 32 bits
-    BrickPos p;
-    p.b2 = lb % d.nbricks[2];
-    const int bij = lb / d.nbricks[2];
-    p.b1 = bij % d.nbricks[1];
-    p.b0 = bij / d.nbricks[1];
-    return p;
-}
 
 // The brick's 1-D factors are evaluated on the fly from the atoms' SlotAtom
 // records (written by the binning sort): along axis x, brick point q has
@@ -706,9 +686,9 @@ hipError_t run_gather_mfma(const SplatArgs &a, hipStream_t s)
 hipError_t run_adjoint_mfma(const SplatArgs &a, hipStream_t s)
 {
     const dim3 grid(int(a.nbricks_total)), block(kMThreads);
-    if (a.grad_rows_vec4 && !a.wide)
+    if (a.grad_rows_vec16 && !a.wide)
         hipLaunchKernelGGL((k_adjoint_mfma<true, false>), grid, block, 0, s, a);
-    else if (a.grad_rows_vec4)
+    else if (a.grad_rows_vec16)
         hipLaunchKernelGGL((k_adjoint_mfma<true, true>), grid, block, 0, s, a);
     else if (!a.wide)
         hipLaunchKernelGGL((k_adjoint_mfma<false, false>), grid, block, 0, s, a);

@@ -319,14 +319,15 @@ def test_binding_pairs(H, prec, case):
     """hartree_atoms_pairs equals the number of (atom, brick) pairs that the
     truncation windows define: per axis the bricks holding a grid index of
     [ceil((X - rc) / h), floor((X + rc) / h)] taken modulo the axis length
-    (bricks of 16 x 16 x 32 points in FP32, 8 x 8 x 32 in FP64)."""
+    (bricks of 16 x 16 x 32 points in both precisions for these diagonal
+    cells)."""
     say("case binding pairs", prec, case)
     p = SPLAT_CASES[case]()
     plan = H.Plan(p.cell, p.dims, precision=prec, max_atoms=p.natoms)
     pos, Z, sig = _atoms(p)
     plan.bind_atoms(pos, Z, sig)
     got = plan.atoms_pairs()
-    bsz = (16, 16, 32) if prec == "fp32" else (8, 8, 32)
+    bsz = (16, 16, 32)
     rc_sig = 6.0 if prec == "fp32" else 8.0
     L = np.diag(p.cell)
     want = 0
