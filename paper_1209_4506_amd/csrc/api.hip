@@ -1255,6 +1255,23 @@ hartree_status hartree_plan_tune(hartree_plan plan, void *grid, int32_t reps, vo
     std::vector<int32_t> cfg;
     get_config(plan, cfg);
     hartree_status result = HARTREE_OK;
+    // time the passes along axis x under configuration c (reps runs after a
+    // warm-up); false when c does not apply
+    auto time_axis = [&](int x, const std::vector<int32_t> &c, float &ms) -> bool {
+        ms = 0.0f;
+        if (apply_config(plan, c.data()) != HARTREE_OK) return false;
+        hipError_t e = run_axis(plan, x, grid, s);  // warm-up (and attribute opt-in)
+        if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+        for (int i = 0; i < reps && e == hipSuccess; ++i) e = run_axis(plan, x, grid, s);
+        if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+        if (e != hipSuccess) {
+            result = hip_fail(e, "timing a pass candidate");
+            return false;
+        }
+        return true;
+    };
     // one key per (axis, length): every problem with that length takes the choice
     for (int x = 2; x >= 0 && result == HARTREE_OK; --x) {
         std::vector<int> lengths;
@@ -1283,17 +1300,10 @@ hartree_status hartree_plan_tune(hartree_plan plan, void *grid, int32_t reps, vo
                         trial[3 * (3 * q + x) + 1] = c.lp;
                         trial[3 * (3 * q + x) + 2] = c.pad;
                     }
-                if (apply_config(plan, trial.data()) != HARTREE_OK) continue;
-                hipError_t e = run_axis(plan, x, grid, s);  // warm-up (and attribute opt-in)
-                if (e == hipSuccess) e = hipEventRecord(ev[0], s);
-                for (int i = 0; i < reps && e == hipSuccess; ++i) e = run_axis(plan, x, grid, s);
-                if (e == hipSuccess) e = hipEventRecord(ev[1], s);
-                if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
                 float ms = 0.0f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
-                if (e != hipSuccess) {
-                    result = hip_fail(e, "timing a pass candidate");
-                    break;
+                if (!time_axis(x, trial, ms)) {
+                    if (result != HARTREE_OK) break;
+                    continue;
                 }
                 if (best == 0.0f || ms < best) {
                     best = ms;

@@ -145,11 +145,15 @@ static_assert(kSub % 4 == 0 && kStage % kSub == 0, "pipeline step");
 // One step's factors, entry-major so that a lane reads its four atoms of one
 // entry as one 16-byte (8-byte) vector: fxy[q][s] = 2^ea W gx (q < 16) or gy
 // (16 <= q < 32) of staged atom s of the step, zhi / zlo[k][s] the two halves
-// of the 16-bit split of 2^eb gz(k).
+// of the 16-bit split of 2^eb gz(k).  Rows of 12 entries: the factor stage's
+// stores of consecutive entries (one per lane) fall two to a bank at most
+// (one for the 16-bit rows), and every read stays an aligned vector.
+constexpr int kFacPitch = 12;
 struct SplatBuf {
-    float fxy[kMI + kMJ][kSub];
-    _Float16 zhi[kMK][kSub], zlo[kMK][kSub];
+    float fxy[kMI + kMJ][kFacPitch];
+    _Float16 zhi[kMK][kFacPitch], zlo[kMK][kFacPitch];
 };
+static_assert(kFacPitch >= kSub && kFacPitch % 4 == 0, "aligned 4-entry reads");
 
 __device__ __forceinline__ void split16(float x, _Float16 &hi, _Float16 &lo)
 {
