@@ -91,6 +91,8 @@ struct AtomInfo {
     double inv2s2;   // 1 / (2 s^2)
     int32_t lo[3];   // unwrapped first grid index of the truncation window per axis
     int32_t hi[3];   // unwrapped last grid index
+    int32_t st[3];   // first brick the window touches per axis ...
+    int32_t ct[3];   // ... and the number of bricks it touches (0 for an invalid atom)
     int32_t prob;    // problem index (batched plans)
     int32_t pad;
 };

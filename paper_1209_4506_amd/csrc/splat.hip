@@ -52,6 +52,8 @@ __device__ __forceinline__ AtomInfo atom_prep(const SplatArgs &a, int atom, bool
             in.X[x] = 0.0;
             in.lo[x] = 1;
             in.hi[x] = 0;
+            in.st[x] = 0;
+            in.ct[x] = 0;
         }
         in.w = 0.0;
         in.inv2s2 = 0.0;
@@ -88,8 +90,10 @@ __device__ __forceinline__ AtomInfo atom_prep(const SplatArgs &a, int atom, bool
         }
         for (int c = 0; c < 3; ++c) in.X[c] = f[0] * d.A[c] + f[1] * d.A[3 + c] + f[2] * d.A[6 + c];
     }
-    in.w = z * pow(6.283185307179586476925286766559 * s * s, -1.5);
+    const double s2 = 6.283185307179586476925286766559 * s * s;  // (2 pi s^2)^(-3/2) without pow
+    in.w = z / (s2 * sqrt(s2));
     in.inv2s2 = 1.0 / (2.0 * s * s);
+    atom_bricks(in, d, in.st, in.ct);
     return in;
 }
 
@@ -100,10 +104,14 @@ struct Touch {
     __device__ int ntouch() const { return ct[0] * ct[1] * ct[2]; }
 };
 
-__device__ __forceinline__ Touch atom_touch(const AtomInfo &in, const ProbDesc &d)
+// (the ranges are formed once per atom by the count pass, in atom_prep)
+__device__ __forceinline__ Touch atom_touch(const AtomInfo &in, const ProbDesc &)
 {
     Touch t;
-    atom_bricks(in, d, t.st, t.ct);
+    for (int x = 0; x < 3; ++x) {
+        t.st[x] = in.st[x];
+        t.ct[x] = in.ct[x];
+    }
     return t;
 }
 
