@@ -154,7 +154,7 @@ struct hartree_plan_s {
     int64_t max_parts = 0;  // E_H partial slots at one pencil per workgroup
     // workspace layout
     size_t o_status = 0, o_desc = 0, o_tw = 0, o_spec = 0, o_parts = 0, o_qsum = 0, o_info = 0, o_counts = 0,
-           o_offsets = 0, o_cursor = 0, o_list = 0, o_lists = 0, o_bpart = 0, o_slot = 0, o_rec = 0, o_zero = 0,
+           o_offsets = 0, o_cursor = 0, o_list = 0, o_lists = 0, o_bpart = 0, o_slot = 0, o_rec = 0, o_order = 0, o_zero = 0,
            ws_size = 0;
     int32_t cap_pa = 0;
     bool wide = false;  // some truncation window can hold two images of one grid point
@@ -509,6 +509,7 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
         p->o_bpart = take(24 * size_t(p->capacity));
         p->o_slot = take(4 * size_t(p->capacity));
         if (!p->general) p->o_rec = take((p->fp64 ? sizeof(SlotAtom64) : sizeof(SlotAtom)) * size_t(p->capacity));
+        if (nprob > 1) p->o_order = take(4 * size_t(p->nbricks));
     }
     p->ws_size = o;
     *out = p;
@@ -658,6 +659,9 @@ SplatArgs splat_args(hartree_plan p, int32_t natoms, const double *pos, const do
     a.slot_of = reinterpret_cast<int32_t *>(p->ws + p->o_slot);
     a.rec = (p->fp64 || p->general) ? nullptr : reinterpret_cast<SlotAtom *>(p->ws + p->o_rec);
     a.rec64 = (!p->fp64 || p->general) ? nullptr : reinterpret_cast<SlotAtom64 *>(p->ws + p->o_rec);
+    // batched plans: the matrix-core kernels take their bricks heaviest first
+    // (per-brick atom counts differ several-fold between problems)
+    a.order = (p->nprob > 1 && !p->general) ? reinterpret_cast<int32_t *>(p->ws + p->o_order) : nullptr;
     a.general = p->general ? 1 : 0;
     a.wide = p->wide ? 1 : 0;
     // |g|, |gd| of a c-axis factor stay below 4 max(1, max_sigma) (a few

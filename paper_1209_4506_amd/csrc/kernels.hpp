@@ -74,6 +74,7 @@ struct SplatArgs {
     int32_t *slot_of;       // max_atoms x cap_pa: sorted-list slot of each (atom, touched brick)
     SlotAtom *rec;          // capacity (FP32 plans): the sorted lists' atoms relative to their brick
     SlotAtom64 *rec64;      // capacity (FP64 plans): the same in double precision
+    int32_t *order;         // nbricks_total (batched plans): bricks by descending atom count, or nullptr
     double *bpart;          // capacity x 3 (adjoint partials): per list slot, or per (atom, touched brick)
                             // (atom * cap_pa + touch) where the per-slot records exist (rec or rec64)
     int64_t capacity;

@@ -54,9 +54,15 @@ __device__ __forceinline__ int brick_prob(const SplatArgs &a, int64_t b)
     return p;
 }
 
-// brick index of this workgroup, with consecutive bricks (which share
-// cache lines at their edges along c) kept on one XCD
-__device__ __forceinline__ int64_t brick_of_block() { return xcd_remap(blockIdx.x, gridDim.x); }
+// brick index of this workgroup: from the binning's work order where there
+// is one (batched plans: bricks by descending atom count), else with
+// consecutive bricks (which share cache lines at their edges along c) kept
+// on one XCD
+__device__ __forceinline__ int64_t brick_of_block(const SplatArgs &a)
+{
+    if (a.order) return a.order[blockIdx.x];
+    return xcd_remap(blockIdx.x, gridDim.x);
+}
 
 // A brick's position (brick index per axis), kept in registers
 struct BrickPos {

@@ -272,7 +272,7 @@ __global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(6))) 
 {
     __shared__ StagedG recs[kStage];
     __shared__ SplatBuf fac[2];  // double buffer of pipeline steps
-    const int64_t b = brick_of_block();
+    const int64_t b = brick_of_block(a);
     const int prob = brick_prob(a, b);
     const ProbDesc &d = a.desc[prob];
     const BrickPos p = brick_pos(d, b);
@@ -547,7 +547,7 @@ __global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(3))) 
     __shared__ StagedG recs[kStage];
     __shared__ AdjBuf buf[2];
     __shared__ float red[2][4][2][2 * kAdjGroup][2];  // [step parity][wave][lane half][n][component]
-    const int64_t b = brick_of_block();
+    const int64_t b = brick_of_block(a);
     const int prob = brick_prob(a, b);
     const ProbDesc &d = a.desc[prob];
     const BrickPos p = brick_pos(d, b);

@@ -176,7 +176,7 @@ __global__ __launch_bounds__(kDThreads) void k_splat_mfma64(SplatArgs a)
 {
     __shared__ SlotAtom64 recs[kDStage];
     __shared__ SplatBuf64 fac[2];  // double buffer of pipeline steps
-    const int64_t b = brick_of_block();
+    const int64_t b = brick_of_block(a);
     const int prob = brick_prob(a, b);
     const ProbDesc &d = a.desc[prob];
     const BrickPos p = brick_pos(d, b);
@@ -381,7 +381,7 @@ __global__ __launch_bounds__(kDThreads) void k_adjoint_mfma64(SplatArgs a)
     __shared__ SlotAtom64 recs[kDStage];
     __shared__ AdjBuf64 buf[2];
     __shared__ double red[2][4][2 * kDGroup][2];  // [group parity][wave][n][component]
-    const int64_t b = brick_of_block();
+    const int64_t b = brick_of_block(a);
     const int prob = brick_prob(a, b);
     const ProbDesc &d = a.desc[prob];
     const BrickPos p = brick_pos(d, b);
