@@ -947,13 +947,15 @@ hartree_status hartree_splat_adjoint_bound(hartree_plan plan, uint64_t token, co
     if (!grad_rho || (a.natoms > 0 && !grad_pos)) return fail(HARTREE_ERR_ARG, "grad_rho or grad_pos is NULL");
     a.grad_rho = grad_rho;
     a.grad_pos = grad_pos;
-    // 16-byte row loads when every problem's rows are whole, aligned vectors
+    // 16-byte row loads where a problem's rows are whole, aligned vectors:
+    // 1 when that holds for every problem, 2 when only some (the kernels
+    // check each problem's row length and offset), 0 for an unaligned grid
     a.grad_rows_vec16 = 0;
     if (reinterpret_cast<uintptr_t>(grad_rho) % 16 == 0) {
         const int per = plan->fp64 ? 2 : 4;  // elements per 16-byte vector
         a.grad_rows_vec16 = 1;
         for (const ProbDesc &d : plan->desc)
-            if (d.dims[2] % per != 0 || d.grid_off % per != 0) a.grad_rows_vec16 = 0;
+            if (d.dims[2] % per != 0 || d.grid_off % per != 0) a.grad_rows_vec16 = 2;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = timed(plan, HARTREE_K_ADJOINT, s, [&]() { return run_adjoint(a, s); });

@@ -89,7 +89,7 @@ struct SplatArgs {
     int32_t b_exp;          // FP32 adjoint: the c-axis factors enter the 16-bit products scaled by 2^b_exp
     void *rho;              // splat output grid
     const void *grad_rho;   // adjoint input grid
-    int32_t grad_rows_vec16;  // every problem's grad_rho rows are whole 16-byte vectors from a 16-byte aligned start
+    int32_t grad_rows_vec16;  // 16-byte grad_rho row loads: 0 none, 1 every problem's rows, 2 per problem (aligned start)
     const float *zeros;     // 64 zero floats in the workspace (never written by kernels)
     double *grad_pos;       // adjoint output
     double *qsum;           // 2 nprob: total charge per problem, then the largest atom weight per problem

@@ -185,13 +185,36 @@ constexpr int kScanPer = 16;
 
 // the weight |Z| (2 pi sigma^2)^(-3/2) of a valid atom in float (a bound
 // for scaling: clamped to the float range), 0 for an invalid one
-__device__ __forceinline__ float weight_bound(const SplatArgs &a, int i)
+__device__ __forceinline__ float weight_bound(double z, double s, double max_sigma)
 {
-    const double s = a.sigma[i], z = a.Z[i];
-    if (!(isfinite(z) && s > 0.0 && s <= a.max_sigma)) return 0.0f;
+    const bool ok = isfinite(z) && s > 0.0 && s <= max_sigma;
     const float s2 = 6.2831855f * float(s) * float(s);
     const float wv = fabsf(float(z)) / (s2 * sqrtf(s2));
-    return wv < 3.0e38f ? wv : 3.0e38f;
+    return ok ? (wv < 3.0e38f ? wv : 3.0e38f) : 0.0f;
+}
+
+// Q += Z and wm = max(wm, weight) over the atoms i0, i0 + step, ... below
+// i1, in that order; four atoms' loads are issued before their sums
+__device__ __forceinline__ void charge_and_weight(const SplatArgs &a, int i0, int i1, int step, double &q, float &wm)
+{
+    int i = i0;
+    for (; i + 3 * step < i1; i += 4 * step) {
+        double z[4], sg[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            z[k] = a.Z[i + k * step];
+            sg[k] = a.sigma[i + k * step];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            q += z[k];
+            wm = fmaxf(wm, weight_bound(z[k], sg[k], a.max_sigma));
+        }
+    }
+    for (; i < i1; i += step) {
+        q += a.Z[i];
+        wm = fmaxf(wm, weight_bound(a.Z[i], a.sigma[i], a.max_sigma));
+    }
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan(SplatArgs a)
@@ -207,10 +230,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(SplatArgs a)
         for (int p = 0; p < a.nprob; ++p) {
             double q = 0.0;
             float wm = 0.0f;
-            for (int i = a.atom_off[p] + t; i < a.atom_off[p + 1]; i += kScanThreads) {
-                q += a.Z[i];
-                wm = fmaxf(wm, weight_bound(a, i));
-            }
+            charge_and_weight(a, a.atom_off[p] + t, a.atom_off[p + 1], kScanThreads, q, wm);
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) {
                 q += __shfl_xor(q, off, 64);
@@ -240,10 +260,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(SplatArgs a)
         for (int p = w; p < a.nprob; p += NW) {
             double q = 0.0;
             float wm = 0.0f;
-            for (int i = a.atom_off[p] + lane; i < a.atom_off[p + 1]; i += 64) {
-                q += a.Z[i];
-                wm = fmaxf(wm, weight_bound(a, i));
-            }
+            charge_and_weight(a, a.atom_off[p] + lane, a.atom_off[p + 1], 64, q, wm);
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) {
                 q += __shfl_xor(q, off, 64);

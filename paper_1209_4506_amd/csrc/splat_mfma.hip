@@ -541,7 +541,7 @@ __device__ __forceinline__ void split_grad(const float (&g0)[16], const float (&
 // previous group's partials are reduced.
 // Three workgroups per CU (a few registers spill to scratch): measured
 // faster than two without spills.
-template <bool VEC, bool WIDE>
+template <int VM, bool WIDE>
 __global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_adjoint_mfma(SplatArgs a)
 {
     __shared__ StagedG recs[kStage];
@@ -575,8 +575,9 @@ __global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(3))) 
     // Every load is unconditional (an element outside the grid reads a zero
     // block of the workspace), so no branch or arithmetic on the loaded
     // values separates the loads from the record wait below: they stay in
-    // flight until the matrix products.  VEC: every problem's rows hold a
-    // multiple of 4 points from a 16-byte aligned start.
+    // flight until the matrix products.  vec: this problem's rows start
+    // 16-byte aligned, each a multiple of 4 points; VM = 1: true of every
+    // problem (known at compile time), 2: checked per problem, 0: never.
     float g0[16], g1[16];
     half8 ah[2][2], al[2][2];
     float unscale[2];
@@ -584,7 +585,8 @@ __global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(3))) 
     const float *src = reinterpret_cast<const float *>(a.grad_rho) + d.grid_off;
     const bool interior =
         (p.b0 + 1) * kMI <= d.dims[0] && (p.b1 + 1) * kMJ <= d.dims[1] && (p.b2 + 1) * kMK <= d.dims[2];
-    if (VEC && interior) {
+    const bool vec = VM == 1 || (VM == 2 && (d.dims[2] & 3) == 0 && (d.grid_off & 3) == 0);
+    if (vec && interior) {
         // a brick inside the grid: a wavefront-uniform base plus a 32-bit
         // lane offset, every load in range
         const int w = __builtin_amdgcn_readfirstlane(wave);
@@ -614,7 +616,7 @@ __global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(3))) 
         const bool in0 = jin && ia < d.dims[0], in1 = jin && ia + 2 < d.dims[0];
         const float *row0 = src + (in0 ? (int64_t(ia) * d.dims[1] + j) * d.dims[2] + k0 : 0);
         const float *row1 = src + (in1 ? (int64_t(ia + 2) * d.dims[1] + j) * d.dims[2] + k0 : 0);
-        if constexpr (VEC) {
+        if (vec) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int ko = 16 * (q >> 1) + 4 * (q & 1);
@@ -690,14 +692,19 @@ hipError_t run_gather_mfma(const SplatArgs &a, hipStream_t s)
 hipError_t run_adjoint_mfma(const SplatArgs &a, hipStream_t s)
 {
     const dim3 grid(int(a.nbricks_total)), block(kMThreads);
-    if (a.grad_rows_vec16 && !a.wide)
-        hipLaunchKernelGGL((k_adjoint_mfma<true, false>), grid, block, 0, s, a);
-    else if (a.grad_rows_vec16)
-        hipLaunchKernelGGL((k_adjoint_mfma<true, true>), grid, block, 0, s, a);
-    else if (!a.wide)
-        hipLaunchKernelGGL((k_adjoint_mfma<false, false>), grid, block, 0, s, a);
+    const int vm = a.grad_rows_vec16;  // 0, 1, 2 as the kernel's VM
+    if (vm == 1 && a.wide)
+        hipLaunchKernelGGL((k_adjoint_mfma<1, true>), grid, block, 0, s, a);
+    else if (vm == 1)
+        hipLaunchKernelGGL((k_adjoint_mfma<1, false>), grid, block, 0, s, a);
+    else if (vm == 2 && a.wide)
+        hipLaunchKernelGGL((k_adjoint_mfma<2, true>), grid, block, 0, s, a);
+    else if (vm == 2)
+        hipLaunchKernelGGL((k_adjoint_mfma<2, false>), grid, block, 0, s, a);
+    else if (a.wide)
+        hipLaunchKernelGGL((k_adjoint_mfma<0, true>), grid, block, 0, s, a);
     else
-        hipLaunchKernelGGL((k_adjoint_mfma<false, true>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_adjoint_mfma<0, false>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 

@@ -399,7 +399,7 @@ __global__ __launch_bounds__(kDThreads) void k_adjoint_mfma64(SplatArgs a)
     const double *src = reinterpret_cast<const double *>(a.grad_rho) + d.grid_off;
     const int jj = lane & 15, kq = lane >> 4;
     const int64_t sb = d.dims[2], sa = int64_t(d.dims[1]) * d.dims[2];
-    if (a.grad_rows_vec16 && brick_inside(d, p)) {
+    if (a.grad_rows_vec16 && brick_inside(d, p) && (d.dims[2] & 1) == 0 && (d.grid_off & 1) == 0) {
         // a wavefront-uniform base plus a 32-bit lane offset, 16-byte loads
         const int w = __builtin_amdgcn_readfirstlane(wave);
         const double *base = src + (int64_t(p.b0 * kMI + 4 * w) * d.dims[1] + p.b1 * kMJ) * sb + p.b2 * kMK;
