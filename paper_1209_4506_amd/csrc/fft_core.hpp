@@ -28,6 +28,8 @@
 // of interest need at most three stages.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "radix_consts.hpp"
 
@@ -48,6 +50,12 @@ template <typename T>
 __device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b)
 {
     return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a times the conjugate of b
+template <typename T>
+__device__ __forceinline__ Cx<T> cmulc(Cx<T> a, Cx<T> b)
+{
+    return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
 // multiply by -i (forward) or +i (inverse)
 template <typename T, bool INV>
@@ -238,6 +246,7 @@ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 template <typename T>
 struct LdsPencil {
     static constexpr bool kLds = true;
+    static constexpr bool kTail = false;
     Cx<T> *buf;
     int pp, p;
     bool cj;
@@ -262,6 +271,7 @@ struct LdsPencil {
 template <typename T>
 struct LdsRow {
     static constexpr bool kLds = true;
+    static constexpr bool kTail = false;
     Cx<T> *buf;
     int ldp, p;
     bool cj;
@@ -289,9 +299,17 @@ struct LdsRow {
 // only then), and the lane offset is a 32-bit byte offset.  A pencil beyond
 // the tile edge (valid false) points at a valid pencil of the tile: it loads
 // real data, is transformed like the others, and stores nothing.
-template <typename T, bool L32>
+// a wavefront-uniform 64-bit value pinned to scalar registers
+__device__ __forceinline__ int64_t uniform64(int64_t x)
+{
+    asm("" : "+s"(x));
+    return x;
+}
+
+template <typename T, bool L32, bool RUN = false>
 struct GlobalPencil {
     static constexpr bool kLds = false;
+    static constexpr bool kRun = L32 && RUN;
     Cx<T> *base;  // element 0 of the tile's first pencil (wavefront-uniform)
     int stride;   // elements between consecutive points of a pencil
     int lane;     // tip * stride + column of this thread's pencil (elements)
@@ -317,7 +335,49 @@ struct GlobalPencil {
         if (cj) v.y = -v.y;
         if (valid) *at(u) = v;
     }
+    // Elements u0 + q du (q = 0 .. K-1; u0 and du uniform) with L32 and RUN:
+    // the row offset advances by a scalar step in scalar registers, and each
+    // address is one 64-bit add of it to the lane's pointer (the compiler
+    // otherwise forms the row chain with 64-bit multiply-adds on the vector
+    // units).  Taken by the vector-bound a pass only: in the memory-bound b
+    // pass the same form measured slower.
+    __device__ __forceinline__ Cx<T> *lane_at(int64_t o) const
+    {
+        return reinterpret_cast<Cx<T> *>(reinterpret_cast<char *>(base + o) + uint32_t(lane) * uint32_t(sizeof(Cx<T>)));
+    }
+    template <int K>
+    __device__ __forceinline__ void load_run(int u0, int du, Cx<T> (&out)[K]) const
+    {
+        int64_t o = uniform64(int64_t(u0) * stride);
+        const int64_t step = int64_t(du) * stride;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            Cx<T> v = *lane_at(o);
+            if (cj) v.y = -v.y;
+            out[q] = v;
+            o = uniform64(o + step);
+        }
+    }
+    template <int K>
+    __device__ __forceinline__ void store_run(int u0, int du, const Cx<T> (&in)[K]) const
+    {
+        int64_t o = uniform64(int64_t(u0) * stride);
+        const int64_t step = int64_t(du) * stride;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            Cx<T> v = in[q];
+            if (cj) v.y = -v.y;
+            if (valid) *lane_at(o) = v;
+            o = uniform64(o + step);
+        }
+    }
 };
+
+// whether an accessor takes runs of rows (load_run / store_run)
+template <typename A, typename = void>
+struct has_run : std::false_type {};
+template <typename A>
+struct has_run<A, std::void_t<decltype(A::kRun)>> : std::bool_constant<A::kRun> {};
 
 // Butterflies per thread a stage holds in registers, by radix: a stage keeps
 // at most 32 complex values per thread in float (21 in double, enough for
@@ -356,9 +416,10 @@ __device__ __forceinline__ void stage(const Src &src, Dst &dst, const Cx<T> *tw,
                 ns = int(nsd.d);
                 jd = int(fdiv(uint32_t(j), nsd));
                 k = j - jd * ns;
-                const int tstep = k * twstride;
+                // twiddle indices stay below n <= 2^24: 24-bit products
+                const int tstep = __mul24(k, twstride);
 #pragma unroll
-                for (int q = 1; q < R; ++q) v[m][q] = cmul(v[m][q], tw[q * tstep]);
+                for (int q = 1; q < R; ++q) v[m][q] = cmul(v[m][q], tw[__mul24(q, tstep)]);
             }
             butterfly<T, R, false>(v[m]);
             if constexpr (Dst::kLds) {
@@ -378,7 +439,9 @@ __device__ __forceinline__ void stage(const Src &src, Dst &dst, const Cx<T> *tw,
 // The same stage with the length, the stride of its outputs (ns, the
 // product of the earlier radices) and its twiddle stride known at compile
 // time (the compiled radix plans): index arithmetic folds into constants.
-template <typename T, int R, int MAXB, bool FIRST, bool SYNC, int NB, int NS, int TWS, typename Src, typename Dst>
+// INV: the inverse transform's stage (conjugate twiddles and butterflies).
+template <typename T, int R, int MAXB, bool FIRST, bool SYNC, int NB, int NS, int TWS, bool INV, typename Src,
+          typename Dst>
 __device__ __forceinline__ void stage_ct(const Src &src, Dst &dst, const Cx<T> *tw, int tip, int tpp)
 {
     Cx<T> v[MAXB][R];
@@ -386,8 +449,12 @@ __device__ __forceinline__ void stage_ct(const Src &src, Dst &dst, const Cx<T> *
     for (int m = 0; m < MAXB; ++m) {
         const int j = tip + m * tpp;
         if (j < NB) {
+            if constexpr (has_run<Src>::value) {
+                src.template load_run<R>(m * tpp, NB, v[m]);
+            } else {
 #pragma unroll
-            for (int q = 0; q < R; ++q) v[m][q] = src.load_at(m * tpp + q * NB, tip);
+                for (int q = 0; q < R; ++q) v[m][q] = src.load_at(m * tpp + q * NB, tip);
+            }
         }
     }
     if (SYNC) __syncthreads();
@@ -399,19 +466,34 @@ __device__ __forceinline__ void stage_ct(const Src &src, Dst &dst, const Cx<T> *
             const int jd = j / NS;
             const int k = j - jd * NS;
             if (!FIRST) {
-                const int tstep = k * TWS;
+                const int tstep = __mul24(k, TWS);
 #pragma unroll
-                for (int q = 1; q < R; ++q) v[m][q] = cmul(v[m][q], tw[q * tstep]);
+                for (int q = 1; q < R; ++q) {
+                    const Cx<T> w = tw[__mul24(q, tstep)];
+                    v[m][q] = INV ? cmulc(v[m][q], w) : cmul(v[m][q], w);
+                }
             }
-            butterfly<T, R, false>(v[m]);
+            butterfly<T, R, INV>(v[m]);
             if constexpr (Dst::kLds) {
                 const int base = jd * (NS * R) + k;
+                if constexpr (Dst::kTail) {
+                    // the last stage into a destination that needs each
+                    // element's index split: base = j < NS, offsets q NS
 #pragma unroll
-                for (int q = 0; q < R; ++q) dst.store(base + q * NS, v[m][q]);
+                    for (int q = 0; q < R; ++q) dst.store_tail(base, q * NS, NS, NS * R, v[m][q]);
+                    dst.end_butterfly();
+                } else {
+#pragma unroll
+                    for (int q = 0; q < R; ++q) dst.store(base + q * NS, v[m][q]);
+                }
             } else {
                 // the last stage (NS = N / R): jd = 0, k = j
+                if constexpr (has_run<Dst>::value) {
+                    dst.template store_run<R>(m * tpp, NS, v[m]);
+                } else {
 #pragma unroll
-                for (int q = 0; q < R; ++q) dst.store_at(m * tpp + q * NS, tip, v[m][q]);
+                    for (int q = 0; q < R; ++q) dst.store_at(m * tpp + q * NS, tip, v[m][q]);
+                }
             }
         }
     }
@@ -473,8 +555,9 @@ __device__ __forceinline__ void fft_pencils(const Src &src, Dst &dst, const L &l
 // for absent stages).  Each stage then gets registers sized for its own
 // radix; a kernel that switches between radices at run time (fft_pencils)
 // must hold registers for the largest case in every stage, which costs
-// occupancy.
-template <typename T, int R0, int R1, int R2, int R3, typename Src, typename Dst, typename L>
+// occupancy.  INV: the inverse transform (unnormalized), with no
+// conjugation of its input or output.
+template <typename T, int R0, int R1, int R2, int R3, bool INV = false, typename Src, typename Dst, typename L>
 __device__ __forceinline__ void fft_static(const Src &src, Dst &dst, const L &lds, const Cx<T> *tw,
                                            const AxisPlan &ap, int tip, int tpp)
 {
@@ -486,21 +569,22 @@ __device__ __forceinline__ void fft_static(const Src &src, Dst &dst, const L &ld
     (void)ap;
     L l = lds;
     l.cj = false;
-    stage_ct<T, R0, stage_maxb<T>(R0), true, Src::kLds, N / R0, 1, 1>(src, l, tw, tip, tpp);
+    stage_ct<T, R0, stage_maxb<T>(R0), true, Src::kLds, N / R0, 1, 1, INV>(src, l, tw, tip, tpp);
     __syncthreads();
     if constexpr (S == 1) {
         for (int u = 0; u + tip < N; u += tpp) dst.store_at(u, tip, l.load(u + tip));
     } else if constexpr (S == 2) {
-        stage_ct<T, Q1, stage_maxb<T>(Q1), false, Dst::kLds, N / Q1, NS1, N / (NS1 * Q1)>(l, dst, tw, tip, tpp);
+        stage_ct<T, Q1, stage_maxb<T>(Q1), false, Dst::kLds, N / Q1, NS1, N / (NS1 * Q1), INV>(l, dst, tw, tip, tpp);
     } else {
-        stage_ct<T, Q1, stage_maxb<T>(Q1), false, true, N / Q1, NS1, N / (NS1 * Q1)>(l, l, tw, tip, tpp);
+        stage_ct<T, Q1, stage_maxb<T>(Q1), false, true, N / Q1, NS1, N / (NS1 * Q1), INV>(l, l, tw, tip, tpp);
         __syncthreads();
         if constexpr (S == 3) {
-            stage_ct<T, Q2, stage_maxb<T>(Q2), false, Dst::kLds, N / Q2, NS2, N / (NS2 * Q2)>(l, dst, tw, tip, tpp);
+            stage_ct<T, Q2, stage_maxb<T>(Q2), false, Dst::kLds, N / Q2, NS2, N / (NS2 * Q2), INV>(l, dst, tw, tip,
+                                                                                               tpp);
         } else {
-            stage_ct<T, Q2, stage_maxb<T>(Q2), false, true, N / Q2, NS2, N / (NS2 * Q2)>(l, l, tw, tip, tpp);
+            stage_ct<T, Q2, stage_maxb<T>(Q2), false, true, N / Q2, NS2, N / (NS2 * Q2), INV>(l, l, tw, tip, tpp);
             __syncthreads();
-            stage_ct<T, Q3, stage_maxb<T>(Q3), false, Dst::kLds, N / Q3, NS3, N / (NS3 * Q3)>(l, dst, tw, tip,
+            stage_ct<T, Q3, stage_maxb<T>(Q3), false, Dst::kLds, N / Q3, NS3, N / (NS3 * Q3), INV>(l, dst, tw, tip,
                                                                                                tpp);
         }
     }

@@ -386,6 +386,7 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 template <typename T>
 struct KernelMultiply {
     static constexpr bool kLds = true;
+    static constexpr bool kTail = true;
     Cx<T> *buf;
     int pp, p;
     const ProbDesc *d;
@@ -398,8 +399,10 @@ struct KernelMultiply {
     bool ortho;       // wavefront-uniform: a diagonal cell (no Nyquist average, q1 = 0)
     bool general;     // a Nyquist b or c index of a non-orthorhombic cell
     T q2, q1, q0;     // |G|^2 = (q2 s_a + q1) s_a + q0
+    T fe;             // K |X|^2 summed over the current butterfly's outputs
     __device__ __forceinline__ void init()
     {
+        fe = T(0);
         const T *B = nullptr;
         if constexpr (sizeof(T) == 4) B = reinterpret_cast<const T *>(d->Bf);
         else B = reinterpret_cast<const T *>(d->B);
@@ -436,6 +439,41 @@ struct KernelMultiply {
         buf[i * pp + p] = cscale(v, K * invn);
     }
     __device__ __forceinline__ void store_at(int u, int t, Cx<T> v) { store(u + t, v); }
+    // The same for the outputs of the last compiled stage: element
+    // i = base + lo with 0 <= base < ns, where lo, ns and the length n are
+    // constants once the stage loop is unrolled.  s_a then needs no
+    // per-element select where the whole run [lo, lo + ns) lies in one half
+    // of the range, and in a diagonal cell only i = 0 can have G = 0.  The
+    // energy terms of one butterfly are summed in the working precision and
+    // added to the FP64 partial by end_butterfly.
+    __device__ __forceinline__ void store_tail(int base, int lo, int ns, int n, Cx<T> v)
+    {
+        const int i = base + lo;
+        T sa;
+        if (2 * (lo + ns - 1) < n) sa = T(base) + T(lo);
+        else if (2 * lo >= n) sa = T(base) + T(lo - n);
+        else sa = T((2 * i < n) ? i : i - n);
+        T K;
+        if (ortho) {
+            const T g2 = q2 * sa * sa + q0;
+            K = T(12.566370614359172953850573533118) * recip(g2);
+            if (lo == 0) K = (g2 > T(0)) ? K : T(0);
+        } else if (general || 2 * i == na) {
+            K = kernel_value_rare<T>(*d, i, mb, mc);
+        } else {
+            const T g2 = (q2 * sa + q1) * sa + q0;
+            K = (g2 > T(0)) ? T(12.566370614359172953850573533118) * recip(g2) : T(0);
+        }
+        if (energy) fe += K * (v.x * v.x + v.y * v.y);
+        buf[i * pp + p] = cscale(v, K * invn);
+    }
+    __device__ __forceinline__ void end_butterfly()
+    {
+        if (energy) {
+            acc += wgt * double(fe);
+            fe = T(0);
+        }
+    }
 };
 
 // mode 0: forward, energy, multiply, inverse.  mode 1: no energy.
@@ -474,7 +512,7 @@ __global__ __launch_bounds__(256) void k_fft_a(PassArgs a)
     const int mc = col - mb * nh;
     Cx<T> *g = reinterpret_cast<Cx<T> *>(a.spec) + d.spec_off + col0;
     const int lane = tip * ncol + (p < valid ? p : 0);
-    GlobalPencil<T, (CP > 0)> gp{g, ncol, lane, p < valid, false};
+    GlobalPencil<T, (CP > 0), true> gp{g, ncol, lane, p < valid, false};
     const LdsPencil<T> lp{buf, PP, p, false};
     KernelMultiply<T> km{buf, PP, p, &d, mb, mc, energy, T(d.inv_n),
                          p < valid ? ((mc == 0 || 2 * mc == Nc) ? 1.0 : 2.0) : 0.0, 0.0};
@@ -497,12 +535,17 @@ __global__ __launch_bounds__(256) void k_fft_a(PassArgs a)
         }
     }
     if (mode == 2) return;
-    // inverse along a: conjugate on the way in and on the way out
-    const LdsPencil<T> lpc{buf, PP, p, true};
-    GlobalPencil<T, (CP > 0)> gpc{g, ncol, lane, p < valid, true};
+    // inverse along a
     if (d.ax[0].nstages == 0) {
         if (tip == 0) gp.store_at(0, 0, lp.load(0));
+    } else if constexpr (R0 > 0) {
+        // a compiled plan: the inverse stages themselves
+        fft_static<T, R0, R1, R2, R3, true>(lp, gp, lp, tw, d.ax[0], tip, TPP);
     } else {
+        // run-time radices: the forward stages, conjugating on the way in
+        // and on the way out
+        const LdsPencil<T> lpc{buf, PP, p, true};
+        GlobalPencil<T, (CP > 0), true> gpc{g, ncol, lane, p < valid, true};
         fft_any<T, R0, R1, R2, R3>(lpc, gpc, lp, tw, d.ax[0], tip, TPP);
     }
 }
