@@ -413,6 +413,11 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
         d.L[0] = A[0];
         d.L[1] = A[4];
         d.L[2] = A[8];
+        for (int k = 0; k < 3; ++k) {
+            d.h[k] = d.L[k] / double(d.dims[k]);
+            d.hf[k] = float(d.h[k]);
+            d.hfl[k] = float(d.h[k] - double(d.hf[k]));
+        }
         for (int k = 0; k < 9; ++k) d.A[k] = A[k];
         d.separable = (ortho && A[0] > 0.0 && A[4] > 0.0 && A[8] > 0.0) ? 1 : 0;
         if (!d.separable) p->general = true;

@@ -66,6 +66,9 @@ struct ProbDesc {
     double eh_scale;    // Omega / (2 npts^2)
     double dv;          // Omega / npts
     double L[3];        // cell edges (orthorhombic cells)
+    double h[3];        // grid spacing L / N per axis (orthorhombic cells)
+    float hf[3];        // h as a float ...
+    float hfl[3];       // ... and the float of its remainder h - hf
     double A[9];        // cell rows a, b, c (any cell)
     int32_t separable;  // 1: diagonal cell with positive edges (separable splat)
     int32_t pad4;

@@ -67,7 +67,7 @@ __device__ __forceinline__ AtomInfo atom_prep(const SplatArgs &a, int atom, bool
             X -= floor(X / L) * L;
             if (X >= L) X -= L;
             if (X < 0.0) X = 0.0;
-            const double h = L / d.dims[x];
+            const double h = d.h[x];
             in.X[x] = X;
             in.lo[x] = int(ceil((X - rc) / h));
             in.hi[x] = int(floor((X + rc) / h));
@@ -452,7 +452,7 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a, int rank_words)
             SlotAtom r;
             for (int x = 0; x < 3; ++x) {
                 const int n = d.dims[x];
-                const double h = d.L[x] / n;
+                const double h = d.h[x];
                 const double xb = in.X[x] - in.lo[x] * h;
                 r.ax[x].xb = float(xb);
                 r.ax[x].xbl = float(xb - double(r.ax[x].xb));

@@ -76,9 +76,8 @@ __device__ __forceinline__ LaneAxis lane_axis(const ProbDesc &d, const BrickPos 
     const int b = la.x == 0 ? p.b0 * kMI : (la.x == 1 ? p.b1 * kMJ : p.b2 * kMK);
     la.g = b + la.qq;
     la.n = d.dims[la.x];
-    const double h = d.L[la.x] / la.n;
-    la.h = float(h);
-    la.hl = float(h - double(la.h));
+    la.h = d.hf[la.x];
+    la.hl = d.hfl[la.x];
     return la;
 }
 
@@ -586,19 +585,44 @@ __global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(3))) 
     const bool interior =
         (p.b0 + 1) * kMI <= d.dims[0] && (p.b1 + 1) * kMJ <= d.dims[1] && (p.b2 + 1) * kMK <= d.dims[2];
     const bool vec = VM == 1 || (VM == 2 && (d.dims[2] & 3) == 0 && (d.grid_off & 3) == 0);
-    if (vec && interior) {
-        // a brick inside the grid: a wavefront-uniform base plus a 32-bit
-        // lane offset, every load in range
-        const int w = __builtin_amdgcn_readfirstlane(wave);
-        const int64_t sb = d.dims[2], sa = int64_t(d.dims[1]) * d.dims[2];
-        const float *base = src + (int64_t(p.b0 * kMI + 4 * w) * d.dims[1] + p.b1 * kMJ) * sb + p.b2 * kMK;
-        const uint32_t loff = uint32_t(((col >> 4) * d.dims[1] + (col & 15)) * d.dims[2] + 8 * half);
-        const float4 *r0 = reinterpret_cast<const float4 *>(base + loff);
-        const float4 *r1 = reinterpret_cast<const float4 *>(base + 2 * sa + loff);
+    if (vec) {
+        // the eight 16-byte vectors of the lane's two rows, addressed first
+        // and loaded by one common sequence
+        const float4 *pv0[4], *pv1[4];
+        if (interior) {
+            // a brick inside the grid: a wavefront-uniform base plus a
+            // 32-bit lane offset, every load in range
+            const int w = __builtin_amdgcn_readfirstlane(wave);
+            const int64_t sb = d.dims[2], sa = int64_t(d.dims[1]) * d.dims[2];
+            const float *base = src + (int64_t(p.b0 * kMI + 4 * w) * d.dims[1] + p.b1 * kMJ) * sb + p.b2 * kMK;
+            const uint32_t loff = uint32_t(((col >> 4) * d.dims[1] + (col & 15)) * d.dims[2] + 8 * half);
+            const float4 *r0 = reinterpret_cast<const float4 *>(base + loff);
+            const float4 *r1 = reinterpret_cast<const float4 *>(base + 2 * sa + loff);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int vo = 4 * (q >> 1) + (q & 1);  // float4 offset of slot vector q
+                pv0[q] = r0 + vo;
+                pv1[q] = r1 + vo;
+            }
+        } else {
+            const int j = p.b1 * kMJ + (col & 15);
+            const int ia = p.b0 * kMI + 4 * wave + (col >> 4);
+            const int k0 = p.b2 * kMK + 8 * half;
+            const bool jin = j < d.dims[1];
+            const bool in0 = jin && ia < d.dims[0], in1 = jin && ia + 2 < d.dims[0];
+            const float *row0 = src + (in0 ? (int64_t(ia) * d.dims[1] + j) * d.dims[2] + k0 : 0);
+            const float *row1 = src + (in1 ? (int64_t(ia + 2) * d.dims[1] + j) * d.dims[2] + k0 : 0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int ko = 16 * (q >> 1) + 4 * (q & 1);
+                const bool kin = k0 + ko < d.dims[2];  // whole vectors: Nc is a multiple of 4
+                pv0[q] = reinterpret_cast<const float4 *>(in0 && kin ? row0 + ko : a.zeros);
+                pv1[q] = reinterpret_cast<const float4 *>(in1 && kin ? row1 + ko : a.zeros);
+            }
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int vo = 4 * (q >> 1) + (q & 1);  // float4 offset of slot vector q
-            const float4 v0 = r0[vo], v1 = r1[vo];
+            const float4 v0 = *pv0[q], v1 = *pv1[q];
             g0[4 * q] = v0.x;
             g0[4 * q + 1] = v0.y;
             g0[4 * q + 2] = v0.z;
@@ -616,30 +640,12 @@ __global__ __launch_bounds__(kMThreads) __attribute__((amdgpu_waves_per_eu(3))) 
         const bool in0 = jin && ia < d.dims[0], in1 = jin && ia + 2 < d.dims[0];
         const float *row0 = src + (in0 ? (int64_t(ia) * d.dims[1] + j) * d.dims[2] + k0 : 0);
         const float *row1 = src + (in1 ? (int64_t(ia + 2) * d.dims[1] + j) * d.dims[2] + k0 : 0);
-        if (vec) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int ko = 16 * (q >> 1) + 4 * (q & 1);
-                const bool kin = k0 + ko < d.dims[2];  // whole vectors: Nc is a multiple of 4
-                const float4 v0 = *reinterpret_cast<const float4 *>(in0 && kin ? row0 + ko : a.zeros);
-                const float4 v1 = *reinterpret_cast<const float4 *>(in1 && kin ? row1 + ko : a.zeros);
-                g0[4 * q] = v0.x;
-                g0[4 * q + 1] = v0.y;
-                g0[4 * q + 2] = v0.z;
-                g0[4 * q + 3] = v0.w;
-                g1[4 * q] = v1.x;
-                g1[4 * q + 1] = v1.y;
-                g1[4 * q + 2] = v1.z;
-                g1[4 * q + 3] = v1.w;
-            }
-        } else {
-#pragma unroll
-            for (int m = 0; m < 16; ++m) {
-                const int ko = 16 * (m >> 3) + (m & 7);
-                const bool kin = k0 + ko < d.dims[2];
-                g0[m] = *(in0 && kin ? row0 + ko : a.zeros);
-                g1[m] = *(in1 && kin ? row1 + ko : a.zeros);
-            }
+        for (int m = 0; m < 16; ++m) {
+            const int ko = 16 * (m >> 3) + (m & 7);
+            const bool kin = k0 + ko < d.dims[2];
+            g0[m] = *(in0 && kin ? row0 + ko : a.zeros);
+            g1[m] = *(in1 && kin ? row1 + ko : a.zeros);
         }
     }
 

@@ -52,7 +52,7 @@ __device__ __forceinline__ LaneAxis64 lane_axis64(const ProbDesc &d, const Brick
     const int b = la.x == 0 ? p.b0 * kMI : (la.x == 1 ? p.b1 * kMJ : p.b2 * kMK);
     la.g = b + la.qq;
     la.n = d.dims[la.x];
-    la.h = d.L[la.x] / la.n;
+    la.h = d.h[la.x];
     return la;
 }
 
