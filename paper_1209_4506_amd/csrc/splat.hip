@@ -146,7 +146,9 @@ __device__ __forceinline__ int touch_index(const Touch &t, const ProbDesc &d, in
 template <int MODE>  // 0: count, 1: fill
 __global__ __launch_bounds__(256) void k_brick_visit(SplatArgs a)
 {
-    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    // the wavefront's index is uniform: kept in scalar registers, so that
+    // the atom's and its problem's data come through scalar loads
+    const int w = __builtin_amdgcn_readfirstlane(int(blockIdx.x * 4 + (threadIdx.x >> 6)));
     const int lane = threadIdx.x & 63;
     if (w >= a.natoms) return;
     const int atom = int((int64_t(w) * a.visit_stride) % a.natoms);
@@ -342,8 +344,8 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a, int rank_words)
 {
     __shared__ int lst[4][kSortLds];
     extern __shared__ uint32_t rank_lds[];  // rank_words > 0: [4 waves][bitmap, word prefix][rank_words]
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t b = int64_t(blockIdx.x) * 4 + w;
+    const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const int64_t b = int64_t(blockIdx.x) * 4 + w;  // uniform: scalar loads of its offsets and problem
     int64_t off = 0;
     int cnt = 0;
     if (b < a.nbricks_total) {
@@ -505,7 +507,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_brick_order(SplatArgs a)
 // sort) in a fixed order, then a fixed butterfly combines the lanes
 __global__ __launch_bounds__(256) void k_adjoint_final(SplatArgs a)
 {
-    const int atom = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int atom = __builtin_amdgcn_readfirstlane(int(blockIdx.x * 4 + (threadIdx.x >> 6)));
     const int lane = threadIdx.x & 63;
     if (atom >= a.natoms) return;
     const AtomInfo in = a.info[atom];
