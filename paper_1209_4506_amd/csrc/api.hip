@@ -255,23 +255,51 @@ void add_launch(std::vector<Launch> &v, int plan, int p_log2, int pad, int n, in
 
 // launch groups of the three pass kinds and the E_H partial slots from the
 // per-axis choices in p->cfg
+// whether every problem's axis x qualifies for one multi-plan launch (FP32
+// batched plans): a compiled plan of length <= 256, one common tile width of
+// the multi-plan kernels, no pitch pad, and (strided axes) 32-bit lane
+// offsets
+bool multi_axis(hartree_plan p, int x)
+{
+    if (p->nprob < 2 || p->fp64) return false;
+    const int lp = p->cfg[x].p_log2;
+    if (lp != kMultiLogP0 && lp != kMultiLogP1) return false;
+    int64_t stride = 0;
+    for (int q = 0; q < p->nprob; ++q) {
+        const auto &c = p->cfg[3 * q + x];
+        if (c.plan < 0 || c.plan >= kMultiPlans || c.p_log2 != lp || c.pad != 0) return false;
+        const ProbDesc &d = p->desc[q];
+        const int64_t st = x == 0 ? int64_t(d.dims[1]) * d.dims[3] : d.dims[3];
+        stride = std::max(stride, st);
+    }
+    // the compiled strided tiles address lanes with 32-bit byte offsets
+    const int64_t tpp = 256 >> lp;  // 256 threads per pass workgroup
+    return x == 2 || ((tpp - 1) * stride + (int64_t(1) << lp)) * 8 < (int64_t(1) << 32);
+}
+
 void rebuild_launches(hartree_plan p)
 {
     p->lr2c.clear();
     p->lb.clear();
     p->la.clear();
     p->nparts = 0;
+    bool multi[3];
+    for (int x = 0; x < 3; ++x) multi[x] = multi_axis(p, x);
     for (int q = 0; q < p->nprob; ++q) {
         ProbDesc &d = p->desc[q];
         const auto *c = &p->cfg[3 * q];
+        for (int x = 0; x < 3; ++x) d.ax[x].cplan = c[x].plan;
         const int pa = 1 << c[0].p_log2, pb = 1 << c[1].p_log2, pc = 1 << c[2].p_log2;
         const int64_t rows = int64_t(d.dims[0]) * d.dims[1];
         const int64_t t1 = (rows + 2 * pc - 1) / (2 * pc);
         const int64_t t2 = int64_t(d.dims[0]) * ((d.dims[3] + pb - 1) / pb);
         const int64_t t3 = (int64_t(d.dims[1]) * d.dims[3] + pa - 1) / pa;
-        add_launch(p->lr2c, c[2].plan, c[2].p_log2, c[2].pad, d.dims[2], 0, q, int(t1));
-        add_launch(p->lb, c[1].plan, c[1].p_log2, c[1].pad, d.dims[1], d.dims[3], q, int(t2));
-        add_launch(p->la, c[0].plan, c[0].p_log2, c[0].pad, d.dims[0], int64_t(d.dims[1]) * d.dims[3], q, int(t3));
+        // a multi-plan axis puts every problem in one launch group (the
+        // kernel reads each problem's plan from its descriptor)
+        add_launch(p->lr2c, multi[2] ? kMultiPlan : c[2].plan, c[2].p_log2, c[2].pad, d.dims[2], 0, q, int(t1));
+        add_launch(p->lb, multi[1] ? kMultiPlan : c[1].plan, c[1].p_log2, c[1].pad, d.dims[1], d.dims[3], q, int(t2));
+        add_launch(p->la, multi[0] ? kMultiPlan : c[0].plan, c[0].p_log2, c[0].pad, d.dims[0],
+                   int64_t(d.dims[1]) * d.dims[3], q, int(t3));
         d.part_off = p->nparts;
         d.nparts = int(t3);
         p->nparts += int(t3);
@@ -1323,6 +1351,38 @@ hartree_status hartree_plan_tune(hartree_plan plan, void *grid, int32_t reps, vo
             }
             if (result != HARTREE_OK) break;
             cfg = best_cfg;
+        }
+        // batched FP32 plans: the axis as one multi-plan launch per pass
+        // (every length on its compiled plan at the multi tile width), kept
+        // when it times faster than the per-length choices
+        if (result == HARTREE_OK && plan->nprob > 1 && !plan->fp64) {
+            float ms_best = 0.0f;
+            if (!time_axis(x, cfg, ms_best)) ms_best = 0.0f;
+            for (int lp : {kMultiLogP0, kMultiLogP1}) {
+                if (result != HARTREE_OK || ms_best == 0.0f) break;
+                std::vector<int32_t> trial = cfg;
+                bool whole = true;
+                for (int q = 0; q < plan->nprob && whole; ++q) {
+                    const int n = plan->desc[q].dims[x];
+                    int id = -1;
+                    for (int i = 0; i < kMultiPlans && id < 0; ++i) {
+                        int rad[4];
+                        const int ns = plan_table_row(i, rad);
+                        long prod = 1;
+                        for (int k = 0; k < ns; ++k) prod *= rad[k];
+                        if (prod == n) id = i;
+                    }
+                    whole = id >= 0;
+                    trial[3 * (3 * q + x)] = id;
+                    trial[3 * (3 * q + x) + 1] = lp;
+                    trial[3 * (3 * q + x) + 2] = 0;
+                }
+                float ms = 0.0f;
+                if (whole && time_axis(x, trial, ms) && ms < ms_best) {
+                    ms_best = ms;
+                    cfg = trial;
+                }
+            }
         }
     }
     (void)hipEventDestroy(ev[0]);

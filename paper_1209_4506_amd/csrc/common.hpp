@@ -45,7 +45,7 @@ struct AxisPlan {
     int32_t n;
     int32_t nstages;
     int32_t tw_off;  // complex-element offset of this length's table
-    int32_t pad;
+    int32_t cplan;   // entry of the compiled plan table in use, or -1
     int32_t radix[kMaxStages];
     int32_t twstride[kMaxStages];
     FastDiv ns[kMaxStages];

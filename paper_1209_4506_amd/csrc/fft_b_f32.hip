@@ -28,6 +28,11 @@ const PassLaunchFn kFixed16[] = {HARTREE_PLANS(HARTREE_ENTRY)};
 hipError_t run_b_f32(int plan, int maxn, int grid, hipStream_t s, const PassArgs &a)
 {
     const size_t lds = pass_lds_bytes<float>(a, maxn);
+    if (plan == kMultiPlan) {
+        if (a.p_log2 == kMultiLogP0) return launch_pass(k_fft_b_multi<float, 1 << kMultiLogP0>, grid, lds, s, a);
+        if (a.p_log2 == kMultiLogP1) return launch_pass(k_fft_b_multi<float, 1 << kMultiLogP1>, grid, lds, s, a);
+        return hipErrorInvalidValue;
+    }
     if (plan < 0 || plan >= int(sizeof(kTable) / sizeof(kTable[0])))
         return launch_one<0, 0, 0, 0, 0>(grid, lds, s, a);
     // the compiled tiles address their pencils with 32-bit lane offsets

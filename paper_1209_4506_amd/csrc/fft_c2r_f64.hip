@@ -18,6 +18,7 @@ const PassLaunchFn kTable[] = {HARTREE_PLANS(HARTREE_ENTRY)};
 hipError_t run_c2r_f64(int plan, int maxn, int grid, hipStream_t s, const PassArgs &a)
 {
     const size_t lds = pass_lds_bytes<double>(a, maxn);
+    if (plan == kMultiPlan) return hipErrorInvalidValue;  // multi-plan launches are FP32 only
     if (plan < 0 || plan >= int(sizeof(kTable) / sizeof(kTable[0]))) return launch_one<0, 0, 0, 0>(grid, lds, s, a);
     return kTable[plan](grid, lds, s, a);
 }

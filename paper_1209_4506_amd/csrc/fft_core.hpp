@@ -619,6 +619,12 @@ __device__ __forceinline__ void fft_any(const Src &src, Dst &dst, const L &lds, 
     X(10, 10, 8, 0) X(8, 7, 5, 3) X(8, 8, 5, 3) X(16, 16, 4, 0) X(16, 16, 8, 0)                          \
     X(10, 6, 6, 0) X(6, 6, 10, 0) X(6, 10, 6, 0) X(10, 6, 3, 0) X(6, 6, 5, 0)
 
+// the plan table as compile-time constants (for kernels that pick a plan per
+// workgroup)
+#define HARTREE_ROW(R0, R1, R2, R3) {R0, R1, R2, R3},
+constexpr int kPlanRadix[][4] = {HARTREE_PLANS(HARTREE_ROW)};
+#undef HARTREE_ROW
+
 // Blocks are dispatched round-robin over the 8 XCDs (each with its own L2);
 // renumber them so that consecutive work items land on the same XCD, where
 // neighbouring tiles share cache lines at their edges.

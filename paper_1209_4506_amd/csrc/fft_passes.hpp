@@ -20,6 +20,7 @@
 
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "fft_core.hpp"
 #include "kernels.hpp"
@@ -170,15 +171,13 @@ constexpr int plan_length(int r0, int r1, int r2, int r3)
 // CP > 0 (passes along c; a compiled plan): tiles of exactly CP pencils
 // (2 CP rows), launched only for that shape, with the pencil length (the
 // plan's) compiled in as well, so tile offsets and loop bounds are constants.
-template <typename T, int MODE, int R0, int R1, int R2, int R3, int CP = 0>
-__global__ __launch_bounds__(256) void k_r2c_mode(PassArgs a)
+template <typename T, int MODE, int R0, int R1, int R2, int R3, int CP>
+__device__ __forceinline__ void r2c_tile(const PassArgs &a, int prob, int tile)
 {
     constexpr int NT = kPassThreads;
     constexpr int NF = CP > 0 ? plan_length(R0, R1, R2, R3) : 0;
     const int P = CP > 0 ? CP : 1 << a.p_log2, TPP = NT / P;
     extern __shared__ __align__(16) unsigned char smem[];
-    int prob, tile;
-    find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
     const ProbDesc &d = a.desc[prob];
     const int n = NF > 0 ? NF : d.dims[2], nh = NF > 0 ? NF / 2 + 1 : d.dims[3];
     const int ldp = row_pitch(n);
@@ -235,17 +234,23 @@ __global__ __launch_bounds__(256) void k_r2c_mode(PassArgs a)
     }
 }
 
+template <typename T, int MODE, int R0, int R1, int R2, int R3, int CP = 0>
+__global__ __launch_bounds__(256) void k_r2c_mode(PassArgs a)
+{
+    int prob, tile;
+    find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
+    r2c_tile<T, MODE, R0, R1, R2, R3, CP>(a, prob, tile);
+}
+
 // ---------------------------------------------------------------- P5
 // CP > 0: as for P1
-template <typename T, int R0, int R1, int R2, int R3, int CP = 0>
-__global__ __launch_bounds__(256) void k_c2r(PassArgs a)
+template <typename T, int R0, int R1, int R2, int R3, int CP>
+__device__ __forceinline__ void c2r_tile(const PassArgs &a, int prob, int tile)
 {
     constexpr int NT = kPassThreads;
     constexpr int NF = CP > 0 ? plan_length(R0, R1, R2, R3) : 0;
     const int P = CP > 0 ? CP : 1 << a.p_log2, TPP = NT / P;
     extern __shared__ __align__(16) unsigned char smem[];
-    int prob, tile;
-    find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
     const ProbDesc &d = a.desc[prob];
     const int n = NF > 0 ? NF : d.dims[2], nh = NF > 0 ? NF / 2 + 1 : d.dims[3];
     const int ldp = row_pitch(n);
@@ -282,21 +287,27 @@ __global__ __launch_bounds__(256) void k_c2r(PassArgs a)
     }
 }
 
+template <typename T, int R0, int R1, int R2, int R3, int CP = 0>
+__global__ __launch_bounds__(256) void k_c2r(PassArgs a)
+{
+    int prob, tile;
+    find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
+    c2r_tile<T, R0, R1, R2, R3, CP>(a, prob, tile);
+}
+
 // ---------------------------------------------------------------- P2 / P4
 // pencils along b: (a, h) for fixed a, P consecutive h per tile; the first
 // stage reads the tile from the spectrum and the last writes it back.
 // CP > 0: tiles of exactly CP pencils with no pitch pad, compiled in (as for
 // the a pass).
-template <typename T, int R0, int R1, int R2, int R3, int CP = 0>
-__global__ __launch_bounds__(256) void k_fft_b(PassArgs a)
+template <typename T, int R0, int R1, int R2, int R3, int CP>
+__device__ __forceinline__ void fft_b_tile(const PassArgs &a, int prob, int tile)
 {
     constexpr int NT = kPassThreads;
     const int P = CP > 0 ? CP : 1 << a.p_log2;
     const int TPP = NT / P;
     const int PP = CP > 0 ? CP : P + a.pad;
     extern __shared__ __align__(16) unsigned char smem[];
-    int prob, tile;
-    find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
     const ProbDesc &d = a.desc[prob];
     const int n = d.dims[1], nh = d.dims[3];
     if (d.ax[1].nstages == 0) return;  // a length-1 axis: identity
@@ -314,6 +325,14 @@ __global__ __launch_bounds__(256) void k_fft_b(PassArgs a)
     GlobalPencil<T, (CP > 0)> gp{g, nh, tip * nh + (p < valid ? p : 0), p < valid, a.inv != 0};
     const LdsPencil<T> lp{buf, PP, p, false};
     fft_any<T, R0, R1, R2, R3>(gp, gp, lp, tw, d.ax[1], tip, TPP);
+}
+
+template <typename T, int R0, int R1, int R2, int R3, int CP = 0>
+__global__ __launch_bounds__(256) void k_fft_b(PassArgs a)
+{
+    int prob, tile;
+    find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
+    fft_b_tile<T, R0, R1, R2, R3, CP>(a, prob, tile);
 }
 
 // ---------------------------------------------------------------- P3
@@ -483,8 +502,8 @@ struct KernelMultiply {
 // it only for that shape), so the tile pitch and the threads per pencil are
 // compile-time constants: LDS offsets become immediates and the per-stage
 // bounds checks fold away.
-template <typename T, int R0, int R1, int R2, int R3, int CP = 0>
-__global__ __launch_bounds__(256) void k_fft_a(PassArgs a)
+template <typename T, int R0, int R1, int R2, int R3, int CP>
+__device__ __forceinline__ void fft_a_tile(const PassArgs &a, int prob, int tile)
 {
     constexpr int NT = kPassThreads;
     const int P = CP > 0 ? CP : 1 << a.p_log2;
@@ -494,8 +513,6 @@ __global__ __launch_bounds__(256) void k_fft_a(PassArgs a)
     const bool energy = mode != 1;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[NT / 64];
-    int prob, tile;
-    find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
     const ProbDesc &d = a.desc[prob];
     const int n = d.dims[0], nh = d.dims[3], Nc = d.dims[2];
     const int ncol = d.dims[1] * nh;
@@ -549,6 +566,83 @@ __global__ __launch_bounds__(256) void k_fft_a(PassArgs a)
         fft_any<T, R0, R1, R2, R3>(lpc, gpc, lp, tw, d.ax[0], tip, TPP);
     }
 }
+
+template <typename T, int R0, int R1, int R2, int R3, int CP = 0>
+__global__ __launch_bounds__(256) void k_fft_a(PassArgs a)
+{
+    int prob, tile;
+    find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
+    fft_a_tile<T, R0, R1, R2, R3, CP>(a, prob, tile);
+}
+
+// ----------------------------------------------------- multi-plan launches
+// A batched plan runs each pass as one launch per (radix plan, tile shape)
+// group.  When every problem's pencils along the pass axis have a compiled
+// plan among the first kMultiPlans entries of HARTREE_PLANS (the lengths up
+// to 240) and one common tile width CP, the host instead makes one launch of
+// these kernels: each workgroup runs the plan recorded in its problem's axis
+// descriptor.  The resources of such a kernel are the largest over its plans
+// (256 = 16 x 16 is left out: its two radix-16 stages need a third more
+// registers than any of these, which would cost every plan occupancy).
+static_assert(plan_length(kPlanRadix[kMultiPlans - 1][0], kPlanRadix[kMultiPlans - 1][1],
+                          kPlanRadix[kMultiPlans - 1][2], kPlanRadix[kMultiPlans - 1][3]) == 240 &&
+                  plan_length(kPlanRadix[kMultiPlans][0], kPlanRadix[kMultiPlans][1], kPlanRadix[kMultiPlans][2],
+                              kPlanRadix[kMultiPlans][3]) > 240,
+              "the multi-plan kernels take the table's entries up to length 240");
+
+// f(integral_constant<I>) for the plan entry I == plan (plan < kMultiPlans)
+template <int I, typename F>
+__device__ __forceinline__ void with_small_plan(int plan, F &&f)
+{
+    if constexpr (I < kMultiPlans) {
+        if (plan == I) f(std::integral_constant<int, I>());
+        else with_small_plan<I + 1>(plan, f);
+    }
+}
+
+#define HARTREE_RADICES(I) kPlanRadix[I][0], kPlanRadix[I][1], kPlanRadix[I][2], kPlanRadix[I][3]
+
+template <typename T, int MODE, int CP>
+__global__ __launch_bounds__(256) void k_r2c_multi(PassArgs a)
+{
+    int prob, tile;
+    find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
+    with_small_plan<0>(a.desc[prob].ax[2].cplan, [&](auto ic) {
+        r2c_tile<T, MODE, HARTREE_RADICES(decltype(ic)::value), CP>(a, prob, tile);
+    });
+}
+
+template <typename T, int CP>
+__global__ __launch_bounds__(256) void k_c2r_multi(PassArgs a)
+{
+    int prob, tile;
+    find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
+    with_small_plan<0>(a.desc[prob].ax[2].cplan, [&](auto ic) {
+        c2r_tile<T, HARTREE_RADICES(decltype(ic)::value), CP>(a, prob, tile);
+    });
+}
+
+template <typename T, int CP>
+__global__ __launch_bounds__(256) void k_fft_b_multi(PassArgs a)
+{
+    int prob, tile;
+    find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
+    with_small_plan<0>(a.desc[prob].ax[1].cplan, [&](auto ic) {
+        fft_b_tile<T, HARTREE_RADICES(decltype(ic)::value), CP>(a, prob, tile);
+    });
+}
+
+template <typename T, int CP>
+__global__ __launch_bounds__(256) void k_fft_a_multi(PassArgs a)
+{
+    int prob, tile;
+    find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
+    with_small_plan<0>(a.desc[prob].ax[0].cplan, [&](auto ic) {
+        fft_a_tile<T, HARTREE_RADICES(decltype(ic)::value), CP>(a, prob, tile);
+    });
+}
+
+#undef HARTREE_RADICES
 
 // ------------------------------------------------------------- launchers
 

@@ -16,6 +16,13 @@ hipError_t launch_one(int grid, size_t lds, hipStream_t s, const PassArgs &a)
     if (a.in != nullptr) return launch_pass(k_r2c_mode<float, 1, R0, R1, R2, R3, CP>, grid, lds, s, a);
     return launch_pass(k_r2c_mode<float, 2, R0, R1, R2, R3, CP>, grid, lds, s, a);
 }
+template <int CP>
+hipError_t launch_multi(int grid, size_t lds, hipStream_t s, const PassArgs &a)
+{
+    if (a.mode == 0 || a.grad_e == nullptr) return launch_pass(k_r2c_multi<float, 0, CP>, grid, lds, s, a);
+    if (a.in != nullptr) return launch_pass(k_r2c_multi<float, 1, CP>, grid, lds, s, a);
+    return launch_pass(k_r2c_multi<float, 2, CP>, grid, lds, s, a);
+}
 #define HARTREE_ENTRY(R0, R1, R2, R3) &launch_one<R0, R1, R2, R3, 0>,
 const PassLaunchFn kTable[] = {HARTREE_PLANS(HARTREE_ENTRY)};
 #undef HARTREE_ENTRY
@@ -33,6 +40,11 @@ const PassLaunchFn kFixed8[] = {HARTREE_PLANS(HARTREE_ENTRY)};
 hipError_t run_r2c_f32(int plan, int maxn, int grid, hipStream_t s, const PassArgs &a)
 {
     const size_t lds = pass_lds_bytes<float>(a, maxn);
+    if (plan == kMultiPlan) {
+        if (a.p_log2 == kMultiLogP0) return launch_multi<1 << kMultiLogP0>(grid, lds, s, a);
+        if (a.p_log2 == kMultiLogP1) return launch_multi<1 << kMultiLogP1>(grid, lds, s, a);
+        return hipErrorInvalidValue;
+    }
     if (plan < 0 || plan >= int(sizeof(kTable) / sizeof(kTable[0])))
         return launch_one<0, 0, 0, 0, 0>(grid, lds, s, a);
     if (a.pad == 0 && a.p_log2 == 1) return kFixed2[plan](grid, lds, s, a);

@@ -41,6 +41,15 @@ struct PassArgs {
     TileList tl;
 };
 
+// Multi-plan launches (FP32): one launch per pass for the problems of a
+// batched plan when each one's axis takes a compiled plan among the first
+// kMultiPlans table entries (lengths up to 240), with one common tile width
+// of 2^kMultiLogP0 or 2^kMultiLogP1 pencils and no pitch pad; such a launch
+// carries plan kMultiPlan.
+constexpr int kMultiPlans = 16;
+constexpr int kMultiLogP0 = 3, kMultiLogP1 = 4;
+constexpr int kMultiPlan = -2;
+
 int pass_p_log2(int fp64, int n, const int *radix, int nstages, int max_p);
 int pass_min_tpp(int fp64, int n, const int *radix, int nstages);
 size_t pass_tile_lds(int fp64, int n, int p_log2, int pad);

@@ -535,3 +535,57 @@ def test_tuned_plan_parity(H, oracle_mod, prec):
         o0, o1 = bplan.offsets[i], bplan.offsets[i + 1]
         assert rel_l2(Vb[o0:o1], V_o.reshape(-1)) <= TOL[prec]["v"]
         assert abs(float(Eb[i]) - e_recip) <= TOL[prec]["e"] * abs(e_recip)
+
+
+# the compiled plan lengths up to 240 (the first 16 entries of the plan
+# table), which one multi-plan launch per pass serves in batched FP32 plans
+SMALL_LENGTHS = [32, 48, 60, 64, 72, 90, 96, 120, 128, 150, 160, 180, 192, 200, 210, 240]
+
+
+@pytest.mark.parametrize("lp_ab,lp_c", [(4, 3), (3, 4)])
+def test_multi_plan_launch(H, oracle_mod, lp_ab, lp_c):
+    """A batched FP32 plan whose every problem takes a compiled plan of length
+    <= 240 at one common tile width per axis (8 or 16 pencils, no pitch pad)
+    runs each pass as one launch whose workgroups pick their problem's plan:
+    every small plan on every axis, diagonal and triclinic cells, both tile
+    widths.  The solve and the backward (with grad_v and grad_e, and grad_e
+    alone) match the oracle for each problem."""
+    probs = []
+    for x in range(3):
+        for i, n in enumerate(SMALL_LENGTHS):
+            d = [32, 48, 60]
+            d[x] = n
+            d[(x + 1) % 3] = 48 if i % 2 else 32
+            probs.append((tuple(d), "triclinic" if (i + x) % 3 == 0 else "ortho"))
+    cells = np.stack([CELLS[c] for _, c in probs])
+    dims = np.array([d for d, _ in probs])
+    say("case multi-plan launch:", len(probs), "problems, tile widths", 1 << lp_ab, 1 << lp_c)
+    plan = H.Plan(cells, dims, precision="fp32", max_atoms=1)
+    cfg = plan.get_config()
+    # the table's entries 0 .. 15 are the plans of these lengths, in order
+    entry = {n: i for i, n in enumerate(SMALL_LENGTHS)}
+    for q, (d, _) in enumerate(probs):
+        for x in range(3):
+            cfg[q, x] = (entry[d[x]], lp_ab if x < 2 else lp_c, 0)
+    plan.set_config(cfg)
+    grids = [inputs.random_grid(d, 60 + q).astype(np.float32) for q, (d, _) in enumerate(probs)]
+    gvs = [inputs.random_grid(d, 160 + q).astype(np.float32) for q, (d, _) in enumerate(probs)]
+    rho_d = to_dev(np.concatenate([g.reshape(-1) for g in grids]), plan.dtype)
+    gv_d = to_dev(np.concatenate([g.reshape(-1) for g in gvs]), plan.dtype)
+    ge = torch.tensor([0.3 + 0.01 * q for q in range(len(probs))], dtype=torch.float64)
+    V, E = plan.solve(rho_d)
+    G = plan.backward(grad_v=gv_d, grad_e=ge, rho=rho_d)
+    Ge = plan.backward(grad_v=None, grad_e=ge, rho=rho_d)
+    torch.cuda.synchronize()
+    V, G, Ge = (t.double().cpu().numpy() for t in (V, G, Ge))
+    for q, (d, c) in enumerate(probs):
+        cell = CELLS[c].reshape(9)
+        rho = grids[q].astype(np.float64)
+        V_o, _, e_recip, _ = oracle_mod.poisson(cell, rho)
+        G_o = oracle_mod.backward(cell, rho, grad_v=gvs[q].astype(np.float64), grad_e=float(ge[q]))
+        G_e = oracle_mod.backward(cell, rho, grad_v=None, grad_e=float(ge[q]))
+        o0, o1 = plan.offsets[q], plan.offsets[q + 1]
+        assert rel_l2(V[o0:o1], V_o.reshape(-1)) <= TOL["fp32"]["v"], (q, d, c)
+        assert abs(float(E[q]) - e_recip) <= TOL["fp32"]["e"] * abs(e_recip), (q, d, c)
+        assert rel_l2(G[o0:o1], G_o.reshape(-1)) <= TOL["fp32"]["v"], (q, d, c)
+        assert rel_l2(Ge[o0:o1], G_e.reshape(-1)) <= TOL["fp32"]["v"], (q, d, c)
