@@ -267,7 +267,9 @@ bool multi_axis(hartree_plan p, int x)
     int64_t stride = 0;
     for (int q = 0; q < p->nprob; ++q) {
         const auto &c = p->cfg[3 * q + x];
-        if (c.plan < 0 || c.plan >= kMultiPlans || c.p_log2 != lp || c.pad != 0) return false;
+        const int *list = multi_plans(x);
+        if (std::find(list, list + kMultiPlans, c.plan) == list + kMultiPlans || c.p_log2 != lp || c.pad != 0)
+            return false;
         const ProbDesc &d = p->desc[q];
         const int64_t st = x == 0 ? int64_t(d.dims[1]) * d.dims[3] : d.dims[3];
         stride = std::max(stride, st);
@@ -1367,10 +1369,10 @@ hartree_status hartree_plan_tune(hartree_plan plan, void *grid, int32_t reps, vo
                     int id = -1;
                     for (int i = 0; i < kMultiPlans && id < 0; ++i) {
                         int rad[4];
-                        const int ns = plan_table_row(i, rad);
+                        const int ns = plan_table_row(multi_plans(x)[i], rad);
                         long prod = 1;
                         for (int k = 0; k < ns; ++k) prod *= rad[k];
-                        if (prod == n) id = i;
+                        if (prod == n) id = multi_plans(x)[i];
                     }
                     whole = id >= 0;
                     trial[3 * (3 * q + x)] = id;

@@ -578,25 +578,34 @@ __global__ __launch_bounds__(256) void k_fft_a(PassArgs a)
 // ----------------------------------------------------- multi-plan launches
 // A batched plan runs each pass as one launch per (radix plan, tile shape)
 // group.  When every problem's pencils along the pass axis have a compiled
-// plan among the first kMultiPlans entries of HARTREE_PLANS (the lengths up
-// to 240) and one common tile width CP, the host instead makes one launch of
-// these kernels: each workgroup runs the plan recorded in its problem's axis
-// descriptor.  The resources of such a kernel are the largest over its plans
-// (256 = 16 x 16 is left out: its two radix-16 stages need a third more
-// registers than any of these, which would cost every plan occupancy).
-static_assert(plan_length(kPlanRadix[kMultiPlans - 1][0], kPlanRadix[kMultiPlans - 1][1],
-                          kPlanRadix[kMultiPlans - 1][2], kPlanRadix[kMultiPlans - 1][3]) == 240 &&
-                  plan_length(kPlanRadix[kMultiPlans][0], kPlanRadix[kMultiPlans][1], kPlanRadix[kMultiPlans][2],
-                              kPlanRadix[kMultiPlans][3]) > 240,
-              "the multi-plan kernels take the table's entries up to length 240");
-
-// f(integral_constant<I>) for the plan entry I == plan (plan < kMultiPlans)
-template <int I, typename F>
-__device__ __forceinline__ void with_small_plan(int plan, F &&f)
+// plan of the axis' multi-plan list (one per length from 32 to 240) and one
+// common tile width CP, the host instead makes one launch of these kernels:
+// each workgroup runs the plan recorded in its problem's axis descriptor.
+// The resources of such a kernel are the largest over its plans (256 =
+// 16 x 16 is left out: its two radix-16 stages need a third more registers
+// than any of these, which would cost every plan occupancy).
+constexpr bool multi_list_ok(const int *list)
 {
-    if constexpr (I < kMultiPlans) {
-        if (plan == I) f(std::integral_constant<int, I>());
-        else with_small_plan<I + 1>(plan, f);
+    int prev = 0;
+    for (int k = 0; k < kMultiPlans; ++k) {
+        const int *r = kPlanRadix[list[k]];
+        const int n = plan_length(r[0], r[1], r[2], r[3]);
+        if (n <= prev || n > 240) return false;
+        prev = n;
+    }
+    return true;
+}
+static_assert(multi_list_ok(kMultiPlansAB) && multi_list_ok(kMultiPlansC),
+              "each multi-plan list has one plan per length, ascending, up to 240");
+
+// f(integral_constant<E>) for the entry E == plan of the list (none if the
+// plan is not in it)
+template <const int *LIST, int K = 0, typename F>
+__device__ __forceinline__ void with_multi_plan(int plan, F &&f)
+{
+    if constexpr (K < kMultiPlans) {
+        if (plan == LIST[K]) f(std::integral_constant<int, LIST[K]>());
+        else with_multi_plan<LIST, K + 1>(plan, f);
     }
 }
 
@@ -607,7 +616,7 @@ __global__ __launch_bounds__(256) void k_r2c_multi(PassArgs a)
 {
     int prob, tile;
     find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
-    with_small_plan<0>(a.desc[prob].ax[2].cplan, [&](auto ic) {
+    with_multi_plan<kMultiPlansC>(a.desc[prob].ax[2].cplan, [&](auto ic) {
         r2c_tile<T, MODE, HARTREE_RADICES(decltype(ic)::value), CP>(a, prob, tile);
     });
 }
@@ -617,7 +626,7 @@ __global__ __launch_bounds__(256) void k_c2r_multi(PassArgs a)
 {
     int prob, tile;
     find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
-    with_small_plan<0>(a.desc[prob].ax[2].cplan, [&](auto ic) {
+    with_multi_plan<kMultiPlansC>(a.desc[prob].ax[2].cplan, [&](auto ic) {
         c2r_tile<T, HARTREE_RADICES(decltype(ic)::value), CP>(a, prob, tile);
     });
 }
@@ -627,7 +636,7 @@ __global__ __launch_bounds__(256) void k_fft_b_multi(PassArgs a)
 {
     int prob, tile;
     find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
-    with_small_plan<0>(a.desc[prob].ax[1].cplan, [&](auto ic) {
+    with_multi_plan<kMultiPlansAB>(a.desc[prob].ax[1].cplan, [&](auto ic) {
         fft_b_tile<T, HARTREE_RADICES(decltype(ic)::value), CP>(a, prob, tile);
     });
 }
@@ -637,7 +646,7 @@ __global__ __launch_bounds__(256) void k_fft_a_multi(PassArgs a)
 {
     int prob, tile;
     find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
-    with_small_plan<0>(a.desc[prob].ax[0].cplan, [&](auto ic) {
+    with_multi_plan<kMultiPlansAB>(a.desc[prob].ax[0].cplan, [&](auto ic) {
         fft_a_tile<T, HARTREE_RADICES(decltype(ic)::value), CP>(a, prob, tile);
     });
 }

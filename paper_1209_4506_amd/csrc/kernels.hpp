@@ -42,13 +42,18 @@ struct PassArgs {
 };
 
 // Multi-plan launches (FP32): one launch per pass for the problems of a
-// batched plan when each one's axis takes a compiled plan among the first
-// kMultiPlans table entries (lengths up to 240), with one common tile width
-// of 2^kMultiLogP0 or 2^kMultiLogP1 pencils and no pitch pad; such a launch
-// carries plan kMultiPlan.
+// batched plan when each one's axis takes a compiled plan of the axis' list
+// below (one per length from 32 to 240: the table's first 16 entries along a
+// and b; along c the entries for 48, 128 and 160 without a radix-16 stage),
+// with one common tile width of 2^kMultiLogP0 or 2^kMultiLogP1 pencils and
+// no pitch pad; such a launch carries plan kMultiPlan.
 constexpr int kMultiPlans = 16;
+constexpr int kMultiPlansAB[kMultiPlans] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15};
+constexpr int kMultiPlansC[kMultiPlans] = {0, 41, 2, 3, 4, 5, 6, 7, 42, 9, 43, 11, 12, 13, 14, 15};
 constexpr int kMultiLogP0 = 3, kMultiLogP1 = 4;
 constexpr int kMultiPlan = -2;
+// the multi-plan list of axis x (0 = a, 1 = b, 2 = c)
+inline const int *multi_plans(int x) { return x == 2 ? kMultiPlansC : kMultiPlansAB; }
 
 int pass_p_log2(int fp64, int n, const int *radix, int nstages, int max_p);
 int pass_min_tpp(int fp64, int n, const int *radix, int nstages);

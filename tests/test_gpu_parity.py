@@ -562,11 +562,14 @@ def test_multi_plan_launch(H, oracle_mod, lp_ab, lp_c):
     say("case multi-plan launch:", len(probs), "problems, tile widths", 1 << lp_ab, 1 << lp_c)
     plan = H.Plan(cells, dims, precision="fp32", max_atoms=1)
     cfg = plan.get_config()
-    # the table's entries 0 .. 15 are the plans of these lengths, in order
+    # along a and b the table's entries 0 .. 15 are the plans of these
+    # lengths, in order; along c the entries 41, 42, 43 (no radix-16 stage)
+    # stand for 48, 128 and 160
     entry = {n: i for i, n in enumerate(SMALL_LENGTHS)}
+    entry_c = {**entry, 48: 41, 128: 42, 160: 43}
     for q, (d, _) in enumerate(probs):
         for x in range(3):
-            cfg[q, x] = (entry[d[x]], lp_ab if x < 2 else lp_c, 0)
+            cfg[q, x] = (entry[d[x]], lp_ab, 0) if x < 2 else (entry_c[d[x]], lp_c, 0)
     plan.set_config(cfg)
     grids = [inputs.random_grid(d, 60 + q).astype(np.float32) for q, (d, _) in enumerate(probs)]
     gvs = [inputs.random_grid(d, 160 + q).astype(np.float32) for q, (d, _) in enumerate(probs)]
