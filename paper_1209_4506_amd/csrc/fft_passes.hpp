@@ -49,12 +49,18 @@ struct VecW<double> {
     __device__ static V zero() { return V{0.0, 0.0}; }
 };
 
+// the problem and tile of work item `item`: the last i with start[i] <= item,
+// by bisection over the launch's problems (uniform scalar loads)
 __device__ __forceinline__ void find_item(const TileList &tl, int item, int &prob, int &tile)
 {
-    int i = 0;
-    while (i + 1 < tl.count && item >= tl.start[i + 1]) ++i;
-    prob = tl.prob[i];
-    tile = item - tl.start[i];
+    int lo = 0, hi = tl.count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (item >= tl.start[mid]) lo = mid;
+        else hi = mid - 1;
+    }
+    prob = tl.prob[lo];
+    tile = item - tl.start[lo];
 }
 
 template <typename T>

@@ -358,9 +358,7 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a, int rank_words)
             a.cursor[b] = 0;
         }
     }
-    int prob = 0;
-    if (cnt > 0)
-        while (prob + 1 < a.nprob && b >= a.desc[prob + 1].brick_off) ++prob;
+    const int prob = cnt > 0 ? brick_prob(a, b) : 0;
     const int a0 = a.atom_off[prob];
     const int span = a.atom_off[prob + 1] - a0;
     // ranks from the bitmap cost about span / 32 word operations per

@@ -6,11 +6,17 @@
 
 namespace hartree {
 
+// the problem of an atom / a brick: the last p whose first atom / brick is
+// at or below it, by bisection over the problems
 __device__ __forceinline__ int find_prob_atom(const SplatArgs &a, int atom)
 {
-    int p = 0;
-    while (p + 1 < a.nprob && atom >= a.atom_off[p + 1]) ++p;
-    return p;
+    int lo = 0, hi = a.nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (atom >= a.atom_off[mid]) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
 }
 
 __device__ __forceinline__ int wrapi(int i, int n)
@@ -49,9 +55,13 @@ __device__ __forceinline__ void atom_bricks(const AtomInfo &in, const ProbDesc &
 
 __device__ __forceinline__ int brick_prob(const SplatArgs &a, int64_t b)
 {
-    int p = 0;
-    while (p + 1 < a.nprob && b >= a.desc[p + 1].brick_off) ++p;
-    return p;
+    int lo = 0, hi = a.nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b >= a.desc[mid].brick_off) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
 }
 
 // brick index of this workgroup: from the binning's work order where there
