@@ -255,28 +255,32 @@ void add_launch(std::vector<Launch> &v, int plan, int p_log2, int pad, int n, in
 
 // launch groups of the three pass kinds and the E_H partial slots from the
 // per-axis choices in p->cfg
-// whether every problem's axis x qualifies for one multi-plan launch (FP32
-// batched plans): a compiled plan of length <= 256, one common tile width of
-// the multi-plan kernels, no pitch pad, and (strided axes) 32-bit lane
-// offsets
-bool multi_axis(hartree_plan p, int x)
+// The multi-plan launch shape of axis x (FP32 batched plans), or -1: every
+// problem on a plan of the axis' multi-plan list with no pitch pad and either
+// one common tile width of the fixed shapes (returns its log2) or each at its
+// length's size-adapted width (returns kMultiAutoLog); on the strided axes
+// the lanes' byte offsets must fit 32 bits.
+int multi_axis(hartree_plan p, int x)
 {
-    if (p->nprob < 2 || p->fp64) return false;
-    const int lp = p->cfg[x].p_log2;
-    if (lp != kMultiLogP0 && lp != kMultiLogP1) return false;
-    int64_t stride = 0;
+    if (p->nprob < 2 || p->fp64) return -1;
+    const int lp0 = p->cfg[x].p_log2;
+    bool common = lp0 == kMultiLogP0 || lp0 == kMultiLogP1, sized = true;
+    const int *list = multi_plans(x);
     for (int q = 0; q < p->nprob; ++q) {
         const auto &c = p->cfg[3 * q + x];
-        const int *list = multi_plans(x);
-        if (std::find(list, list + kMultiPlans, c.plan) == list + kMultiPlans || c.p_log2 != lp || c.pad != 0)
-            return false;
+        if (std::find(list, list + kMultiPlans, c.plan) == list + kMultiPlans || c.pad != 0) return -1;
         const ProbDesc &d = p->desc[q];
-        const int64_t st = x == 0 ? int64_t(d.dims[1]) * d.dims[3] : d.dims[3];
-        stride = std::max(stride, st);
+        common = common && c.p_log2 == lp0;
+        sized = sized && (1 << c.p_log2) == multi_auto_p(d.dims[x], x);
+        if (x < 2) {
+            // the compiled strided tiles address lanes with 32-bit byte offsets
+            const int64_t st = x == 0 ? int64_t(d.dims[1]) * d.dims[3] : d.dims[3];
+            const int64_t P = int64_t(1) << c.p_log2, tpp = 256 / P;  // 256 threads per pass workgroup
+            if (((tpp - 1) * st + P) * 8 >= (int64_t(1) << 32)) return -1;
+        }
     }
-    // the compiled strided tiles address lanes with 32-bit byte offsets
-    const int64_t tpp = 256 >> lp;  // 256 threads per pass workgroup
-    return x == 2 || ((tpp - 1) * stride + (int64_t(1) << lp)) * 8 < (int64_t(1) << 32);
+    if (common) return lp0;
+    return sized ? kMultiAutoLog : -1;
 }
 
 void rebuild_launches(hartree_plan p)
@@ -285,7 +289,7 @@ void rebuild_launches(hartree_plan p)
     p->lb.clear();
     p->la.clear();
     p->nparts = 0;
-    bool multi[3];
+    int multi[3];
     for (int x = 0; x < 3; ++x) multi[x] = multi_axis(p, x);
     for (int q = 0; q < p->nprob; ++q) {
         ProbDesc &d = p->desc[q];
@@ -298,9 +302,12 @@ void rebuild_launches(hartree_plan p)
         const int64_t t3 = (int64_t(d.dims[1]) * d.dims[3] + pa - 1) / pa;
         // a multi-plan axis puts every problem in one launch group (the
         // kernel reads each problem's plan from its descriptor)
-        add_launch(p->lr2c, multi[2] ? kMultiPlan : c[2].plan, c[2].p_log2, c[2].pad, d.dims[2], 0, q, int(t1));
-        add_launch(p->lb, multi[1] ? kMultiPlan : c[1].plan, c[1].p_log2, c[1].pad, d.dims[1], d.dims[3], q, int(t2));
-        add_launch(p->la, multi[0] ? kMultiPlan : c[0].plan, c[0].p_log2, c[0].pad, d.dims[0],
+        // (launch shape: the common tile width, or kMultiAutoLog for tiles
+        // sized per length; the tile counts above use each problem's own)
+        auto shape = [&](int x) { return multi[x] >= 0 ? multi[x] : c[x].p_log2; };
+        add_launch(p->lr2c, multi[2] >= 0 ? kMultiPlan : c[2].plan, shape(2), c[2].pad, d.dims[2], 0, q, int(t1));
+        add_launch(p->lb, multi[1] >= 0 ? kMultiPlan : c[1].plan, shape(1), c[1].pad, d.dims[1], d.dims[3], q, int(t2));
+        add_launch(p->la, multi[0] >= 0 ? kMultiPlan : c[0].plan, shape(0), c[0].pad, d.dims[0],
                    int64_t(d.dims[1]) * d.dims[3], q, int(t3));
         d.part_off = p->nparts;
         d.nparts = int(t3);
@@ -1360,7 +1367,7 @@ hartree_status hartree_plan_tune(hartree_plan plan, void *grid, int32_t reps, vo
         if (result == HARTREE_OK && plan->nprob > 1 && !plan->fp64) {
             float ms_best = 0.0f;
             if (!time_axis(x, cfg, ms_best)) ms_best = 0.0f;
-            for (int lp : {kMultiLogP0, kMultiLogP1}) {
+            for (int lp : {kMultiLogP0, kMultiLogP1, kMultiAutoLog}) {
                 if (result != HARTREE_OK || ms_best == 0.0f) break;
                 std::vector<int32_t> trial = cfg;
                 bool whole = true;
@@ -1375,8 +1382,12 @@ hartree_status hartree_plan_tune(hartree_plan plan, void *grid, int32_t reps, vo
                         if (prod == n) id = multi_plans(x)[i];
                     }
                     whole = id >= 0;
+                    int l2 = lp;
+                    if (lp == kMultiAutoLog)
+                        for (l2 = 0; (1 << l2) < multi_auto_p(n, x); ++l2) {
+                        }
                     trial[3 * (3 * q + x)] = id;
-                    trial[3 * (3 * q + x) + 1] = lp;
+                    trial[3 * (3 * q + x) + 1] = l2;
                     trial[3 * (3 * q + x) + 2] = 0;
                 }
                 float ms = 0.0f;

@@ -604,6 +604,36 @@ constexpr bool multi_list_ok(const int *list)
 static_assert(multi_list_ok(kMultiPlansAB) && multi_list_ok(kMultiPlansC),
               "each multi-plan list has one plan per length, ascending, up to 240");
 
+// whether every stage of a plan fits its registers with tpp threads per
+// pencil (what the host checks for every configuration it accepts)
+constexpr bool plan_fits(const int *r, int tpp)
+{
+    int n = 1;
+    for (int s = 0; s < 4; ++s) n *= r[s] > 0 ? r[s] : 1;
+    for (int s = 0; s < 4; ++s)
+        if (r[s] > 0 && (n / r[s] + tpp - 1) / tpp > stage_maxb<float>(r[s])) return false;
+    return true;
+}
+constexpr bool multi_auto_ok(const int *list, int x)
+{
+    for (int k = 0; k < kMultiPlans; ++k) {
+        const int *r = kPlanRadix[list[k]];
+        if (!plan_fits(r, kPassThreads / multi_auto_p(plan_length(r[0], r[1], r[2], r[3]), x))) return false;
+    }
+    return true;
+}
+static_assert(multi_auto_ok(kMultiPlansAB, 0) && multi_auto_ok(kMultiPlansC, 2),
+              "the size-adapted tiles leave every listed plan enough threads per pencil");
+
+// the tile width of plan entry E in a multi-plan kernel of width W (0: sized
+// per length) along axis x
+template <int W, int E, int X>
+constexpr int multi_cp()
+{
+    return W > 0 ? W : multi_auto_p(plan_length(kPlanRadix[E][0], kPlanRadix[E][1], kPlanRadix[E][2],
+                                                 kPlanRadix[E][3]), X);
+}
+
 // f(integral_constant<E>) for the entry E == plan of the list (none if the
 // plan is not in it)
 template <const int *LIST, int K = 0, typename F>
@@ -623,7 +653,7 @@ __global__ __launch_bounds__(256) void k_r2c_multi(PassArgs a)
     int prob, tile;
     find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
     with_multi_plan<kMultiPlansC>(a.desc[prob].ax[2].cplan, [&](auto ic) {
-        r2c_tile<T, MODE, HARTREE_RADICES(decltype(ic)::value), CP>(a, prob, tile);
+        r2c_tile<T, MODE, HARTREE_RADICES(decltype(ic)::value), multi_cp<CP, decltype(ic)::value, 2>()>(a, prob, tile);
     });
 }
 
@@ -633,7 +663,7 @@ __global__ __launch_bounds__(256) void k_c2r_multi(PassArgs a)
     int prob, tile;
     find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
     with_multi_plan<kMultiPlansC>(a.desc[prob].ax[2].cplan, [&](auto ic) {
-        c2r_tile<T, HARTREE_RADICES(decltype(ic)::value), CP>(a, prob, tile);
+        c2r_tile<T, HARTREE_RADICES(decltype(ic)::value), multi_cp<CP, decltype(ic)::value, 2>()>(a, prob, tile);
     });
 }
 
@@ -643,7 +673,7 @@ __global__ __launch_bounds__(256) void k_fft_b_multi(PassArgs a)
     int prob, tile;
     find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
     with_multi_plan<kMultiPlansAB>(a.desc[prob].ax[1].cplan, [&](auto ic) {
-        fft_b_tile<T, HARTREE_RADICES(decltype(ic)::value), CP>(a, prob, tile);
+        fft_b_tile<T, HARTREE_RADICES(decltype(ic)::value), multi_cp<CP, decltype(ic)::value, 1>()>(a, prob, tile);
     });
 }
 
@@ -653,7 +683,7 @@ __global__ __launch_bounds__(256) void k_fft_a_multi(PassArgs a)
     int prob, tile;
     find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
     with_multi_plan<kMultiPlansAB>(a.desc[prob].ax[0].cplan, [&](auto ic) {
-        fft_a_tile<T, HARTREE_RADICES(decltype(ic)::value), CP>(a, prob, tile);
+        fft_a_tile<T, HARTREE_RADICES(decltype(ic)::value), multi_cp<CP, decltype(ic)::value, 0>()>(a, prob, tile);
     });
 }
 
@@ -710,6 +740,24 @@ inline size_t pass_lds_bytes(const PassArgs &a, int maxn)
     const size_t P = size_t(1) << a.p_log2;
     const size_t strided = (P + size_t(a.pad)) * maxn, rows = P * (maxn + 31);
     return sizeof(Cx<T>) * ((strided > rows ? strided : rows) + maxn);
+}
+
+// LDS of a size-adapted multi-plan launch along axis x whose longest pencil
+// is maxn: the largest tile (and twiddle table) over the listed plans up to
+// that length, n P (strided axes) or P row_pitch(n) (axis c)
+template <typename T>
+inline size_t multi_auto_lds(int x, int maxn)
+{
+    size_t most = 0;
+    for (int k = 0; k < kMultiPlans; ++k) {
+        const int *r = kPlanRadix[multi_plans(x)[k]];
+        const int n = plan_length(r[0], r[1], r[2], r[3]);
+        if (n > maxn) continue;
+        const size_t P = size_t(multi_auto_p(n, x));
+        const size_t e = (x == 2 ? P * size_t(row_pitch(n)) : P * size_t(n)) + size_t(n);
+        most = e > most ? e : most;
+    }
+    return sizeof(Cx<T>) * most;
 }
 
 }  // namespace hartree

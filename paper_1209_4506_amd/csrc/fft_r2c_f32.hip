@@ -43,6 +43,7 @@ hipError_t run_r2c_f32(int plan, int maxn, int grid, hipStream_t s, const PassAr
     if (plan == kMultiPlan) {
         if (a.p_log2 == kMultiLogP0) return launch_multi<1 << kMultiLogP0>(grid, lds, s, a);
         if (a.p_log2 == kMultiLogP1) return launch_multi<1 << kMultiLogP1>(grid, lds, s, a);
+        if (a.p_log2 == kMultiAutoLog) return launch_multi<0>(grid, multi_auto_lds<float>(2, maxn), s, a);
         return hipErrorInvalidValue;
     }
     if (plan < 0 || plan >= int(sizeof(kTable) / sizeof(kTable[0])))

@@ -52,6 +52,18 @@ constexpr int kMultiPlansAB[kMultiPlans] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
 constexpr int kMultiPlansC[kMultiPlans] = {0, 41, 2, 3, 4, 5, 6, 7, 42, 9, 43, 11, 12, 13, 14, 15};
 constexpr int kMultiLogP0 = 3, kMultiLogP1 = 4;
 constexpr int kMultiPlan = -2;
+// A third multi-plan shape sizes the tile per length instead: the most
+// pencils (a power of two, at most 64 along a and b, 32 along c) whose
+// points stay within 4096 (a, b) or 2048 (c), at least 8 (a, b) or 4 (c);
+// its launches carry p_log2 = kMultiAutoLog.
+constexpr int kMultiAutoLog = 15;
+constexpr int multi_auto_p(int n, int x)
+{
+    int p = x == 2 ? 32 : 64;
+    const int lo = x == 2 ? 4 : 8, target = x == 2 ? 2048 : 4096;
+    while (p > lo && p * n > target) p >>= 1;
+    return p;
+}
 // the multi-plan list of axis x (0 = a, 1 = b, 2 = c)
 inline const int *multi_plans(int x) { return x == 2 ? kMultiPlansC : kMultiPlansAB; }
 

@@ -542,14 +542,25 @@ def test_tuned_plan_parity(H, oracle_mod, prec):
 SMALL_LENGTHS = [32, 48, 60, 64, 72, 90, 96, 120, 128, 150, 160, 180, 192, 200, 210, 240]
 
 
-@pytest.mark.parametrize("lp_ab,lp_c", [(4, 3), (3, 4)])
+def multi_auto_log2(n, x):
+    """log2 of the size-adapted multi-plan tile width for length n on axis x:
+    the most pencils (at most 64 along a and b, 32 along c) whose points stay
+    within 4096 (a, b) or 2048 (c), at least 8 (a, b) or 4 (c)."""
+    p, lo, target = (32, 4, 2048) if x == 2 else (64, 8, 4096)
+    while p > lo and p * n > target:
+        p //= 2
+    return p.bit_length() - 1
+
+
+@pytest.mark.parametrize("lp_ab,lp_c", [(4, 3), (3, 4), ("auto", "auto")])
 def test_multi_plan_launch(H, oracle_mod, lp_ab, lp_c):
     """A batched FP32 plan whose every problem takes a compiled plan of length
-    <= 240 at one common tile width per axis (8 or 16 pencils, no pitch pad)
-    runs each pass as one launch whose workgroups pick their problem's plan:
-    every small plan on every axis, diagonal and triclinic cells, both tile
-    widths.  The solve and the backward (with grad_v and grad_e, and grad_e
-    alone) match the oracle for each problem."""
+    <= 240 at one common tile width per axis (8 or 16 pencils), or each at its
+    length's size-adapted width, with no pitch pad, runs each pass as one
+    launch whose workgroups pick their problem's plan: every listed plan on
+    every axis, diagonal and triclinic cells, every tile shape.  The solve
+    and the backward (with grad_v and grad_e, and grad_e alone) match the
+    oracle for each problem."""
     probs = []
     for x in range(3):
         for i, n in enumerate(SMALL_LENGTHS):
@@ -559,7 +570,7 @@ def test_multi_plan_launch(H, oracle_mod, lp_ab, lp_c):
             probs.append((tuple(d), "triclinic" if (i + x) % 3 == 0 else "ortho"))
     cells = np.stack([CELLS[c] for _, c in probs])
     dims = np.array([d for d, _ in probs])
-    say("case multi-plan launch:", len(probs), "problems, tile widths", 1 << lp_ab, 1 << lp_c)
+    say("case multi-plan launch:", len(probs), "problems, tile widths (log2)", lp_ab, lp_c)
     plan = H.Plan(cells, dims, precision="fp32", max_atoms=1)
     cfg = plan.get_config()
     # along a and b the table's entries 0 .. 15 are the plans of these
@@ -569,7 +580,9 @@ def test_multi_plan_launch(H, oracle_mod, lp_ab, lp_c):
     entry_c = {**entry, 48: 41, 128: 42, 160: 43}
     for q, (d, _) in enumerate(probs):
         for x in range(3):
-            cfg[q, x] = (entry[d[x]], lp_ab, 0) if x < 2 else (entry_c[d[x]], lp_c, 0)
+            lp = lp_ab if x < 2 else lp_c
+            lp = multi_auto_log2(d[x], x) if lp == "auto" else lp
+            cfg[q, x] = (entry[d[x]], lp, 0) if x < 2 else (entry_c[d[x]], lp, 0)
     plan.set_config(cfg)
     grids = [inputs.random_grid(d, 60 + q).astype(np.float32) for q, (d, _) in enumerate(probs)]
     gvs = [inputs.random_grid(d, 160 + q).astype(np.float32) for q, (d, _) in enumerate(probs)]
