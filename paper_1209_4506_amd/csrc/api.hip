@@ -264,7 +264,7 @@ int multi_axis(hartree_plan p, int x)
 {
     if (p->nprob < 2 || p->fp64) return -1;
     const int lp0 = p->cfg[x].p_log2;
-    bool common = lp0 == kMultiLogP0 || lp0 == kMultiLogP1, sized = true;
+    bool common = lp0 == multi_log_p(x, 0) || lp0 == multi_log_p(x, 1), sized = true;
     const int *list = multi_plans(x);
     for (int q = 0; q < p->nprob; ++q) {
         const auto &c = p->cfg[3 * q + x];
@@ -1367,7 +1367,7 @@ hartree_status hartree_plan_tune(hartree_plan plan, void *grid, int32_t reps, vo
         if (result == HARTREE_OK && plan->nprob > 1 && !plan->fp64) {
             float ms_best = 0.0f;
             if (!time_axis(x, cfg, ms_best)) ms_best = 0.0f;
-            for (int lp : {kMultiLogP0, kMultiLogP1, kMultiAutoLog}) {
+            for (int lp : {multi_log_p(x, 0), multi_log_p(x, 1), kMultiAutoLog}) {
                 if (result != HARTREE_OK || ms_best == 0.0f) break;
                 std::vector<int32_t> trial = cfg;
                 bool whole = true;

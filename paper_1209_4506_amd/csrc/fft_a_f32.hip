@@ -35,8 +35,10 @@ hipError_t run_a_f32(int plan, int maxn, int grid, hipStream_t s, const PassArgs
 {
     const size_t lds = pass_lds_bytes<float>(a, maxn);
     if (plan == kMultiPlan) {
-        if (a.p_log2 == kMultiLogP0) return launch_pass(k_fft_a_multi<float, 1 << kMultiLogP0>, grid, lds, s, a);
-        if (a.p_log2 == kMultiLogP1) return launch_pass(k_fft_a_multi<float, 1 << kMultiLogP1>, grid, lds, s, a);
+        if (a.p_log2 == multi_log_p(0, 0))
+            return launch_pass(k_fft_a_multi<float, 1 << multi_log_p(0, 0)>, grid, lds, s, a);
+        if (a.p_log2 == multi_log_p(0, 1))
+            return launch_pass(k_fft_a_multi<float, 1 << multi_log_p(0, 1)>, grid, lds, s, a);
         if (a.p_log2 == kMultiAutoLog)
             return launch_pass(k_fft_a_multi<float, 0>, grid, multi_auto_lds<float>(0, maxn), s, a);
         return hipErrorInvalidValue;

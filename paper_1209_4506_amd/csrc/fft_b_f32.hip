@@ -29,8 +29,10 @@ hipError_t run_b_f32(int plan, int maxn, int grid, hipStream_t s, const PassArgs
 {
     const size_t lds = pass_lds_bytes<float>(a, maxn);
     if (plan == kMultiPlan) {
-        if (a.p_log2 == kMultiLogP0) return launch_pass(k_fft_b_multi<float, 1 << kMultiLogP0>, grid, lds, s, a);
-        if (a.p_log2 == kMultiLogP1) return launch_pass(k_fft_b_multi<float, 1 << kMultiLogP1>, grid, lds, s, a);
+        if (a.p_log2 == multi_log_p(1, 0))
+            return launch_pass(k_fft_b_multi<float, 1 << multi_log_p(1, 0)>, grid, lds, s, a);
+        if (a.p_log2 == multi_log_p(1, 1))
+            return launch_pass(k_fft_b_multi<float, 1 << multi_log_p(1, 1)>, grid, lds, s, a);
         if (a.p_log2 == kMultiAutoLog)
             return launch_pass(k_fft_b_multi<float, 0>, grid, multi_auto_lds<float>(1, maxn), s, a);
         return hipErrorInvalidValue;

@@ -41,8 +41,8 @@ hipError_t run_r2c_f32(int plan, int maxn, int grid, hipStream_t s, const PassAr
 {
     const size_t lds = pass_lds_bytes<float>(a, maxn);
     if (plan == kMultiPlan) {
-        if (a.p_log2 == kMultiLogP0) return launch_multi<1 << kMultiLogP0>(grid, lds, s, a);
-        if (a.p_log2 == kMultiLogP1) return launch_multi<1 << kMultiLogP1>(grid, lds, s, a);
+        if (a.p_log2 == multi_log_p(2, 0)) return launch_multi<1 << multi_log_p(2, 0)>(grid, lds, s, a);
+        if (a.p_log2 == multi_log_p(2, 1)) return launch_multi<1 << multi_log_p(2, 1)>(grid, lds, s, a);
         if (a.p_log2 == kMultiAutoLog) return launch_multi<0>(grid, multi_auto_lds<float>(2, maxn), s, a);
         return hipErrorInvalidValue;
     }

@@ -45,12 +45,14 @@ struct PassArgs {
 // batched plan when each one's axis takes a compiled plan of the axis' list
 // below (one per length from 32 to 240: the table's first 16 entries along a
 // and b; along c the entries for 48, 128 and 160 without a radix-16 stage),
-// with one common tile width of 2^kMultiLogP0 or 2^kMultiLogP1 pencils and
+// with one common tile width of 2^multi_log_p(x, 0 or 1) pencils and
 // no pitch pad; such a launch carries plan kMultiPlan.
 constexpr int kMultiPlans = 16;
 constexpr int kMultiPlansAB[kMultiPlans] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15};
 constexpr int kMultiPlansC[kMultiPlans] = {0, 41, 2, 3, 4, 5, 6, 7, 42, 9, 43, 11, 12, 13, 14, 15};
-constexpr int kMultiLogP0 = 3, kMultiLogP1 = 4;
+// the two fixed tile widths (log2) of multi-plan launches along axis x: 8
+// and 16 pencils along a and b, 4 and 8 along c
+constexpr int multi_log_p(int x, int k) { return x == 2 ? 2 + k : 3 + k; }
 constexpr int kMultiPlan = -2;
 // A third multi-plan shape sizes the tile per length instead: the most
 // pencils (a power of two, at most 64 along a and b, 32 along c) whose

@@ -552,10 +552,11 @@ def multi_auto_log2(n, x):
     return p.bit_length() - 1
 
 
-@pytest.mark.parametrize("lp_ab,lp_c", [(4, 3), (3, 4), ("auto", "auto")])
+@pytest.mark.parametrize("lp_ab,lp_c", [(4, 2), (3, 3), ("auto", "auto")])
 def test_multi_plan_launch(H, oracle_mod, lp_ab, lp_c):
     """A batched FP32 plan whose every problem takes a compiled plan of length
-    <= 240 at one common tile width per axis (8 or 16 pencils), or each at its
+    <= 240 at one common tile width per axis (8 or 16 pencils along a and b,
+    4 or 8 along c), or each at its
     length's size-adapted width, with no pitch pad, runs each pass as one
     launch whose workgroups pick their problem's plan: every listed plan on
     every axis, diagonal and triclinic cells, every tile shape.  The solve
