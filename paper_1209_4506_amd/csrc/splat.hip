@@ -184,6 +184,13 @@ __global__ __launch_bounds__(256) void k_brick_visit(SplatArgs a)
 // FP32 splat scales its 16-bit operands by it).
 constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 16;
+// Work order of the bricks for the matrix-core kernels of batched plans
+// (a.order, written by the same workgroup after the scan): a counting sort
+// by descending number of 16-atom groups, so that the longest bricks start
+// first and the short ones fill the tail.  The order within a group count is
+// whatever the LDS atomics give: each brick writes only its own outputs, so
+// results do not depend on it.
+constexpr int kOrderKeys = 32;
 
 // the weight |Z| (2 pi sigma^2)^(-3/2) of a valid atom in float (a bound
 // for scaling: clamped to the float range), 0 for an invalid one
@@ -324,6 +331,26 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(SplatArgs a)
     if (t == 0) {
         a.offsets[n] = int32_t(carry < a.capacity ? carry : a.capacity);
         if (carry > a.capacity) atomicOr(&a.status->bits, 0x4u);
+    }
+    if (a.order) {
+        __shared__ int hist[kOrderKeys], next[kOrderKeys];
+        auto key = [&](int64_t b) {
+            const int k = (a.counts[b] + 15) >> 4;
+            return k < kOrderKeys - 1 ? k : kOrderKeys - 1;
+        };
+        if (t < kOrderKeys) hist[t] = 0;
+        __syncthreads();
+        for (int64_t b = t; b < n; b += kScanThreads) atomicAdd(&hist[key(b)], 1);
+        __syncthreads();
+        if (t == 0) {
+            int run = 0;
+            for (int k = kOrderKeys - 1; k >= 0; --k) {
+                next[k] = run;
+                run += hist[k];
+            }
+        }
+        __syncthreads();
+        for (int64_t b = t; b < n; b += kScanThreads) a.order[atomicAdd(&next[key(b)], 1)] = int32_t(b);
     }
 }
 
@@ -468,39 +495,6 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a, int rank_words)
     }
 }
 
-// Work order of the bricks for the matrix-core kernels of batched plans
-// (one workgroup): a counting sort by descending number of 16-atom groups,
-// so that the longest bricks start first and the short ones fill the tail.
-// The order within a group count is whatever the LDS atomics give: each
-// brick writes only its own outputs, so results do not depend on it.
-constexpr int kOrderThreads = 1024;
-constexpr int kOrderKeys = 32;
-
-__global__ __launch_bounds__(kOrderThreads) void k_brick_order(SplatArgs a)
-{
-    __shared__ int hist[kOrderKeys], next[kOrderKeys];
-    const int t = threadIdx.x;
-    if (t < kOrderKeys) hist[t] = 0;
-    __syncthreads();
-    const int64_t n = a.nbricks_total;
-    auto key = [&](int64_t b) {
-        const int c = a.offsets[b + 1] - a.offsets[b];
-        const int k = (c + 15) >> 4;
-        return k < kOrderKeys - 1 ? k : kOrderKeys - 1;
-    };
-    for (int64_t b = t; b < n; b += kOrderThreads) atomicAdd(&hist[key(b)], 1);
-    __syncthreads();
-    if (t == 0) {
-        int run = 0;
-        for (int k = kOrderKeys - 1; k >= 0; --k) {
-            next[k] = run;
-            run += hist[k];
-        }
-    }
-    __syncthreads();
-    for (int64_t b = t; b < n; b += kOrderThreads) a.order[atomicAdd(&next[key(b)], 1)] = int32_t(b);
-}
-
 // one wavefront per atom: lanes sum its per-brick partials (slots from the
 // sort) in a fixed order, then a fixed butterfly combines the lanes
 __global__ __launch_bounds__(256) void k_adjoint_final(SplatArgs a)
@@ -564,7 +558,6 @@ hipError_t run_bin(const SplatArgs &a, hipStream_t s)
     const int rank_words = words <= kRankWords ? words : 0;
     hipLaunchKernelGGL(k_brick_sort, dim3(int((nbt + 3) / 4)), dim3(256), size_t(rank_words) * 4 * 2 * 4, s, a,
                        rank_words);
-    if (a.order) hipLaunchKernelGGL(k_brick_order, dim3(1), dim3(kOrderThreads), 0, s, a);
     return hipGetLastError();
 }
 
