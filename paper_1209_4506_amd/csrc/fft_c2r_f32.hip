@@ -29,12 +29,14 @@ hipError_t run_c2r_f32(int plan, int maxn, int grid, hipStream_t s, const PassAr
 {
     const size_t lds = pass_lds_bytes<float>(a, maxn);
     if (plan == kMultiPlan) {
+        // the multi-plan c2r tiles stage their rows in LDS (stage_lds)
+        const size_t lds_staged = lds + stage_lds<float>(1 << (a.p_log2 & 7), maxn);
         if (a.p_log2 == multi_log_p(2, 0))
-            return launch_pass(k_c2r_multi<float, 1 << multi_log_p(2, 0)>, grid, lds, s, a);
+            return launch_pass(k_c2r_multi<float, 1 << multi_log_p(2, 0)>, grid, lds_staged, s, a);
         if (a.p_log2 == multi_log_p(2, 1))
-            return launch_pass(k_c2r_multi<float, 1 << multi_log_p(2, 1)>, grid, lds, s, a);
+            return launch_pass(k_c2r_multi<float, 1 << multi_log_p(2, 1)>, grid, lds_staged, s, a);
         if (a.p_log2 == kMultiAutoLog)
-            return launch_pass(k_c2r_multi<float, 0>, grid, multi_auto_lds<float>(2, maxn), s, a);
+            return launch_pass(k_c2r_multi<float, 0>, grid, multi_auto_lds<float>(2, maxn, true), s, a);
         return hipErrorInvalidValue;
     }
     if (plan < 0 || plan >= int(sizeof(kTable) / sizeof(kTable[0])))

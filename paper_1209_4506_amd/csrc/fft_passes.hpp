@@ -161,6 +161,39 @@ struct RealPairOut {
     }
 };
 
+constexpr int kStageUnroll = 8;  // staging loads each thread keeps in flight
+
+// Staged variants of the c-axis accessors (the multi-plan kernels of batched
+// plans, whose short rows leave most lanes of a pencil idle in the first and
+// last stages): a tile's rows are contiguous in the grid and in the half
+// spectrum, so the workgroup moves them between global memory and an LDS
+// block with every lane on consecutive elements, and the stages read and
+// write that block.
+// P1 input from the block: element i of rows 2q and 2q + 1
+template <typename T>
+struct LdsRealPairIn {
+    static constexpr bool kLds = true;
+    const T *r;  // row 2q of the block; row 2q + 1 follows at r + n
+    int n;
+    __device__ __forceinline__ Cx<T> load(int i) const { return Cx<T>{r[i], r[n + i]}; }
+    __device__ __forceinline__ Cx<T> load_at(int u, int t) const { return load(u + t); }
+};
+
+// P5 output into the block: the conjugate of the last stage's value is
+// x + i y for rows 2q and 2q + 1
+template <typename T>
+struct LdsRealPairOut {
+    static constexpr bool kLds = false;
+    T *o;  // row 2q of the block; row 2q + 1 follows at o + n
+    int n;
+    __device__ __forceinline__ void store(int i, Cx<T> v) const
+    {
+        o[i] = v.x;
+        o[n + i] = -v.y;
+    }
+    __device__ __forceinline__ void store_at(int u, int t, Cx<T> v) const { store(u + t, v); }
+};
+
 // pencil-major tile pitch: n rounded so that consecutive pencils start in
 // opposite halves of the LDS banks
 __host__ __device__ constexpr int row_pitch(int n) { return n + ((16 - n % 32) + 32) % 32; }
@@ -177,7 +210,9 @@ constexpr int plan_length(int r0, int r1, int r2, int r3)
 // CP > 0 (passes along c; a compiled plan): tiles of exactly CP pencils
 // (2 CP rows), launched only for that shape, with the pencil length (the
 // plan's) compiled in as well, so tile offsets and loop bounds are constants.
-template <typename T, int MODE, int R0, int R1, int R2, int R3, int CP>
+// STAGE: the tile's rows are loaded into an LDS block after the twiddles
+// first (2 P n reals; see LdsRealPairIn).
+template <typename T, int MODE, int R0, int R1, int R2, int R3, int CP, bool STAGE = false>
 __device__ __forceinline__ void r2c_tile(const PassArgs &a, int prob, int tile)
 {
     constexpr int NT = kPassThreads;
@@ -203,22 +238,58 @@ __device__ __forceinline__ void r2c_tile(const PassArgs &a, int prob, int tile)
     const bool v0 = 2 * q < rows, v1 = 2 * q + 1 < rows;
     const int64_t g_even = d.grid_off + (row0 + (v0 ? 2 * q : 0)) * n;
     const int64_t g_odd = d.grid_off + (row0 + (v1 ? 2 * q + 1 : 0)) * n;
-    RealPairIn<T, MODE> in;
-    in.r0 = reinterpret_cast<const T *>(a.in) + g_even;
-    in.r1 = reinterpret_cast<const T *>(a.in) + g_odd;
-    in.h0 = reinterpret_cast<const T *>(a.in2) + g_even;
-    in.h1 = reinterpret_cast<const T *>(a.in2) + g_odd;
-    in.w0 = v0 ? T(1) : T(0);
-    in.w1 = v1 ? T(1) : T(0);
     const T scale = MODE == 0 ? T(0) : T(a.grad_e[prob] * d.dv);
-    in.s0 = scale * in.w0;
-    in.s1 = scale * in.w1;
     const LdsRow<T> lr{buf, ldp, q, false};
-    if (d.ax[2].nstages > 0) {
-        LdsRow<T> out = lr;
-        fft_any<T, R0, R1, R2, R3>(in, out, lr, tw, d.ax[2], tip, TPP);
-    } else if (tip == 0) {
-        lr.store(0, in.load(0));
+    if constexpr (STAGE) {
+        // the rows (zero beyond the grid) into the block, every lane on
+        // consecutive reals
+        T *blk = reinterpret_cast<T *>(tw + n);
+        const int64_t g0 = d.grid_off + row0 * n;
+        const T *x = reinterpret_cast<const T *>(a.in) + g0;
+        const T *h = reinterpret_cast<const T *>(a.in2) + g0;
+        // (kStageUnroll loads in flight per thread before their stores)
+        const int cnt = rows * n, tot = 2 * P * n;
+        for (int e0 = tid; e0 < tot; e0 += kStageUnroll * NT) {
+            T v[kStageUnroll];
+#pragma unroll
+            for (int u = 0; u < kStageUnroll; ++u) {
+                const int e = e0 + u * NT;
+                v[u] = T(0);
+                if (e < cnt) {
+                    if constexpr (MODE == 0) v[u] = __builtin_nontemporal_load(x + e);
+                    else if constexpr (MODE == 1)
+                        v[u] = __builtin_nontemporal_load(x + e) + scale * __builtin_nontemporal_load(h + e);
+                    else v[u] = scale * __builtin_nontemporal_load(h + e);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kStageUnroll; ++u)
+                if (e0 + u * NT < tot) blk[e0 + u * NT] = v[u];
+        }
+        __syncthreads();
+        const LdsRealPairIn<T> in{blk + 2 * q * n, n};
+        if (d.ax[2].nstages > 0) {
+            LdsRow<T> out = lr;
+            fft_any<T, R0, R1, R2, R3>(in, out, lr, tw, d.ax[2], tip, TPP);
+        } else if (tip == 0) {
+            lr.store(0, in.load(0));
+        }
+    } else {
+        RealPairIn<T, MODE> in;
+        in.r0 = reinterpret_cast<const T *>(a.in) + g_even;
+        in.r1 = reinterpret_cast<const T *>(a.in) + g_odd;
+        in.h0 = reinterpret_cast<const T *>(a.in2) + g_even;
+        in.h1 = reinterpret_cast<const T *>(a.in2) + g_odd;
+        in.w0 = v0 ? T(1) : T(0);
+        in.w1 = v1 ? T(1) : T(0);
+        in.s0 = scale * in.w0;
+        in.s1 = scale * in.w1;
+        if (d.ax[2].nstages > 0) {
+            LdsRow<T> out = lr;
+            fft_any<T, R0, R1, R2, R3>(in, out, lr, tw, d.ax[2], tip, TPP);
+        } else if (tip == 0) {
+            lr.store(0, in.load(0));
+        }
     }
     __syncthreads();
 
@@ -250,7 +321,10 @@ __global__ __launch_bounds__(256) void k_r2c_mode(PassArgs a)
 
 // ---------------------------------------------------------------- P5
 // CP > 0: as for P1
-template <typename T, int R0, int R1, int R2, int R3, int CP>
+// STAGE: the tile's half-spectrum rows are loaded into an LDS block after
+// the twiddles first (2 P nh complex), and the real rows are written there
+// and then copied out (2 P n reals, in the same block; see LdsRealPairOut).
+template <typename T, int R0, int R1, int R2, int R3, int CP, bool STAGE = false>
 __device__ __forceinline__ void c2r_tile(const PassArgs &a, int prob, int tile)
 {
     constexpr int NT = kPassThreads;
@@ -273,23 +347,59 @@ __device__ __forceinline__ void c2r_tile(const PassArgs &a, int prob, int tile)
     const int tip = tid & (TPP - 1);  // TPP is a power of two
     const bool v0 = 2 * q < rows, v1 = 2 * q + 1 < rows;
     const Cx<T> *spec = reinterpret_cast<const Cx<T> *>(a.spec) + d.spec_off + row0 * nh;
-    HermitianPairIn<T> in;
-    in.x0 = spec + (v0 ? 2 * q : 0) * nh;
-    in.x1 = spec + (v1 ? 2 * q + 1 : 0) * nh;
-    in.n = n;
-    in.nh = nh;
-    in.w0 = v0 ? T(1) : T(0);
-    in.w1 = v1 ? T(1) : T(0);
-    RealPairOut<T> out;
-    out.o0 = reinterpret_cast<T *>(a.out) + d.grid_off + (row0 + 2 * q) * n;
-    out.o1 = out.o0 + n;
-    out.v0 = v0;
-    out.v1 = v1;
     const LdsRow<T> lr{buf, ldp, q, false};
-    if (d.ax[2].nstages > 0) {
-        fft_any<T, R0, R1, R2, R3>(in, out, lr, tw, d.ax[2], tip, TPP);
-    } else if (tip == 0) {
-        out.store(0, in.load(0));
+    if constexpr (STAGE) {
+        Cx<T> *blk = tw + n;
+        const int cnt = rows * nh, tot = 2 * P * nh;
+        for (int e0 = tid; e0 < tot; e0 += kStageUnroll * NT) {
+            Cx<T> v[kStageUnroll];
+#pragma unroll
+            for (int u = 0; u < kStageUnroll; ++u) {
+                const int e = e0 + u * NT;
+                v[u] = e < cnt ? spec[e] : Cx<T>{T(0), T(0)};
+            }
+#pragma unroll
+            for (int u = 0; u < kStageUnroll; ++u)
+                if (e0 + u * NT < tot) blk[e0 + u * NT] = v[u];
+        }
+        __syncthreads();
+        HermitianPairIn<T> in;
+        in.x0 = blk + 2 * q * nh;
+        in.x1 = blk + (2 * q + 1) * nh;
+        in.n = n;
+        in.nh = nh;
+        in.w0 = T(1);
+        in.w1 = T(1);
+        // the last stage writes the real rows over the block, whose reads
+        // all precede the first stage's barrier
+        const LdsRealPairOut<T> out{reinterpret_cast<T *>(blk) + 2 * q * n, n};
+        if (d.ax[2].nstages > 0) {
+            fft_any<T, R0, R1, R2, R3>(in, out, lr, tw, d.ax[2], tip, TPP);
+        } else if (tip == 0) {
+            out.store(0, in.load(0));
+        }
+        __syncthreads();
+        const T *rb = reinterpret_cast<const T *>(blk);
+        T *dst = reinterpret_cast<T *>(a.out) + d.grid_off + row0 * n;
+        for (int e = tid; e < rows * n; e += NT) __builtin_nontemporal_store(rb[e], dst + e);
+    } else {
+        HermitianPairIn<T> in;
+        in.x0 = spec + (v0 ? 2 * q : 0) * nh;
+        in.x1 = spec + (v1 ? 2 * q + 1 : 0) * nh;
+        in.n = n;
+        in.nh = nh;
+        in.w0 = v0 ? T(1) : T(0);
+        in.w1 = v1 ? T(1) : T(0);
+        RealPairOut<T> out;
+        out.o0 = reinterpret_cast<T *>(a.out) + d.grid_off + (row0 + 2 * q) * n;
+        out.o1 = out.o0 + n;
+        out.v0 = v0;
+        out.v1 = v1;
+        if (d.ax[2].nstages > 0) {
+            fft_any<T, R0, R1, R2, R3>(in, out, lr, tw, d.ax[2], tip, TPP);
+        } else if (tip == 0) {
+            out.store(0, in.load(0));
+        }
     }
 }
 
@@ -663,7 +773,7 @@ __global__ __launch_bounds__(256) void k_c2r_multi(PassArgs a)
     int prob, tile;
     find_item(a.tl, xcd_remap(blockIdx.x, gridDim.x), prob, tile);
     with_multi_plan<kMultiPlansC>(a.desc[prob].ax[2].cplan, [&](auto ic) {
-        c2r_tile<T, HARTREE_RADICES(decltype(ic)::value), multi_cp<CP, decltype(ic)::value, 2>()>(a, prob, tile);
+        c2r_tile<T, HARTREE_RADICES(decltype(ic)::value), multi_cp<CP, decltype(ic)::value, 2>(), true>(a, prob, tile);
     });
 }
 
@@ -745,8 +855,16 @@ inline size_t pass_lds_bytes(const PassArgs &a, int maxn)
 // LDS of a size-adapted multi-plan launch along axis x whose longest pencil
 // is maxn: the largest tile (and twiddle table) over the listed plans up to
 // that length, n P (strided axes) or P row_pitch(n) (axis c)
+// LDS block of the staged c-axis tiles: 2 P (n / 2 + 1) complex, which also
+// holds the 2 P n reals of the c2r output
 template <typename T>
-inline size_t multi_auto_lds(int x, int maxn)
+inline size_t stage_lds(int P, int n)
+{
+    return sizeof(Cx<T>) * size_t(2 * P) * size_t(n / 2 + 1);
+}
+
+template <typename T>
+inline size_t multi_auto_lds(int x, int maxn, bool staged = false)
 {
     size_t most = 0;
     for (int k = 0; k < kMultiPlans; ++k) {
@@ -754,10 +872,11 @@ inline size_t multi_auto_lds(int x, int maxn)
         const int n = plan_length(r[0], r[1], r[2], r[3]);
         if (n > maxn) continue;
         const size_t P = size_t(multi_auto_p(n, x));
-        const size_t e = (x == 2 ? P * size_t(row_pitch(n)) : P * size_t(n)) + size_t(n);
+        const size_t e = sizeof(Cx<T>) * ((x == 2 ? P * size_t(row_pitch(n)) : P * size_t(n)) + size_t(n)) +
+                         (staged ? stage_lds<T>(int(P), n) : 0);
         most = e > most ? e : most;
     }
-    return sizeof(Cx<T>) * most;
+    return most;
 }
 
 }  // namespace hartree
