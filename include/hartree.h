@@ -116,7 +116,8 @@ hartree_status hartree_plan_grid_offset(hartree_plan plan, int32_t p, int64_t *o
  * synchronizes.  Rebinding replaces the previous workspace.  The first binding
  * also creates three internal streams of default priority on the current
  * device.  Work forked onto them (the launch groups of a batched plan's
- * transform passes, i.e. problems with different pass shapes, and the E_H
+ * transform passes, i.e. problems with different pass shapes that no single
+ * multi-plan launch takes, and the E_H
  * finalize of hartree_solve, which runs beside the inverse passes) starts
  * after the work already queued on the caller's stream and is joined back
  * before the call returns, so calls stay ordered on the caller's stream
