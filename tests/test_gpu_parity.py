@@ -606,3 +606,38 @@ def test_multi_plan_launch(H, oracle_mod, lp_ab, lp_c):
         assert abs(float(E[q]) - e_recip) <= TOL["fp32"]["e"] * abs(e_recip), (q, d, c)
         assert rel_l2(G[o0:o1], G_o.reshape(-1)) <= TOL["fp32"]["v"], (q, d, c)
         assert rel_l2(Ge[o0:o1], G_e.reshape(-1)) <= TOL["fp32"]["v"], (q, d, c)
+
+
+def test_multi_plan_launch_noalloc(H):
+    """The multi-plan launches through hartree_solve_noalloc: a batched FP32
+    plan with no workspace bound, every pass one launch with tiles sized per
+    length, gives V and E_H of hartree_solve under the same configuration
+    (rel-L2 <= 5e-6, E_H rel <= 1e-6: the no-allocation call generates its
+    twiddles on the device)."""
+    probs = [((48, 60, 72), "ortho"), ((60, 72, 90), "triclinic"), ((72, 90, 120), "ortho"),
+             ((90, 120, 48), "ortho"), ((120, 48, 60), "triclinic")]
+    cells = np.stack([CELLS[c] for _, c in probs])
+    dims = np.array([d for d, _ in probs])
+    say("case multi-plan launch, no-allocation solve:", len(probs), "problems")
+    entry = {n: i for i, n in enumerate(SMALL_LENGTHS)}
+    entry_c = {**entry, 48: 41, 128: 42, 160: 43}
+    ref = H.Plan(cells, dims, precision="fp32", max_atoms=1)
+    plan = H.Plan(cells, dims, precision="fp32", max_atoms=1, bind=False)
+    cfg = ref.get_config()
+    for q, (d, _) in enumerate(probs):
+        for x in range(3):
+            cfg[q, x] = (entry[d[x]] if x < 2 else entry_c[d[x]], multi_auto_log2(d[x], x), 0)
+    ref.set_config(cfg)
+    plan.set_config(cfg)
+    rho = to_dev(np.concatenate([inputs.random_grid(d, 70 + q).astype(np.float32).reshape(-1)
+                                 for q, (d, _) in enumerate(probs)]), ref.dtype)
+    V_ref, E_ref = ref.solve(rho)
+    V = torch.full_like(V_ref, float("nan"))
+    E = torch.full((len(probs),), float("nan"), dtype=torch.float64, device="cuda")
+    plan.solve_noalloc(rho, V, E)
+    torch.cuda.synchronize()
+    V_ref, V = V_ref.double().cpu().numpy(), V.double().cpu().numpy()
+    for q in range(len(probs)):
+        o0, o1 = ref.offsets[q], ref.offsets[q + 1]
+        assert rel_l2(V[o0:o1], V_ref[o0:o1]) <= TOL["fp32"]["v"], q
+        assert abs(float(E[q]) - float(E_ref[q])) <= TOL["fp32"]["e"] * abs(float(E_ref[q])), q
