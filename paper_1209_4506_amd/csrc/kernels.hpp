@@ -56,13 +56,13 @@ constexpr int multi_log_p(int x, int k) { return x == 2 ? 2 + k : 3 + k; }
 constexpr int kMultiPlan = -2;
 // A third multi-plan shape sizes the tile per length instead: the most
 // pencils (a power of two, at most 64 along a and b, 32 along c) whose
-// points stay within 4096 (a, b) or 2048 (c), at least 8 (a, b) or 4 (c);
+// points stay within 4096 (a) or 2048 (b, c), at least 8 (a, b) or 4 (c);
 // its launches carry p_log2 = kMultiAutoLog.
 constexpr int kMultiAutoLog = 15;
 constexpr int multi_auto_p(int n, int x)
 {
     int p = x == 2 ? 32 : 64;
-    const int lo = x == 2 ? 4 : 8, target = x == 2 ? 2048 : 4096;
+    const int lo = x == 2 ? 4 : 8, target = x == 0 ? 4096 : 2048;
     while (p > lo && p * n > target) p >>= 1;
     return p;
 }

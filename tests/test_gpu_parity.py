@@ -545,8 +545,8 @@ SMALL_LENGTHS = [32, 48, 60, 64, 72, 90, 96, 120, 128, 150, 160, 180, 192, 200, 
 def multi_auto_log2(n, x):
     """log2 of the size-adapted multi-plan tile width for length n on axis x:
     the most pencils (at most 64 along a and b, 32 along c) whose points stay
-    within 4096 (a, b) or 2048 (c), at least 8 (a, b) or 4 (c)."""
-    p, lo, target = (32, 4, 2048) if x == 2 else (64, 8, 4096)
+    within 4096 (a) or 2048 (b, c), at least 8 (a, b) or 4 (c)."""
+    p, lo, target = (32, 4, 2048) if x == 2 else (64, 8, 4096 if x == 0 else 2048)
     while p > lo and p * n > target:
         p //= 2
     return p.bit_length() - 1
