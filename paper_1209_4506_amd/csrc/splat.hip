@@ -126,15 +126,12 @@ __device__ __forceinline__ int64_t touch_brick(const Touch &t, const ProbDesc &d
     return d.brick_off + (int64_t(bi) * d.nbricks[1] + bj) * d.nbricks[2] + bk;
 }
 
-// index t of brick (bi, bj, bk) in the atom's enumeration
-__device__ __forceinline__ int touch_index(const Touch &t, const ProbDesc &d, int64_t lb)
+// index t of the brick at per-axis position bc in the atom's enumeration
+__device__ __forceinline__ int touch_index(const Touch &t, const ProbDesc &d, const int bc[3])
 {
-    const int bk = int(lb % d.nbricks[2]);
-    const int bj = int((lb / d.nbricks[2]) % d.nbricks[1]);
-    const int bi = int(lb / (int64_t(d.nbricks[2]) * d.nbricks[1]));
-    const int u = (bi - t.st[0] + d.nbricks[0]) % d.nbricks[0];
-    const int v = (bj - t.st[1] + d.nbricks[1]) % d.nbricks[1];
-    const int w = (bk - t.st[2] + d.nbricks[2]) % d.nbricks[2];
+    const int u = (bc[0] - t.st[0] + d.nbricks[0]) % d.nbricks[0];
+    const int v = (bc[1] - t.st[1] + d.nbricks[1]) % d.nbricks[1];
+    const int w = (bc[2] - t.st[2] + d.nbricks[2]) % d.nbricks[2];
     return (u * t.ct[1] + v) * t.ct[2] + w;
 }
 
@@ -233,6 +230,31 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(SplatArgs a)
     __shared__ double qw[NW];
     __shared__ float ww[NW];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t n = a.nbricks_total;
+    constexpr int64_t CH = int64_t(kScanThreads) * kScanPer;
+    // this thread's kScanPer consecutive counts from e0 (zeros past n)
+    auto load_counts = [&](int64_t e0, int *v) {
+        if (e0 + kScanPer <= n) {
+            // the counts array is 256-byte aligned and e0 a multiple of 16
+            const int4 *src = reinterpret_cast<const int4 *>(a.counts + e0);
+#pragma unroll
+            for (int k = 0; k < kScanPer / 4; ++k) {
+                const int4 x = src[k];
+                v[4 * k] = x.x;
+                v[4 * k + 1] = x.y;
+                v[4 * k + 2] = x.z;
+                v[4 * k + 3] = x.w;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kScanPer; ++k) v[k] = e0 + k < n ? a.counts[e0 + k] : 0;
+        }
+    };
+    // the first chunk is loaded before the charge sums, so that its latency
+    // overlaps them; with a single chunk it stays in registers for the
+    // brick order as well
+    int v[kScanPer];
+    load_counts(int64_t(t) * kScanPer, v);
     if (a.nprob <= 4) {
         // few problems: the whole workgroup sums each problem's charges,
         // thread t the atoms t, t + kScanThreads, ..., then fixed butterflies
@@ -281,27 +303,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(SplatArgs a)
             }
         }
     }
-    const int64_t n = a.nbricks_total;
-    constexpr int64_t CH = int64_t(kScanThreads) * kScanPer;
     int64_t carry = 0;  // total of the chunks before this one (the same in every thread)
     for (int64_t c0 = 0; c0 < n; c0 += CH) {
         const int64_t e0 = c0 + int64_t(t) * kScanPer;
-        int v[kScanPer];
-        if (e0 + kScanPer <= n) {
-            // the counts array is 256-byte aligned and e0 a multiple of 16
-            const int4 *src = reinterpret_cast<const int4 *>(a.counts + e0);
-#pragma unroll
-            for (int k = 0; k < kScanPer / 4; ++k) {
-                const int4 x = src[k];
-                v[4 * k] = x.x;
-                v[4 * k + 1] = x.y;
-                v[4 * k + 2] = x.z;
-                v[4 * k + 3] = x.w;
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < kScanPer; ++k) v[k] = e0 + k < n ? a.counts[e0 + k] : 0;
-        }
+        if (c0 > 0) load_counts(e0, v);
         int64_t s = 0;
 #pragma unroll
         for (int k = 0; k < kScanPer; ++k) s += v[k];
@@ -334,13 +339,23 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(SplatArgs a)
     }
     if (a.order) {
         __shared__ int hist[kOrderKeys], next[kOrderKeys];
-        auto key = [&](int64_t b) {
-            const int k = (a.counts[b] + 15) >> 4;
+        auto keyc = [](int c) {
+            const int k = (c + 15) >> 4;
             return k < kOrderKeys - 1 ? k : kOrderKeys - 1;
         };
+        auto key = [&](int64_t b) { return keyc(a.counts[b]); };
+        // one chunk: the thread's counts are still in v (bricks t kScanPer + k)
+        const bool held = n <= CH;
+        const int64_t e0 = int64_t(t) * kScanPer;
         if (t < kOrderKeys) hist[t] = 0;
         __syncthreads();
-        for (int64_t b = t; b < n; b += kScanThreads) atomicAdd(&hist[key(b)], 1);
+        if (held) {
+#pragma unroll
+            for (int k = 0; k < kScanPer; ++k)
+                if (e0 + k < n) atomicAdd(&hist[keyc(v[k])], 1);
+        } else {
+            for (int64_t b = t; b < n; b += kScanThreads) atomicAdd(&hist[key(b)], 1);
+        }
         __syncthreads();
         if (t == 0) {
             int run = 0;
@@ -350,20 +365,27 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(SplatArgs a)
             }
         }
         __syncthreads();
-        for (int64_t b = t; b < n; b += kScanThreads) a.order[atomicAdd(&next[key(b)], 1)] = int32_t(b);
+        if (held) {
+#pragma unroll
+            for (int k = 0; k < kScanPer; ++k)
+                if (e0 + k < n) a.order[atomicAdd(&next[keyc(v[k])], 1)] = int32_t(e0 + k);
+        } else {
+            for (int64_t b = t; b < n; b += kScanThreads) a.order[atomicAdd(&next[key(b)], 1)] = int32_t(b);
+        }
     }
 }
 
 // one wavefront per brick: order the list by atom index, and record each
 // entry's final slot under (atom, brick) for the adjoint's reduction.  A
 // brick's atoms all belong to its problem, whose indices span
-// [atom_off[p], atom_off[p + 1]).  When every problem's span fits rank_words
-// 32-bit words (rank_words > 0), each entry sets its bit in an LDS bitmap of
-// the span and its rank is the number of set bits below it: prefix sums of
-// the words' bit counts plus one popcount, O(cnt + span / 32) per brick.
-// Otherwise (rank_words = 0) the rank is the count of smaller entries
-// (indices are distinct), O(cnt^2), read from LDS for lists of up to kSortLds
-// entries.
+// [atom_off[p], atom_off[p + 1]).  The entries are distinct atom indices,
+// and an entry's rank is the number of smaller ones: for lists of up to 64
+// entries (the usual case) counted over the lanes' registers; for longer
+// lists, when every problem's span fits rank_words 32-bit words
+// (rank_words > 0), from an LDS bitmap of the span (each entry sets its bit;
+// its rank is the number of set bits below it: prefix sums of the words'
+// bit counts plus one popcount, O(cnt + span / 32) per brick); otherwise
+// counted over the list in LDS (up to kSortLds entries) or in memory.
 constexpr int kSortLds = 256;
 constexpr int kRankWords = 1024;  // bitmap ranks for spans of up to 32,768 atoms
 
@@ -385,6 +407,13 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a, int rank_words)
             a.cursor[b] = 0;
         }
     }
+    // the first 128 entries are loaded once, two per lane, and the first
+    // entry's atom is fetched before the ranking so that its latency
+    // overlaps the barriers
+    const int v0 = lane < cnt ? a.list[off + lane] : 0;
+    const int v1 = lane + 64 < cnt ? a.list[off + 64 + lane] : 0;
+    AtomInfo in0;
+    if (lane < cnt) in0 = a.info[v0];
     const int prob = cnt > 0 ? brick_prob(a, b) : 0;
     const int a0 = a.atom_off[prob];
     const int span = a.atom_off[prob + 1] - a0;
@@ -393,20 +422,22 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a, int rank_words)
     // short lists over wide spans (many atoms per problem, few per brick)
     // are ranked by counting
     const int nw = (span + 31) >> 5;
-    const bool bitmap = rank_words > 0 && !(cnt <= kSortLds && cnt <= nw / 32 + 16);
+    const bool small = cnt <= 64;
+    const bool bitmap = !small && rank_words > 0 && !(cnt <= kSortLds && cnt <= nw / 32 + 16);
     uint32_t *bm = rank_lds + w * 2 * rank_words, *pre = bm + rank_words;
-    const bool in_lds = !bitmap && cnt <= kSortLds;
+    const bool in_lds = !small && !bitmap && cnt <= kSortLds;
+    auto entry = [&](int e) { return e < 64 ? v0 : (e < 128 ? v1 : a.list[off + e]); };
     // the barriers are reached by every wavefront whatever its brick's method
     if (bitmap)
         for (int i = lane; i < nw; i += 64) bm[i] = 0u;
     __syncthreads();
     if (bitmap) {
         for (int e = lane; e < cnt; e += 64) {
-            const int r = a.list[off + e] - a0;
+            const int r = entry(e) - a0;
             if (unsigned(r) < unsigned(span)) atomicOr(&bm[r >> 5], 1u << (r & 31));
         }
     } else if (in_lds) {
-        for (int e = lane; e < cnt; e += 64) lst[w][e] = a.list[off + e];
+        for (int e = lane; e < cnt; e += 64) lst[w][e] = entry(e);
     }
     __syncthreads();
     if (bitmap) {
@@ -431,32 +462,34 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a, int rank_words)
     __syncthreads();
     if (cnt == 0) return;
     const ProbDesc &d = a.desc[prob];
-    for (int e = lane; e < cnt; e += 64) {
-        int v, rank = 0;
-        if (bitmap) {
-            v = a.list[off + e];
+    // the brick's position per axis (the bricks of one problem fit 32 bits)
+    const int lb = int(b - d.brick_off);
+    const int bc[3] = {lb / (d.nbricks[2] * d.nbricks[1]), (lb / d.nbricks[2]) % d.nbricks[1], lb % d.nbricks[2]};
+    // the rank of entry v (-1: not an atom of this problem, never written)
+    auto rank_of = [&](int v) {
+        int rank = 0;
+        if (small) {
+            for (int j = 0; j < cnt; ++j) rank += __builtin_amdgcn_readlane(v0, j) < v ? 1 : 0;
+        } else if (bitmap) {
             const int r = v - a0;
-            if (unsigned(r) >= unsigned(span)) continue;  // not an atom of this problem: never written
+            if (unsigned(r) >= unsigned(span)) return -1;
             rank = int(pre[r >> 5]) + __popc(bm[r >> 5] & ((1u << (r & 31)) - 1u));
         } else if (in_lds) {
-            v = lst[w][e];
             for (int j = 0; j < cnt; ++j) rank += (lst[w][j] < v) ? 1 : 0;
         } else {
-            v = a.list[off + e];
             for (int j = 0; j < cnt; ++j) rank += (a.list[off + j] < v) ? 1 : 0;
         }
+        return rank;
+    };
+    auto emit = [&](int v, int rank, const AtomInfo &in) {
         a.list_sorted[off + rank] = v;
-        const AtomInfo in = a.info[v];
         const Touch t = atom_touch(in, d);
-        const int ti = touch_index(t, d, b - d.brick_off);
+        const int ti = touch_index(t, d, bc);
         // with records, the adjoint writes its partials under (atom, touch)
         // directly; otherwise the slot map leads the reduction to them
         if (!a.rec && !a.rec64) a.slot_of[int64_t(v) * a.cap_pa + ti] = int32_t(off + rank);
         if (a.rec64) {
             // the atom relative to this brick, for the FP64 splat kernels
-            const int64_t lb = b - d.brick_off;
-            const int bc[3] = {int(lb / (int64_t(d.nbricks[2]) * d.nbricks[1])),
-                               int((lb / d.nbricks[2]) % d.nbricks[1]), int(lb % d.nbricks[2])};
             SlotAtom64 r;
             for (int x = 0; x < 3; ++x) {
                 r.X[x] = in.X[x];
@@ -473,9 +506,6 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a, int rank_words)
         }
         if (a.rec) {
             // the atom relative to this brick, for the FP32 splat kernels
-            const int64_t lb = b - d.brick_off;
-            const int bc[3] = {int(lb / (int64_t(d.nbricks[2]) * d.nbricks[1])),
-                               int((lb / d.nbricks[2]) % d.nbricks[1]), int(lb % d.nbricks[2])};
             SlotAtom r;
             for (int x = 0; x < 3; ++x) {
                 const int n = d.dims[x];
@@ -492,6 +522,17 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a, int rank_words)
             r.touch = ti;
             a.rec[off + rank] = r;
         }
+    };
+    // the first entry of each lane with the atom fetched above, the rest
+    // (lists longer than 64) with their own loads
+    if (lane < cnt) {
+        const int rank = rank_of(v0);
+        if (rank >= 0) emit(v0, rank, in0);
+    }
+    for (int e = lane + 64; e < cnt; e += 64) {
+        const int v = entry(e);
+        const int rank = rank_of(v);
+        if (rank >= 0) emit(v, rank, a.info[v]);
     }
 }
 

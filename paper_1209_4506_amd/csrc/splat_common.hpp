@@ -6,17 +6,29 @@
 
 namespace hartree {
 
-// the problem of an atom / a brick: the last p whose first atom / brick is
-// at or below it, by bisection over the problems
+// The last p < n whose start(p) is at or below v, for starts that do not
+// decrease with p and start(0) <= v: the number of q in [1, n) with
+// start(q) <= v.  v is the same in every lane and every lane is active:
+// lane l compares start(q) for q = 1 + l, 65 + l, ..., so the lookup costs
+// one load per 64 problems instead of a chain of dependent loads.
+template <class Start>
+__device__ __forceinline__ int wave_find(int n, int64_t v, Start start)
+{
+    const int lane = threadIdx.x & 63;
+    int p = 0;
+    for (int q0 = 1; q0 < n; q0 += 64) {
+        const int q = q0 + lane;
+        const bool le = q < n && start(q) <= v;
+        p += __popcll(__ballot(le));
+    }
+    return __builtin_amdgcn_readfirstlane(p);
+}
+
+// the problem of an atom (atom_off ascending); callers hold the atom index
+// in every lane with the whole wavefront active
 __device__ __forceinline__ int find_prob_atom(const SplatArgs &a, int atom)
 {
-    int lo = 0, hi = a.nprob - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (atom >= a.atom_off[mid]) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
+    return wave_find(a.nprob, atom, [&](int q) { return int64_t(a.atom_off[q]); });
 }
 
 __device__ __forceinline__ int wrapi(int i, int n)
@@ -53,15 +65,11 @@ __device__ __forceinline__ void atom_bricks(const AtomInfo &in, const ProbDesc &
     for (int x = 0; x < 3; ++x) axis_bricks(in.lo[x], in.hi[x], d.dims[x], d.bsz[x], d.nbricks[x], st[x], ct[x]);
 }
 
+// the problem of a brick (brick_off ascending); callers hold the brick
+// index in every lane with the whole wavefront active
 __device__ __forceinline__ int brick_prob(const SplatArgs &a, int64_t b)
 {
-    int lo = 0, hi = a.nprob - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (b >= a.desc[mid].brick_off) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
+    return wave_find(a.nprob, b, [&](int q) { return a.desc[q].brick_off; });
 }
 
 // brick index of this workgroup: from the binning's work order where there
