@@ -251,8 +251,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(SplatArgs a)
         }
     };
     // the first chunk is loaded before the charge sums, so that its latency
-    // overlaps them; with a single chunk it stays in registers for the
-    // brick order as well
+    // overlaps them
     int v[kScanPer];
     load_counts(int64_t(t) * kScanPer, v);
     if (a.nprob <= 4) {
@@ -338,24 +337,18 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(SplatArgs a)
         if (carry > a.capacity) atomicOr(&a.status->bits, 0x4u);
     }
     if (a.order) {
+        // bricks in strided order (thread t takes bricks t, t + kScanThreads,
+        // ...), so that bricks next to each other in space stay next to each
+        // other within a group count (the counts are read again, from cache:
+        // the thread's registers hold a contiguous run instead)
         __shared__ int hist[kOrderKeys], next[kOrderKeys];
-        auto keyc = [](int c) {
-            const int k = (c + 15) >> 4;
+        auto key = [&](int64_t b) {
+            const int k = (a.counts[b] + 15) >> 4;
             return k < kOrderKeys - 1 ? k : kOrderKeys - 1;
         };
-        auto key = [&](int64_t b) { return keyc(a.counts[b]); };
-        // one chunk: the thread's counts are still in v (bricks t kScanPer + k)
-        const bool held = n <= CH;
-        const int64_t e0 = int64_t(t) * kScanPer;
         if (t < kOrderKeys) hist[t] = 0;
         __syncthreads();
-        if (held) {
-#pragma unroll
-            for (int k = 0; k < kScanPer; ++k)
-                if (e0 + k < n) atomicAdd(&hist[keyc(v[k])], 1);
-        } else {
-            for (int64_t b = t; b < n; b += kScanThreads) atomicAdd(&hist[key(b)], 1);
-        }
+        for (int64_t b = t; b < n; b += kScanThreads) atomicAdd(&hist[key(b)], 1);
         __syncthreads();
         if (t == 0) {
             int run = 0;
@@ -365,13 +358,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(SplatArgs a)
             }
         }
         __syncthreads();
-        if (held) {
-#pragma unroll
-            for (int k = 0; k < kScanPer; ++k)
-                if (e0 + k < n) a.order[atomicAdd(&next[keyc(v[k])], 1)] = int32_t(e0 + k);
-        } else {
-            for (int64_t b = t; b < n; b += kScanThreads) a.order[atomicAdd(&next[key(b)], 1)] = int32_t(b);
-        }
+        for (int64_t b = t; b < n; b += kScanThreads) a.order[atomicAdd(&next[key(b)], 1)] = int32_t(b);
     }
 }
 
@@ -414,7 +401,7 @@ __global__ __launch_bounds__(256) void k_brick_sort(SplatArgs a, int rank_words)
     const int v1 = lane + 64 < cnt ? a.list[off + 64 + lane] : 0;
     AtomInfo in0;
     if (lane < cnt) in0 = a.info[v0];
-    const int prob = cnt > 0 ? brick_prob(a, b) : 0;
+    const int prob = cnt > 0 ? brick_prob_wave(a, b) : 0;
     const int a0 = a.atom_off[prob];
     const int span = a.atom_off[prob + 1] - a0;
     // ranks from the bitmap cost about span / 32 word operations per

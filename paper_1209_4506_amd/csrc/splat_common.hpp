@@ -65,9 +65,24 @@ __device__ __forceinline__ void atom_bricks(const AtomInfo &in, const ProbDesc &
     for (int x = 0; x < 3; ++x) axis_bricks(in.lo[x], in.hi[x], d.dims[x], d.bsz[x], d.nbricks[x], st[x], ct[x]);
 }
 
-// the problem of a brick (brick_off ascending); callers hold the brick
-// index in every lane with the whole wavefront active
+// the problem of a brick (brick_off ascending), by bisection over the
+// problems: a chain of scalar loads, which the scalar cache serves to every
+// wavefront of the long splat kernels
 __device__ __forceinline__ int brick_prob(const SplatArgs &a, int64_t b)
+{
+    int lo = 0, hi = a.nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b >= a.desc[mid].brick_off) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// the same by one vector load and a ballot, for the short binning kernels
+// whose wavefronts are load chains; callers hold the brick index in every
+// lane with the whole wavefront active
+__device__ __forceinline__ int brick_prob_wave(const SplatArgs &a, int64_t b)
 {
     return wave_find(a.nprob, b, [&](int q) { return a.desc[q].brick_off; });
 }
