@@ -62,6 +62,9 @@ def parse():
                          "permutation, or the recursive-bisection order of hartree_atom_partition")
     ap.add_argument("--atom-parts", type=int, default=64, help="parts of the bisection order")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
+    ap.add_argument("--serial-chains", action="store_true",
+                    help="replay the step with the solve and the backward in order (two calls) instead of "
+                         "hartree_solve_backward, whose backward chain runs beside the solve's")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (to calibrate HBM byte counters)")
     return ap.parse_args()
@@ -145,13 +148,18 @@ class Step:
         self.grho = p.empty_grid()
         self.gpos = torch.empty((self.pos.shape[0], 3), dtype=torch.float64, device=dev)
 
-    def __call__(self):
+    def __call__(self, fused=False):
         p = self.plan
         # binning shared by splat and adjoint
         token = p.bind_atoms(self.pos, self.Z, self.sig, atom_counts=self.counts)
         p.splat_bound(token, out=self.rho)
-        p.solve(self.rho, v=self.V, e_h=self.E)
-        p.backward(grad_v=self.gv, grad_e=self.ge, rho=self.rho, out=self.grho)
+        if fused:
+            # the backward chain (it needs rho and the loss weights, not V)
+            # beside the solve's, on the plan's second stream and spectrum
+            p.solve_backward(self.rho, grad_v=self.gv, grad_e=self.ge, v=self.V, e_h=self.E, out=self.grho)
+        else:
+            p.solve(self.rho, v=self.V, e_h=self.E)
+            p.backward(grad_v=self.gv, grad_e=self.ge, rho=self.rho, out=self.grho)
         p.splat_adjoint_bound(token, self.grho, out=self.gpos)
 
     def timed(self, steps, warmup, profile=False):
@@ -172,16 +180,18 @@ class Step:
     def outputs(self):
         return [t.clone() for t in (self.rho, self.V, self.E, self.grho, self.gpos)]
 
-    def timed_graph(self, steps, warmup):
-        """The same step captured once as a HIP graph and replayed; the
-        replayed outputs are checked bit for bit against an eager step.
-        Returns (seconds for `steps` replays, bit-identical, per-replay
-        milliseconds from HIP events over at least one second)."""
+    def timed_graph(self, steps, warmup, fused=True):
+        """The step captured once as a HIP graph and replayed (with `fused`,
+        the solve and backward as hartree_solve_backward's two concurrent
+        chains); the replayed outputs are checked bit for bit against an
+        eager step with the calls in order.  Returns (seconds for `steps`
+        replays, bit-identical, per-replay milliseconds from HIP events over
+        at least one second)."""
         torch = self.torch
         self()
         torch.cuda.synchronize()
         ref = self.outputs()
-        self.plan.capture(self)
+        self.plan.capture(lambda: self(fused=fused))
         for _ in range(warmup):
             self.plan.replay()
         torch.cuda.synchronize()
@@ -377,10 +387,14 @@ def run_workload(name, args, torch, H, inputs, steps, warmup, fp64_steps):
         dt = dt_eager
         mode = "eager launches, per-kernel HIP events"
     else:
-        dt, same, stats = step.timed_graph(steps, warmup)
+        dt, same, stats = step.timed_graph(steps, warmup, fused=not args.serial_chains)
         assert same, "graph replay differs from the eager step"
         assert step.plan.device_status() == 0, "device status bits set"
-        mode = "HIP graph replay of the whole step (outputs bit-identical to the eager step)"
+        mode = ("HIP graph replay of the whole step" +
+                (" (solve, then backward)" if args.serial_chains else
+                 " (hartree_solve_backward: the backward chain beside the solve's)") +
+                "; outputs bit-identical to the eager step with the calls in order; per-kernel times from "
+                "that eager step")
     ms = 1000.0 * dt / steps
     s = 4
     n = sum(q.npoints for q in probs)

@@ -152,6 +152,24 @@ hartree_status hartree_energy(hartree_plan plan, const void *rho, double *e_h, v
 hartree_status hartree_backward(hartree_plan plan, const void *grad_v, const double *grad_e, const void *rho,
                                 void *grad_rho, void *stream);
 
+/* hartree_solve and hartree_backward in one call, for a loss whose upstream
+ * gradients grad_v and grad_e are known before the solve (a loss linear in V
+ * and E_H, or a step that reuses the previous gradients): the backward
+ * chain needs only rho, grad_v and grad_e, not V, so it runs as a second
+ * chain of the five passes beside the solve's, on a stream of the plan's
+ * own with its own spectrum buffer (the workspace's last part), forked from
+ * `stream` after the work already on it and joined back into it before the
+ * call returns (under capture: a parallel branch of the graph).  Results are
+ * identical to the two calls in order.  Arguments as in the two calls; v may
+ * in addition not alias grad_v or grad_rho.  The chains run side by side
+ * when their two spectra fit the 256 MiB last-level cache together and every
+ * pass of the plan is one launch group (single plans, and batched plans
+ * whose problems all take multi-plan launches); otherwise, or without the
+ * plan's side streams, in order on `stream` (a spectrum that fits the cache
+ * alone then stays there between passes). */
+hartree_status hartree_solve_backward(hartree_plan plan, const void *rho, void *v, double *e_h, const void *grad_v,
+                                      const double *grad_e, void *grad_rho, void *stream);
+
 /* Gaussian atomic density on the grid (stands in for the density of Eq. (9)):
  *   rho(r) = sum_a Z_a (2 pi s_a^2)^(-3/2) sum_L exp(-|r - R_a - L|^2 / (2 s_a^2))  [- Q / Omega]
  * over lattice vectors L, truncated at cutoff_sigmas * s_a (per axis in a

@@ -155,7 +155,7 @@ struct hartree_plan_s {
     // workspace layout
     size_t o_status = 0, o_desc = 0, o_tw = 0, o_spec = 0, o_parts = 0, o_qsum = 0, o_info = 0, o_counts = 0,
            o_offsets = 0, o_cursor = 0, o_list = 0, o_lists = 0, o_bpart = 0, o_slot = 0, o_rec = 0, o_order = 0, o_zero = 0,
-           ws_size = 0;
+           o_spec2 = 0, ws_size = 0;
     int32_t cap_pa = 0;
     bool wide = false;  // some truncation window can hold two images of one grid point
     unsigned char *ws = nullptr;
@@ -194,6 +194,11 @@ struct hartree_plan_s {
     hipStream_t side[kSide] = {};
     hipEvent_t fork_ev = nullptr;
     hipEvent_t join_ev[kSide] = {};
+    // the backward chain of hartree_solve_backward runs on a stream of its
+    // own (a parallel branch beside the forward chain, on its own spectrum
+    // buffer), forked from and joined back into the caller's stream
+    hipStream_t chain_b = nullptr;
+    hipEvent_t chain_fork = nullptr, chain_join = nullptr;
     bool side_ready = false;
     void drop_side()
     {
@@ -203,8 +208,12 @@ struct hartree_plan_s {
             side[i] = nullptr;
             join_ev[i] = nullptr;
         }
-        if (fork_ev) (void)hipEventDestroy(fork_ev);
-        fork_ev = nullptr;
+        if (chain_b) (void)hipStreamDestroy(chain_b);
+        chain_b = nullptr;
+        for (hipEvent_t *q : {&fork_ev, &chain_fork, &chain_join}) {
+            if (*q) (void)hipEventDestroy(*q);
+            *q = nullptr;
+        }
         side_ready = false;
     }
     ~hartree_plan_s()
@@ -553,6 +562,9 @@ hartree_status create(hartree_plan *out, int nprob, const double *cells, const i
         if (!p->general) p->o_rec = take((p->fp64 ? sizeof(SlotAtom64) : sizeof(SlotAtom)) * size_t(p->capacity));
         if (nprob > 1) p->o_order = take(4 * size_t(p->nbricks));
     }
+    // the second spectrum (hartree_solve_backward's backward chain), last,
+    // so that the solve's part of the layout is the same with or without it
+    p->o_spec2 = take(cx * size_t(p->spec_count));
     p->ws_size = o;
     *out = p;
     return ok();
@@ -827,7 +839,9 @@ hartree_status hartree_bind_workspace(hartree_plan plan, void *workspace, size_t
         for (int i = 0; i < hartree_plan_s::kSide && okay; ++i)
             okay = hipStreamCreateWithFlags(&plan->side[i], hipStreamNonBlocking) == hipSuccess &&
                    hipEventCreateWithFlags(&plan->join_ev[i], hipEventDisableTiming) == hipSuccess;
-        okay = okay && hipEventCreateWithFlags(&plan->fork_ev, hipEventDisableTiming) == hipSuccess;
+        okay = okay && hipStreamCreateWithFlags(&plan->chain_b, hipStreamNonBlocking) == hipSuccess;
+        for (hipEvent_t *q : {&plan->fork_ev, &plan->chain_fork, &plan->chain_join})
+            okay = okay && hipEventCreateWithFlags(q, hipEventDisableTiming) == hipSuccess;
         if (okay) plan->side_ready = true;
         else plan->drop_side();
     }
@@ -842,16 +856,11 @@ hartree_status hartree_bind_workspace(hartree_plan plan, void *workspace, size_t
     return ok();
 }
 
-hartree_status hartree_solve(hartree_plan plan, const void *rho, void *v, double *e_h, void *stream)
+namespace {
+// P1..P5 of the solve on stream s (a.in = rho, a.out = v); the E_H finalize
+// runs beside P4 and P5 on the first side stream
+hartree_status solve_chain(hartree_plan plan, PassArgs a, double *e_h, hipStream_t s)
 {
-    hartree_status st = check_ws(plan);
-    if (st != HARTREE_OK) return st;
-    if (!rho || !v) return fail(HARTREE_ERR_ARG, "rho or v is NULL");
-    if (rho == v) return fail(HARTREE_ERR_ARG, "v may not alias rho");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    PassArgs a = base_args(plan);
-    a.in = rho;
-    a.out = v;
     hipError_t e;
     if ((e = run_group(plan, plan->lr2c, PASS_R2C_FWD, a, s)) != hipSuccess) return hip_fail(e, "P1");
     if ((e = run_group(plan, plan->lb, PASS_B_FWD, a, s)) != hipSuccess) return hip_fail(e, "P2");
@@ -883,6 +892,21 @@ hartree_status hartree_solve(hartree_plan plan, const void *rho, void *v, double
     return ok();
 }
 
+
+}  // namespace
+
+hartree_status hartree_solve(hartree_plan plan, const void *rho, void *v, double *e_h, void *stream)
+{
+    hartree_status st = check_ws(plan);
+    if (st != HARTREE_OK) return st;
+    if (!rho || !v) return fail(HARTREE_ERR_ARG, "rho or v is NULL");
+    if (rho == v) return fail(HARTREE_ERR_ARG, "v may not alias rho");
+    PassArgs a = base_args(plan);
+    a.in = rho;
+    a.out = v;
+    return solve_chain(plan, a, e_h, static_cast<hipStream_t>(stream));
+}
+
 hartree_status hartree_energy(hartree_plan plan, const void *rho, double *e_h, void *stream)
 {
     hartree_status st = check_ws(plan);
@@ -901,23 +925,14 @@ hartree_status hartree_energy(hartree_plan plan, const void *rho, double *e_h, v
     return ok();
 }
 
-hartree_status hartree_backward(hartree_plan plan, const void *grad_v, const double *grad_e, const void *rho,
-                                void *grad_rho, void *stream)
+namespace {
+// P1..P5 of the backward on stream s (a.in = grad_v, a.in2 = rho, a.grad_e,
+// a.out = grad_rho)
+hartree_status backward_chain(hartree_plan plan, PassArgs a, hipStream_t s)
 {
-    hartree_status st = check_ws(plan);
-    if (st != HARTREE_OK) return st;
-    if (!grad_rho) return fail(HARTREE_ERR_ARG, "grad_rho is NULL");
-    if (grad_e && !rho) return fail(HARTREE_ERR_ARG, "rho is needed when grad_e is given");
-    if (grad_rho == grad_v || grad_rho == rho) return fail(HARTREE_ERR_ARG, "grad_rho may not alias an input");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    PassArgs a = base_args(plan);
-    a.in = grad_v;
-    a.in2 = rho;
-    a.grad_e = grad_e;
-    a.out = grad_rho;
     hipError_t e;
-    if (!grad_v && !grad_e) {  // no upstream gradient: the result is zero
-        if ((e = run_zero(grad_rho, size_t(plan->grid_total) * (plan->fp64 ? 8 : 4), s)) != hipSuccess)
+    if (!a.in && !a.grad_e) {  // no upstream gradient: the result is zero
+        if ((e = run_zero(a.out, size_t(plan->grid_total) * (plan->fp64 ? 8 : 4), s)) != hipSuccess)
             return hip_fail(e, "zeroing grad_rho");
         return ok();
     }
@@ -927,6 +942,83 @@ hartree_status hartree_backward(hartree_plan plan, const void *grad_v, const dou
     if ((e = run_group(plan, plan->lb, PASS_B_INV, a, s)) != hipSuccess) return hip_fail(e, "P4");
     if ((e = run_group(plan, plan->lr2c, PASS_C2R, a, s)) != hipSuccess) return hip_fail(e, "P5");
     return ok();
+}
+
+hartree_status check_backward_args(const void *grad_v, const double *grad_e, const void *rho, const void *grad_rho)
+{
+    if (!grad_rho) return fail(HARTREE_ERR_ARG, "grad_rho is NULL");
+    if (grad_e && !rho) return fail(HARTREE_ERR_ARG, "rho is needed when grad_e is given");
+    if (grad_rho == grad_v || grad_rho == rho) return fail(HARTREE_ERR_ARG, "grad_rho may not alias an input");
+    return ok();
+}
+}  // namespace
+
+hartree_status hartree_backward(hartree_plan plan, const void *grad_v, const double *grad_e, const void *rho,
+                                void *grad_rho, void *stream)
+{
+    hartree_status st = check_ws(plan);
+    if (st != HARTREE_OK) return st;
+    if ((st = check_backward_args(grad_v, grad_e, rho, grad_rho)) != HARTREE_OK) return st;
+    PassArgs a = base_args(plan);
+    a.in = grad_v;
+    a.in2 = rho;
+    a.grad_e = grad_e;
+    a.out = grad_rho;
+    return backward_chain(plan, a, static_cast<hipStream_t>(stream));
+}
+
+// the last-level cache (MI355X: 256 MiB of Infinity Cache) that two spectra
+// side by side must fit for hartree_solve_backward to overlap its chains
+constexpr size_t kOverlapCacheBytes = size_t(256) << 20;
+
+hartree_status hartree_solve_backward(hartree_plan plan, const void *rho, void *v, double *e_h, const void *grad_v,
+                                      const double *grad_e, void *grad_rho, void *stream)
+{
+    hartree_status st = check_ws(plan);
+    if (st != HARTREE_OK) return st;
+    if (!rho || !v) return fail(HARTREE_ERR_ARG, "rho or v is NULL");
+    if (rho == v) return fail(HARTREE_ERR_ARG, "v may not alias rho");
+    if ((st = check_backward_args(grad_v, grad_e, rho, grad_rho)) != HARTREE_OK) return st;
+    if (v == grad_v || v == grad_rho)
+        return fail(HARTREE_ERR_ARG, "v may not alias grad_v or grad_rho (the two chains run concurrently)");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    PassArgs a = base_args(plan);
+    a.in = rho;
+    a.out = v;
+    PassArgs b = base_args(plan);
+    b.spec = plan->ws + plan->o_spec2;  // the backward chain's own spectrum
+    b.in = grad_v;
+    b.in2 = rho;
+    b.grad_e = grad_e;
+    b.out = grad_rho;
+    // The chains run side by side when their two spectra fit the last-level
+    // cache together, and every pass is one launch group (single plans;
+    // batched plans whose problems all take multi-plan launches), so that the
+    // backward chain forks no side streams of its own.  Otherwise, or without
+    // the plan's streams, in order on the caller's stream: a spectrum that
+    // fits the cache alone stays there from one pass to the next, which two
+    // chains side by side would give up.
+    const bool single_groups = plan->lr2c.size() == 1 && plan->lb.size() == 1 && plan->la.size() == 1;
+    const size_t spec_bytes = size_t(plan->spec_count) * (plan->fp64 ? 16 : 8);
+    if (!plan->side_ready || !single_groups || 2 * spec_bytes > kOverlapCacheBytes) {
+        // in order, on the one spectrum (the cache still holds it)
+        if ((st = solve_chain(plan, a, e_h, s)) != HARTREE_OK) return st;
+        b.spec = a.spec;
+        return backward_chain(plan, b, s);
+    }
+    // the backward chain forks after the work already on s (rho's producer)
+    // and is joined back before the call returns, also after an error, so
+    // that no capture keeps an open branch
+    hipError_t e = hipEventRecord(plan->chain_fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(plan->chain_b, plan->chain_fork, 0);
+    if (e != hipSuccess) return hip_fail(e, "forking the backward chain");
+    const hartree_status sb = backward_chain(plan, b, plan->chain_b);
+    const hartree_status sf = sb == HARTREE_OK ? solve_chain(plan, a, e_h, s) : sb;
+    e = hipEventRecord(plan->chain_join, plan->chain_b);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, plan->chain_join, 0);
+    if (e != hipSuccess) return hip_fail(e, "joining the backward chain");
+    if (sb != HARTREE_OK) return sb;
+    return sf;
 }
 
 hartree_status hartree_atoms_bind(hartree_plan plan, int32_t natoms, const double *pos, const double *Z,

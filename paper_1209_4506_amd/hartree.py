@@ -11,6 +11,8 @@ Names follow the C ABI:
 * ``Plan.solve``           -- hartree_solve: V = P rho and E_H (Eq. (6), Eq. (7))
 * ``Plan.energy``          -- hartree_energy
 * ``Plan.backward``        -- hartree_backward: P (grad_v + grad_e dV rho)
+* ``Plan.solve_backward``  -- hartree_solve_backward: both, as two concurrent
+                              chains of passes
 * ``Plan.splat``           -- hartree_splat: Gaussian atomic density
 * ``Plan.splat_adjoint``   -- hartree_splat_adjoint: d/dR of sum grad_rho * rho
 * ``atom_partition``       -- hartree_atom_partition: recursive bisection of
@@ -62,6 +64,7 @@ def _load():
         "hartree_solve": [vp, vp, vp, vp, vp],
         "hartree_energy": [vp, vp, vp, vp],
         "hartree_backward": [vp, vp, vp, vp, vp, vp],
+        "hartree_solve_backward": [vp, vp, vp, vp, vp, vp, vp, vp],
         "hartree_splat": [vp, i32, vp, vp, vp, P(i32), vp, i32, vp],
         "hartree_splat_adjoint": [vp, i32, vp, vp, vp, P(i32), vp, vp, vp],
         "hartree_device_status": [vp, P(ctypes.c_uint32), vp],
@@ -96,7 +99,7 @@ LIB = _load()
 # every symbol the header declares
 EXPORTED = ["hartree_plan_create", "hartree_plan_create_batched", "hartree_plan_destroy", "hartree_plan_nprob",
             "hartree_plan_grid_offset", "hartree_workspace_size", "hartree_bind_workspace", "hartree_solve",
-            "hartree_energy", "hartree_backward", "hartree_splat", "hartree_splat_adjoint",
+            "hartree_energy", "hartree_backward", "hartree_solve_backward", "hartree_splat", "hartree_splat_adjoint",
             "hartree_device_status", "hartree_atoms_bind", "hartree_splat_bound", "hartree_splat_adjoint_bound",
             "hartree_profile_begin", "hartree_profile_end", "hartree_graph_begin", "hartree_graph_end",
             "hartree_graph_launch", "hartree_plan_get_config", "hartree_plan_set_config", "hartree_plan_tune",
@@ -287,6 +290,23 @@ class Plan:
         _check(LIB.hartree_backward(self._h, _ptr(grad_v), _ptr(grad_e), _ptr(rho), _ptr(out),
                                     stream or _stream(self.device)))
         return out
+
+    def solve_backward(self, rho, grad_v=None, grad_e=None, v=None, e_h=None, out=None, stream=None):
+        """solve and backward in one call, the backward chain beside the
+        solve's (it needs rho and the upstream gradients, not V); returns
+        (V, E_H, grad_rho), identical to the two calls in order."""
+        self._grid(rho, "rho")
+        self._grid(grad_v, "grad_v")
+        if grad_e is not None:
+            grad_e = grad_e.to(device=self.device, dtype=torch.float64).contiguous().reshape(-1)
+            if grad_e.numel() != self.nprob:
+                raise ValueError("grad_e needs one value per problem")
+        v = self.empty_grid() if v is None else self._grid(v, "v")
+        e_h = torch.empty(self.nprob, dtype=torch.float64, device=self.device) if e_h is None else e_h
+        out = self.empty_grid() if out is None else self._grid(out, "out")
+        _check(LIB.hartree_solve_backward(self._h, _ptr(rho), _ptr(v), _ptr(e_h), _ptr(grad_v), _ptr(grad_e),
+                                          _ptr(out), stream or _stream(self.device)))
+        return v, e_h, out
 
     # ------------------------------------------------------------ atoms
     def _atoms(self, pos, Z, sigma, atom_counts):
