@@ -609,8 +609,10 @@ __device__ __forceinline__ void fft_any(const Src &src, Dst &dst, const L &lds, 
 // whose butterfly counts (36 and 60 per pencil for 360) fill a 64-lane
 // wavefront better than 40, 45 and 72; and plans of 48, 128 and 160 without
 // a radix-16 stage, which the multi-plan kernels of the c passes take (a
-// radix-16 butterfly there sets the whole kernel's registers).  Entries are
-// only ever appended, so that stored tuner choices keep their meaning.
+// radix-16 butterfly there sets the whole kernel's registers); and radix-12
+// first stages for 360, whose 30 butterflies per pencil take one round on 32
+// threads (radix 10's 36 take two).  Entries are only ever appended, so that
+// stored tuner choices keep their meaning.
 // Other lengths run the run-time radix switch.
 #define HARTREE_PLANS(X)                                                                                  \
     X(8, 4, 0, 0) X(16, 3, 0, 0) X(5, 4, 3, 0) X(8, 8, 0, 0) X(9, 8, 0, 0) X(10, 9, 0, 0) X(8, 4, 3, 0)   \
@@ -620,7 +622,7 @@ __device__ __forceinline__ void fft_any(const Src &src, Dst &dst, const L &lds, 
     X(8, 8, 8, 0) X(9, 8, 8, 0) X(8, 5, 5, 3) X(10, 8, 8, 0) X(10, 9, 8, 0) X(16, 16, 3, 0)              \
     X(10, 10, 8, 0) X(8, 7, 5, 3) X(8, 8, 5, 3) X(16, 16, 4, 0) X(16, 16, 8, 0)                          \
     X(10, 6, 6, 0) X(6, 6, 10, 0) X(6, 10, 6, 0) X(10, 6, 3, 0) X(6, 6, 5, 0)                           \
-    X(8, 6, 0, 0) X(8, 4, 4, 0) X(8, 5, 4, 0)
+    X(8, 6, 0, 0) X(8, 4, 4, 0) X(8, 5, 4, 0) X(12, 5, 6, 0) X(12, 6, 5, 0)
 
 // the plan table as compile-time constants (for kernels that pick a plan per
 // workgroup)

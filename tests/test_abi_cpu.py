@@ -180,15 +180,16 @@ def test_pass_config_validation(lib):
 
 def test_compiled_plans_for_360_and_180(lib):
     """The compiled radix plans accepted for a length are exactly the table
-    entries whose radices multiply to it: for 360 the 9 x 8 x 5 entry and the
-    three radix-6 orders (10 x 6 x 6, 6 x 6 x 10, 6 x 10 x 6), for 180 the
-    9 x 5 x 4 entry and 10 x 6 x 3, 6 x 6 x 5.  Entries are only appended to
+    entries whose radices multiply to it: for 360 the 9 x 8 x 5 entry, the
+    three radix-6 orders (10 x 6 x 6, 6 x 6 x 10, 6 x 10 x 6) and the two
+    radix-12 first stages (12 x 5 x 6, 12 x 6 x 5), for 180 the 9 x 5 x 4
+    entry and 10 x 6 x 3, 6 x 6 x 5.  Entries are only appended to
     the table, so these indices are stable (stored tuner choices use them).
     Host-side validation only (64 KiB of LDS assumed without a device)."""
     lib.hartree_plan_destroy.argtypes = [ctypes.c_void_p]
     for fn in ("hartree_plan_get_config", "hartree_plan_set_config"):
         getattr(lib, fn).restype = ctypes.c_int
-    expect = {360: {20, 36, 37, 38}, 180: {11, 39, 40}}
+    expect = {360: {20, 36, 37, 38, 44, 45}, 180: {11, 39, 40}}
     for prec in (0, 1):
         for n, ids in expect.items():
             for x in range(3):
