@@ -230,3 +230,23 @@ def test_solve_backward_zero_gradient_and_errors(H):
     out = plan.empty_grid()
     with pytest.raises(H.HartreeError):
         plan.solve_backward(rho, grad_v=gv, v=out, out=out)
+
+
+@pytest.mark.parametrize("which", ["grad_v only", "grad_e only"])
+def test_solve_backward_partial_gradients(H, which):
+    """One upstream gradient only, on the concurrent path (a small single
+    plan): V, E_H and grad_rho equal the two calls in order bit for bit."""
+    say("case solve_backward", which)
+    p = inputs.cubic32()
+    plan = H.Plan(p.cell, p.dims, precision="fp32", max_atoms=p.natoms)
+    rho = torch.tensor(inputs.random_grid(p.dims, 8), dtype=torch.float32, device="cuda").contiguous()
+    gv = torch.tensor(inputs.random_grid(p.dims, 9), dtype=torch.float32, device="cuda").contiguous()
+    ge = torch.tensor([0.7], dtype=torch.float64, device="cuda")
+    kw = {"grad_v": gv} if which == "grad_v only" else {"grad_e": ge}
+    V, E = plan.solve(rho)
+    G = plan.backward(rho=rho, **kw)
+    V2, E2, G2 = plan.solve_backward(rho, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(V, V2) and torch.equal(E, E2)
+    assert torch.equal(G, G2)
+    assert torch.count_nonzero(G2).item() > 0
