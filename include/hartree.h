@@ -114,11 +114,11 @@ hartree_status hartree_plan_grid_offset(hartree_plan plan, int32_t p, int64_t *o
  * twiddle tables with a synchronous copy; apart from hartree_device_status,
  * hartree_plan_set_config and hartree_plan_tune it is the only call that
  * synchronizes.  Rebinding replaces the previous workspace.  The first binding
- * also creates three internal streams of default priority on the current
+ * also creates four internal streams of default priority on the current
  * device.  Work forked onto them (the launch groups of a batched plan's
  * transform passes, i.e. problems with different pass shapes that no single
- * multi-plan launch takes, and the E_H
- * finalize of hartree_solve, which runs beside the inverse passes) starts
+ * multi-plan launch takes, and the backward chain of
+ * hartree_solve_backward) starts
  * after the work already queued on the caller's stream and is joined back
  * before the call returns, so calls stay ordered on the caller's stream
  * (under capture the forked work becomes parallel branches of the graph).

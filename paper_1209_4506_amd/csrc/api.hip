@@ -832,9 +832,10 @@ hartree_status hartree_bind_workspace(hartree_plan plan, void *workspace, size_t
     e = hipMemcpy(ws + plan->o_zero, zero, sizeof(zero), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "clearing the zero block");
     if (!plan->side_ready) {
-        // side streams for the launch groups of batched passes and the E_H
-        // finalize (on the device current now, the workspace's); without
-        // them that work runs in order on the caller's stream
+        // side streams for the launch groups of batched passes and the
+        // backward chain of hartree_solve_backward (on the device current
+        // now, the workspace's); without them that work runs in order on the
+        // caller's stream
         bool okay = true;
         for (int i = 0; i < hartree_plan_s::kSide && okay; ++i)
             okay = hipStreamCreateWithFlags(&plan->side[i], hipStreamNonBlocking) == hipSuccess &&
@@ -866,29 +867,15 @@ hartree_status solve_chain(hartree_plan plan, PassArgs a, double *e_h, hipStream
     if ((e = run_group(plan, plan->lb, PASS_B_FWD, a, s)) != hipSuccess) return hip_fail(e, "P2");
     if ((e = run_group(plan, plan->la, e_h ? PASS_A_FULL : PASS_A_NOENERGY, a, s)) != hipSuccess)
         return hip_fail(e, "P3");
-    // the E_H sum needs only P3's partials: with a side stream it runs beside
-    // P4 and P5 and is joined back before the call returns
-    const bool side = e_h && plan->side_ready;
-    hipStream_t fs = side ? plan->side[0] : s;
-    if (side) {
-        if ((e = hipEventRecord(plan->fork_ev, s)) != hipSuccess ||
-            (e = hipStreamWaitEvent(fs, plan->fork_ev, 0)) != hipSuccess)
-            return hip_fail(e, "forking the E_H finalize");
-    }
-    if (e_h && (e = timed(plan, HARTREE_K_FINALIZE, fs, [&]() {
-                    return run_finalize(a.desc, a.partials, e_h, plan->nprob, fs);
+    // the E_H sum in order on s: beside P4 and P5 on a side stream, the fork
+    // and the join cost more (a gap before P4 and one after P5) than the
+    // short kernel does in order
+    if (e_h && (e = timed(plan, HARTREE_K_FINALIZE, s, [&]() {
+                    return run_finalize(a.desc, a.partials, e_h, plan->nprob, s);
                 })) != hipSuccess)
         return hip_fail(e, "E_H finalize");
-    hipError_t e4 = run_group(plan, plan->lb, PASS_B_INV, a, s);
-    hipError_t e5 = e4 == hipSuccess ? run_group(plan, plan->lr2c, PASS_C2R, a, s) : hipSuccess;
-    if (side) {
-        // joined also after an error, so that no capture keeps an open branch
-        if ((e = hipEventRecord(plan->join_ev[0], fs)) != hipSuccess ||
-            (e = hipStreamWaitEvent(s, plan->join_ev[0], 0)) != hipSuccess)
-            return hip_fail(e, "joining the E_H finalize");
-    }
-    if (e4 != hipSuccess) return hip_fail(e4, "P4");
-    if (e5 != hipSuccess) return hip_fail(e5, "P5");
+    if ((e = run_group(plan, plan->lb, PASS_B_INV, a, s)) != hipSuccess) return hip_fail(e, "P4");
+    if ((e = run_group(plan, plan->lr2c, PASS_C2R, a, s)) != hipSuccess) return hip_fail(e, "P5");
     return ok();
 }
 
