@@ -155,11 +155,12 @@ hartree_status hartree_backward(hartree_plan plan, const void *grad_v, const dou
 /* hartree_solve and hartree_backward in one call, for a loss whose upstream
  * gradients grad_v and grad_e are known before the solve (a loss linear in V
  * and E_H, or a step that reuses the previous gradients): the backward
- * chain needs only rho, grad_v and grad_e, not V, so it runs as a second
- * chain of the five passes beside the solve's, on a stream of the plan's
- * own with its own spectrum buffer (the workspace's last part), forked from
- * `stream` after the work already on it and joined back into it before the
- * call returns (under capture: a parallel branch of the graph).  Results are
+ * chain needs only rho, grad_v and grad_e, not V, so the two chains of five
+ * passes run side by side: the solve's on a stream of the plan's own,
+ * forked from `stream` after the work already on it and joined back into it
+ * before the call returns (under capture: a parallel branch of the graph),
+ * the backward's on `stream` with its own spectrum buffer (the workspace's
+ * last part).  Results are
  * identical to the two calls in order.  Arguments as in the two calls; v may
  * in addition not alias grad_v or grad_rho.  The chains run side by side
  * when their two spectra fit the 256 MiB last-level cache together and every

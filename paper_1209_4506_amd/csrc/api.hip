@@ -194,9 +194,9 @@ struct hartree_plan_s {
     hipStream_t side[kSide] = {};
     hipEvent_t fork_ev = nullptr;
     hipEvent_t join_ev[kSide] = {};
-    // the backward chain of hartree_solve_backward runs on a stream of its
-    // own (a parallel branch beside the forward chain, on its own spectrum
-    // buffer), forked from and joined back into the caller's stream
+    // hartree_solve_backward runs one of its two chains on this stream (a
+    // parallel branch beside the other, each on its own spectrum buffer),
+    // forked from and joined back into the caller's stream
     hipStream_t chain_b = nullptr;
     hipEvent_t chain_fork = nullptr, chain_join = nullptr;
     bool side_ready = false;
@@ -858,8 +858,8 @@ hartree_status hartree_bind_workspace(hartree_plan plan, void *workspace, size_t
 }
 
 namespace {
-// P1..P5 of the solve on stream s (a.in = rho, a.out = v); the E_H finalize
-// runs beside P4 and P5 on the first side stream
+// P1..P5 of the solve on stream s (a.in = rho, a.out = v), with the E_H
+// finalize after P3
 hartree_status solve_chain(hartree_plan plan, PassArgs a, double *e_h, hipStream_t s)
 {
     hipError_t e;
@@ -993,19 +993,22 @@ hartree_status hartree_solve_backward(hartree_plan plan, const void *rho, void *
         b.spec = a.spec;
         return backward_chain(plan, b, s);
     }
-    // the backward chain forks after the work already on s (rho's producer)
-    // and is joined back before the call returns, also after an error, so
-    // that no capture keeps an open branch
+    // The forward chain (the shorter one: its P1 reads one grid, the
+    // backward's two) forks onto the plan's stream after the work already on
+    // s (rho's producer); the backward chain stays on s, so that the join
+    // before the caller's next work (the adjoint) finds the forward chain
+    // already done.  The join comes also after an error, so that no capture
+    // keeps an open branch.
     hipError_t e = hipEventRecord(plan->chain_fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(plan->chain_b, plan->chain_fork, 0);
-    if (e != hipSuccess) return hip_fail(e, "forking the backward chain");
-    const hartree_status sb = backward_chain(plan, b, plan->chain_b);
-    const hartree_status sf = sb == HARTREE_OK ? solve_chain(plan, a, e_h, s) : sb;
+    if (e != hipSuccess) return hip_fail(e, "forking the forward chain");
+    const hartree_status sf = solve_chain(plan, a, e_h, plan->chain_b);
+    const hartree_status sb = sf == HARTREE_OK ? backward_chain(plan, b, s) : sf;
     e = hipEventRecord(plan->chain_join, plan->chain_b);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, plan->chain_join, 0);
-    if (e != hipSuccess) return hip_fail(e, "joining the backward chain");
-    if (sb != HARTREE_OK) return sb;
-    return sf;
+    if (e != hipSuccess) return hip_fail(e, "joining the forward chain");
+    if (sf != HARTREE_OK) return sf;
+    return sb;
 }
 
 hartree_status hartree_atoms_bind(hartree_plan plan, int32_t natoms, const double *pos, const double *Z,
