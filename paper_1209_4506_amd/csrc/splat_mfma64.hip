@@ -376,7 +376,7 @@ __device__ __forceinline__ void adjoint_reduce64(const SplatArgs &a, const doubl
 // first, the next group's factors are evaluated while they run, then the
 // fold; the previous group's partials are reduced at the top.
 template <bool WIDE>
-__global__ __launch_bounds__(kDThreads) void k_adjoint_mfma64(SplatArgs a)
+__global__ __launch_bounds__(kDThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_adjoint_mfma64(SplatArgs a)
 {
     __shared__ SlotAtom64 recs[kDStage];
     __shared__ AdjBuf64 buf[2];
