@@ -392,7 +392,7 @@ def run_workload(name, args, torch, H, inputs, steps, warmup, fp64_steps):
         assert step.plan.device_status() == 0, "device status bits set"
         mode = ("HIP graph replay of the whole step" +
                 (" (solve, then backward)" if args.serial_chains else
-                 " (hartree_solve_backward: the backward chain beside the solve's)") +
+                 " (hartree_solve_backward: the solve's and the backward's chains side by side when their spectra fit the cache)") +
                 "; outputs bit-identical to the eager step with the calls in order; per-kernel times from "
                 "that eager step")
     ms = 1000.0 * dt / steps

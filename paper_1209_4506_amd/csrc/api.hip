@@ -197,7 +197,7 @@ struct hartree_plan_s {
     // hartree_solve_backward runs one of its two chains on this stream (a
     // parallel branch beside the other, each on its own spectrum buffer),
     // forked from and joined back into the caller's stream
-    hipStream_t chain_b = nullptr;
+    hipStream_t chain_side = nullptr;
     hipEvent_t chain_fork = nullptr, chain_join = nullptr;
     bool side_ready = false;
     void drop_side()
@@ -208,8 +208,8 @@ struct hartree_plan_s {
             side[i] = nullptr;
             join_ev[i] = nullptr;
         }
-        if (chain_b) (void)hipStreamDestroy(chain_b);
-        chain_b = nullptr;
+        if (chain_side) (void)hipStreamDestroy(chain_side);
+        chain_side = nullptr;
         for (hipEvent_t *q : {&fork_ev, &chain_fork, &chain_join}) {
             if (*q) (void)hipEventDestroy(*q);
             *q = nullptr;
@@ -840,7 +840,7 @@ hartree_status hartree_bind_workspace(hartree_plan plan, void *workspace, size_t
         for (int i = 0; i < hartree_plan_s::kSide && okay; ++i)
             okay = hipStreamCreateWithFlags(&plan->side[i], hipStreamNonBlocking) == hipSuccess &&
                    hipEventCreateWithFlags(&plan->join_ev[i], hipEventDisableTiming) == hipSuccess;
-        okay = okay && hipStreamCreateWithFlags(&plan->chain_b, hipStreamNonBlocking) == hipSuccess;
+        okay = okay && hipStreamCreateWithFlags(&plan->chain_side, hipStreamNonBlocking) == hipSuccess;
         for (hipEvent_t *q : {&plan->fork_ev, &plan->chain_fork, &plan->chain_join})
             okay = okay && hipEventCreateWithFlags(q, hipEventDisableTiming) == hipSuccess;
         if (okay) plan->side_ready = true;
@@ -1000,11 +1000,11 @@ hartree_status hartree_solve_backward(hartree_plan plan, const void *rho, void *
     // already done.  The join comes also after an error, so that no capture
     // keeps an open branch.
     hipError_t e = hipEventRecord(plan->chain_fork, s);
-    if (e == hipSuccess) e = hipStreamWaitEvent(plan->chain_b, plan->chain_fork, 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(plan->chain_side, plan->chain_fork, 0);
     if (e != hipSuccess) return hip_fail(e, "forking the forward chain");
-    const hartree_status sf = solve_chain(plan, a, e_h, plan->chain_b);
+    const hartree_status sf = solve_chain(plan, a, e_h, plan->chain_side);
     const hartree_status sb = sf == HARTREE_OK ? backward_chain(plan, b, s) : sf;
-    e = hipEventRecord(plan->chain_join, plan->chain_b);
+    e = hipEventRecord(plan->chain_join, plan->chain_side);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, plan->chain_join, 0);
     if (e != hipSuccess) return hip_fail(e, "joining the forward chain");
     if (sf != HARTREE_OK) return sf;

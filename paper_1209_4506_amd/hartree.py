@@ -292,9 +292,10 @@ class Plan:
         return out
 
     def solve_backward(self, rho, grad_v=None, grad_e=None, v=None, e_h=None, out=None, stream=None):
-        """solve and backward in one call, the backward chain beside the
-        solve's (it needs rho and the upstream gradients, not V); returns
-        (V, E_H, grad_rho), identical to the two calls in order."""
+        """solve and backward in one call (hartree_solve_backward): the
+        backward needs rho and the upstream gradients, not V, so the two
+        chains of passes run side by side when their spectra fit the cache;
+        returns (V, E_H, grad_rho), identical to the two calls in order."""
         self._grid(rho, "rho")
         self._grid(grad_v, "grad_v")
         if grad_e is not None:
